@@ -1,0 +1,146 @@
+"""CPU oracle for affine-gap alignment (local, global, semi-global).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and
+the benchmark's CPU-baseline leg, never by the product path.  It shares no
+code with the HIP library.
+
+Two independent implementations live here:
+
+* ``gotoh.c`` (built into ``liboracle.so`` with gcc): plain int64 O(m*n)
+  dynamic programming, full matrices for traceback, a pthread pool over pairs.
+* ``pyref.py``: a separately written pure-Python version (small inputs only)
+  used to cross-check the C code, including its traceback.
+
+Conventions (the paper leaves them open; see the module docstring of
+``gotoh.c``): a gap of length L costs open + (L-1)*extend; end cell = best
+score, then smallest target end, then smallest query end; traceback priority
+zero > diagonal > D > I, open wins ties; CIGAR ops use the BAM numbering
+(= 7, X 8, I 1, D 2), len << 4 | op.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+LOCAL, GLOBAL, SEMIGLOBAL = 0, 1, 2
+QB, QE, TB, TE = 1, 2, 4, 8
+MODES = {"local": LOCAL, "global": GLOBAL, "semiglobal": SEMIGLOBAL}
+OP_I, OP_D, OP_EQ, OP_X = 1, 2, 7, 8
+OP_CHARS = {OP_I: "I", OP_D: "D", OP_EQ: "=", OP_X: "X"}
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile gotoh.c into liboracle.so with gcc."""
+    src = os.path.join(HERE, "gotoh.c")
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
+                               "-Wall", "-o", tmp, src])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        L.or_align_batch.restype = ctypes.c_int
+        L.or_align_batch.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_int32,
+                                     ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def default_ends(mode: int, ends) -> int:
+    if mode == SEMIGLOBAL:
+        return TB | TE if not ends else int(ends)
+    return 0
+
+
+def align_index(qi, ti, queries, targets, matrix, gap_open, gap_extend, mode="local",
+                ends=None, traceback=False, threads=None) -> dict:
+    """Align pairs (queries[qi[k]], targets[ti[k]]) with the C oracle.
+
+    queries/targets: objects with .codes (uint8) and .offsets (int64, n+1).
+    Returns a dict of numpy arrays: score (int64), q_begin, q_end, t_begin,
+    t_end (int32) and, with traceback, cigars (list of uint32 arrays)."""
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    qi = np.ascontiguousarray(qi, dtype=np.int64)
+    ti = np.ascontiguousarray(ti, dtype=np.int64)
+    n = len(qi)
+    S = np.ascontiguousarray(matrix, dtype=np.int8)
+    A = S.shape[0]
+    if threads is None:
+        threads = len(os.sched_getaffinity(0))
+    score = np.zeros(n, np.int64)
+    coords = np.zeros((n, 4), np.int32)
+    n_ops = np.zeros(n, np.int32)
+    status = np.zeros(n, np.int32)
+    cig = cig_off = cig_cap = None
+    if traceback:
+        ql = (queries.offsets[qi + 1] - queries.offsets[qi])
+        tl = (targets.offsets[ti + 1] - targets.offsets[ti])
+        cig_cap = (ql + tl + 1).astype(np.int64)
+        cig_off = np.zeros(n, np.int64)
+        if n:
+            cig_off[1:] = np.cumsum(cig_cap)[:-1]
+        cig = np.zeros(int(cig_cap.sum()) if n else 1, np.uint32)
+    rc = lib().or_align_batch(n, _ptr(qi), _ptr(ti), _ptr(queries.codes), _ptr(queries.offsets),
+                              _ptr(targets.codes), _ptr(targets.offsets), _ptr(S), A,
+                              int(gap_open), int(gap_extend), m, default_ends(m, ends),
+                              1 if traceback else 0, int(threads), _ptr(score), _ptr(coords),
+                              _ptr(n_ops), _ptr(status), _ptr(cig), _ptr(cig_off), _ptr(cig_cap))
+    if rc != 0:
+        raise RuntimeError(f"oracle failed with code {rc}")
+    out = dict(score=score, q_begin=coords[:, 0].copy(), q_end=coords[:, 1].copy(),
+               t_begin=coords[:, 2].copy(), t_end=coords[:, 3].copy())
+    if traceback:
+        out["cigars"] = [cig[cig_off[k]:cig_off[k] + n_ops[k]].copy() for k in range(n)]
+    return out
+
+
+def align_pairs(queries, targets, matrix, gap_open, gap_extend, mode="local", ends=None,
+                traceback=False, threads=None) -> dict:
+    """Pairwise: queries[k] vs targets[k]."""
+    n = len(queries.offsets) - 1
+    idx = np.arange(n, dtype=np.int64)
+    return align_index(idx, idx, queries, targets, matrix, gap_open, gap_extend, mode, ends,
+                       traceback, threads)
+
+
+def search(queries, targets, matrix, gap_open, gap_extend, mode="local", ends=None,
+           traceback=False, threads=None) -> dict:
+    """Every query vs every target, results query-major (n_q * n_t)."""
+    nq = len(queries.offsets) - 1
+    nt = len(targets.offsets) - 1
+    qi = np.repeat(np.arange(nq, dtype=np.int64), nt)
+    ti = np.tile(np.arange(nt, dtype=np.int64), nq)
+    return align_index(qi, ti, queries, targets, matrix, gap_open, gap_extend, mode, ends,
+                       traceback, threads)
+
+
+def cigar_string(ops) -> str:
+    return "".join(f"{int(x) >> 4}{OP_CHARS[int(x) & 15]}" for x in ops)
+
+
+def top_k(scores: np.ndarray, k: int):
+    """Top-k target indices of one query by (score desc, index asc), score > 0
+    only: a full stable sort of the oracle's per-target scores."""
+    order = np.lexsort((np.arange(len(scores)), -scores.astype(np.int64)))
+    order = order[scores[order] > 0]
+    return order[:k]
