@@ -1,0 +1,184 @@
+/*
+ * dsa.h - C ABI of the MI355X affine-gap alignment library (libdsa.so).
+ *
+ * The library aligns query sequences against a database of target sequences
+ * (every query against every target), or queries against targets pairwise,
+ * with the three algorithms of the DSA paper (Section II.C.2): local
+ * Smith-Waterman, global Needleman-Wunsch and semi-global alignment, all
+ * with affine gaps as in the SIMD libraries the paper builds on
+ * (Section II.B.1).  Each result is the alignment object of Section II.B.1:
+ * optimal score, location (begin/end in both sequences) and, on request, a
+ * CIGAR; per-query top-K selection follows Section II.B.2.
+ *
+ * Definitions (shared by every entry point):
+ *   codes        sequences are arrays of uint8 codes < alphabet_size (<= 32)
+ *   subst        alphabet_size x alphabet_size int8 matrix, row = query code,
+ *                column = target code
+ *   gaps         a run of L gap columns costs gap_open + (L-1) * gap_extend,
+ *                0 <= gap_extend <= gap_open
+ *   local        max(0, best score over all pairs of substrings); 0 = none
+ *   global       both sequences end to end
+ *   semiglobal   the query end to end, the target's prefix/suffix free by
+ *                default; free_ends (DSA_QB|DSA_QE|DSA_TB|DSA_TE) selects which
+ *                ends are free (0 = DSA_TB|DSA_TE); the result is the best of
+ *                H[m][n], the last row if TE, the last column if QE
+ *   end cell     among the cells reaching the result: smallest target end,
+ *                then smallest query end
+ *   traceback    priority zero (local) > diagonal > gap in query (D) > gap in
+ *                target (I); inside a gap run, opening wins ties
+ *   coordinates  0-based inclusive; -1 everywhere for "no alignment"; begins
+ *                are computed only with DSA_TRACEBACK (else -1)
+ *   CIGAR        uint32 runs, (length << 4) | op, op in BAM numbering:
+ *                1 = I (query residue vs gap), 2 = D (gap vs target residue),
+ *                7 = '=' (identical residues), 8 = 'X' (different residues)
+ *
+ * Memory: pointers marked [dev] are device pointers on the current HIP
+ * device, [host] are host pointers.  The caller owns every input and output
+ * buffer.  The library owns only a dsa_db (device memory allocated by
+ * dsa_db_create, released by dsa_db_destroy) and a small pinned staging
+ * buffer per device for work tables.
+ *
+ * Streams: dsa_align_batch enqueues its copies and kernels on args->stream
+ * (a hipStream_t, NULL = default stream) and returns without waiting;
+ * outputs are valid once that stream has been synchronised.  It performs no
+ * device allocation: all scratch memory is the caller's workspace.
+ *
+ * Errors: every entry point returns a dsa_status; no C++ exception crosses
+ * the ABI.  dsa_last_error() returns a thread-local message for the last
+ * failure on the calling thread.
+ */
+#ifndef DSA_H
+#define DSA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DSA_ABI_VERSION 1
+
+typedef enum {
+    DSA_OK = 0,
+    DSA_E_INVAL = 1,      /* bad pointer, mode, flag, code, penalty or size */
+    DSA_E_RANGE = 2,      /* scores could reach 2^31 even in int32 */
+    DSA_E_WORKSPACE = 3,  /* workspace smaller than dsa_workspace_size */
+    DSA_E_CAPACITY = 4,   /* CIGAR buffer too small (results still valid) */
+    DSA_E_DEVICE = 5,     /* a HIP call failed; see dsa_last_error */
+    DSA_E_NOTSUP = 6      /* combination not supported by this build */
+} dsa_status;
+
+enum { DSA_LOCAL = 0, DSA_GLOBAL = 1, DSA_SEMIGLOBAL = 2 };
+enum { DSA_QB = 1, DSA_QE = 2, DSA_TB = 4, DSA_TE = 8 };
+
+/* flags */
+#define DSA_TRACEBACK   1u  /* compute begins and CIGAR */
+#define DSA_PLAIN       2u  /* one launch per query (per pair batch), no persistent kernel */
+#define DSA_FORCE_INT32 4u  /* skip the packed int16 pass */
+
+/* per-result status bits */
+#define DSA_ST_INT32     1u  /* the result came from the int32 rerun */
+#define DSA_ST_TRUNCATED 2u  /* the CIGAR did not fit in its slot */
+
+typedef struct dsa_db dsa_db;
+
+/*
+ * dsa_db_create - pack a target database into device memory (Section II.B.1
+ * "Map": the reference set is converted once into a layout suited to the
+ * parallel workers and kept memory-resident, Section II.A).
+ *   codes      [host] concatenated target codes, offsets[n_targets] bytes
+ *   offsets    [host] n_targets + 1 int64 offsets, non-decreasing, offsets[0] = 0
+ *   n_targets  >= 1
+ *   alphabet_size  2..32; every code must be < alphabet_size
+ *   stream     hipStream_t for the uploads (the call synchronises it)
+ *   out        receives the handle
+ * Targets are sorted by length into groups of 128 (two per lane of a
+ * 64-wide wave), their codes interleaved so a wave reads 8 bytes per lane
+ * per 4 columns.  Errors: DSA_E_INVAL, DSA_E_DEVICE.
+ */
+int dsa_db_create(const uint8_t *codes, const int64_t *offsets, int64_t n_targets,
+                  int32_t alphabet_size, void *stream, dsa_db **out);
+
+/* dsa_db_destroy - free a database (NULL is accepted).  Not stream-ordered:
+ * the caller must make sure no enqueued work still reads it. */
+int dsa_db_destroy(dsa_db *db);
+
+/* Number of targets, total residues and device bytes held by a database. */
+int dsa_db_info(const dsa_db *db, int64_t *n_targets, int64_t *n_residues, int64_t *device_bytes);
+
+typedef struct {
+    /* queries */
+    const uint8_t *q_codes;    /* [dev]  concatenated query codes */
+    const int64_t *q_offsets;  /* [host] n_q + 1 offsets into q_codes */
+    int64_t n_q;               /* >= 1 */
+    /* targets: exactly one of db / (t_codes, t_offsets) */
+    const dsa_db *db;          /* database search: every query vs every target */
+    const uint8_t *t_codes;    /* [dev]  pairwise: query k vs target k */
+    const int64_t *t_offsets;  /* [host] n_q + 1 offsets into t_codes */
+    /* scoring */
+    const int8_t *subst;       /* [host] alphabet_size^2, row = query code */
+    int32_t alphabet_size;     /* 2..32; must equal the database's */
+    int32_t gap_open;          /* >= gap_extend >= 0 */
+    int32_t gap_extend;
+    int32_t mode;              /* DSA_LOCAL | DSA_GLOBAL | DSA_SEMIGLOBAL */
+    int32_t free_ends;         /* semiglobal only; 0 = DSA_TB|DSA_TE */
+    uint32_t flags;            /* DSA_TRACEBACK | DSA_PLAIN | DSA_FORCE_INT32 */
+    int32_t top_k;             /* database search only: 0 = all targets, else K <= 64 best per query */
+    /* scratch */
+    void *workspace;           /* [dev] >= dsa_workspace_size bytes, 256-byte aligned */
+    size_t workspace_bytes;
+    void *stream;              /* hipStream_t */
+} dsa_args;
+
+/*
+ * Results.  Layout: database search without top_k: n_q * n_targets entries,
+ * query-major, targets in original order.  With top_k: n_q * top_k entries,
+ * best first (score descending, original target index ascending; only
+ * positive local scores; unused slots have t_index = -1, score = 0).
+ * Pairwise: n_q entries.  All pointers [dev]; NULL = not wanted (score is
+ * required).
+ */
+typedef struct {
+    int32_t *score;
+    int32_t *q_begin, *q_end, *t_begin, *t_end;
+    int64_t *t_index;          /* top_k only: original target index */
+    uint8_t *status;           /* DSA_ST_* bits */
+    /* DSA_TRACEBACK: result r's runs are cigar_ops[cigar_off[r] .. + cigar_len[r]) */
+    int64_t *cigar_off;
+    int32_t *cigar_len;
+    uint32_t *cigar_ops;
+    int64_t cigar_capacity;    /* uint32 entries in cigar_ops */
+} dsa_out;
+
+/*
+ * dsa_workspace_size - bytes of device workspace dsa_align_batch needs for
+ * these arguments (the workspace pointer itself is not read).
+ * Errors: DSA_E_INVAL, DSA_E_NOTSUP, DSA_E_RANGE.
+ */
+int dsa_workspace_size(const dsa_args *args, size_t *bytes);
+
+/*
+ * dsa_cigar_capacity - uint32 entries dsa_out.cigar_ops needs so that no
+ * CIGAR can be truncated (sum over results of query + target length).
+ */
+int dsa_cigar_capacity(const dsa_args *args, int64_t *entries);
+
+/*
+ * dsa_align_batch - align (Sections II.B.1 and II.C.2; top-K per
+ * Section II.B.2).  Asynchronous on args->stream.  Scores are exact: a
+ * packed int16 pass is followed by an exact int32 rerun of every result
+ * that could have saturated.
+ * Errors: DSA_E_INVAL, DSA_E_RANGE, DSA_E_WORKSPACE, DSA_E_NOTSUP,
+ * DSA_E_DEVICE.
+ */
+int dsa_align_batch(const dsa_args *args, const dsa_out *out);
+
+const char *dsa_strerror(int status);
+const char *dsa_last_error(void);
+int32_t dsa_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSA_H */

@@ -1,0 +1,185 @@
+"""MI355X affine-gap sequence alignment (local, global, semi-global).
+
+The alignment itself runs in libdsa.so (hand-written HIP kernels for
+gfx950); this module marshals arguments and uses torch only to own device
+memory and streams.  There is no CPU fallback: without the built library
+or a GPU every call raises.
+
+    db = Database(codes, offsets, alphabet_size=24)
+    res = align(queries, db=db, matrix=blosum62, gap_open=11, gap_extend=1)
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import binding as B
+from .binding import (  # noqa: F401
+    DSA_FORCE_INT32, DSA_GLOBAL, DSA_LOCAL, DSA_PLAIN, DSA_QB, DSA_QE, DSA_SEMIGLOBAL,
+    DSA_ST_INT32, DSA_ST_TRUNCATED, DSA_TB, DSA_TE, DSA_TRACEBACK, DsaError,
+)
+
+MODES = {"local": DSA_LOCAL, "global": DSA_GLOBAL, "semiglobal": DSA_SEMIGLOBAL}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU: the alignment kernels need an MI355X (gfx950)")
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class Database:
+    """A target database packed into device memory (dsa_db_create)."""
+
+    def __init__(self, codes, offsets, alphabet_size: int, device=None):
+        torch = _torch()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        with torch.cuda.device(self.device):
+            self._codes = _host(codes, np.uint8)
+            self._offsets = _host(offsets, np.int64)
+            self.n_targets = len(self._offsets) - 1
+            self.alphabet_size = int(alphabet_size)
+            stream = torch.cuda.current_stream().cuda_stream
+            self.handle = B.dsa_db_create(self._codes.ctypes.data_as(ctypes.c_void_p),
+                                          self._offsets.ctypes.data_as(ctypes.c_void_p),
+                                          self.n_targets, self.alphabet_size, ctypes.c_void_p(stream))
+        self.lengths = np.diff(self._offsets)
+
+    @classmethod
+    def from_seqset(cls, s, alphabet_size: int, device=None):
+        return cls(s.codes, s.offsets, alphabet_size, device)
+
+    def info(self):
+        return B.dsa_db_info(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            B.dsa_db_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Workspace:
+    def __init__(self):
+        self.buf = {}
+
+    def get(self, nbytes: int, device):
+        torch = _torch()
+        key = str(device)
+        cur = self.buf.get(key)
+        if cur is None or cur.numel() < nbytes + 256:
+            self.buf.pop(key, None)
+            cur = torch.empty(max(nbytes + 256, 1 << 20), dtype=torch.uint8, device=device)
+            self.buf[key] = cur
+        base = cur.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        return aligned, cur.numel() - (aligned - base)
+
+
+_WS = _Workspace()
+
+
+def device_queries(queries, device):
+    """Stage a SeqSet's codes on the device: returns (codes tensor, host offsets)."""
+    torch = _torch()
+    codes = torch.from_numpy(_host(queries.codes, np.uint8)).to(device) if len(queries.codes) else \
+        torch.zeros(1, dtype=torch.uint8, device=device)
+    return codes, _host(queries.offsets, np.int64)
+
+
+def make_args(q_codes, q_offsets, matrix, gap_open, gap_extend, mode="local", db=None,
+              t_codes=None, t_offsets=None, free_ends=None, traceback=False, top_k=0,
+              plain=False, force_int32=False, stream=None):
+    torch = _torch()
+    a = B.dsa_args()
+    q_offsets = _host(q_offsets, np.int64)
+    S = _host(matrix, np.int8)
+    a.q_codes = q_codes.data_ptr()
+    a.q_offsets = q_offsets.ctypes.data
+    a.n_q = len(q_offsets) - 1
+    a.db = db.handle if db is not None else None
+    keep = [q_offsets, S]
+    if t_codes is not None:
+        t_offsets = _host(t_offsets, np.int64)
+        keep.append(t_offsets)
+        a.t_codes = t_codes.data_ptr()
+        a.t_offsets = t_offsets.ctypes.data
+    a.subst = S.ctypes.data
+    a.alphabet_size = S.shape[0]
+    a.gap_open = int(gap_open)
+    a.gap_extend = int(gap_extend)
+    a.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    a.free_ends = int(free_ends or 0)
+    a.flags = (DSA_TRACEBACK if traceback else 0) | (DSA_PLAIN if plain else 0) | \
+        (DSA_FORCE_INT32 if force_int32 else 0)
+    a.top_k = int(top_k)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    a.stream = stream.cuda_stream
+    a._keep = keep
+    return a
+
+
+def align_args(a, device, n_results, want_coords=True, want_begin=True):
+    """Allocate outputs + workspace and call dsa_align_batch; returns tensors."""
+    torch = _torch()
+    need = B.dsa_workspace_size(a)
+    ws, ws_bytes = _WS.get(need, device)
+    a.workspace = ws
+    a.workspace_bytes = ws_bytes
+    out = B.dsa_out()
+    i32 = dict(dtype=torch.int32, device=device)
+    res = {"score": torch.empty(max(n_results, 1), **i32)}
+    if want_coords:
+        res["q_end"] = torch.empty(max(n_results, 1), **i32)
+        res["t_end"] = torch.empty(max(n_results, 1), **i32)
+    if want_begin:
+        res["q_begin"] = torch.empty(max(n_results, 1), **i32)
+        res["t_begin"] = torch.empty(max(n_results, 1), **i32)
+    res["status"] = torch.empty(max(n_results, 1), dtype=torch.uint8, device=device)
+    for k in ("score", "q_begin", "q_end", "t_begin", "t_end", "status"):
+        if k in res:
+            setattr(out, k, res[k].data_ptr())
+    st = B.dsa_align_batch(a, out)
+    res = {k: v[:n_results] for k, v in res.items()}
+    res["capacity_ok"] = st == B.DSA_OK
+    return res
+
+
+def align(queries, db: Database = None, targets=None, matrix=None, gap_open=11, gap_extend=1,
+          mode="local", free_ends=None, traceback=False, top_k=0, plain=False,
+          force_int32=False, stream=None) -> dict:
+    """Align a SeqSet of queries against a Database (every query vs every
+    target, query-major results) or against a SeqSet of targets pairwise.
+    Returns a dict of device tensors (score, q_begin, q_end, t_begin, t_end,
+    status)."""
+    torch = _torch()
+    device = db.device if db is not None else torch.device("cuda", torch.cuda.current_device())
+    qc, qo = device_queries(queries, device)
+    tc = to = None
+    if targets is not None:
+        tc, to = device_queries(targets, device)
+    a = make_args(qc, qo, matrix, gap_open, gap_extend, mode, db, tc, to, free_ends, traceback,
+                  top_k, plain, force_int32, stream)
+    nq = len(qo) - 1
+    n = nq * (db.n_targets if db is not None else 1) if not top_k else nq * top_k
+    if targets is not None:
+        n = nq
+    res = align_args(a, device, n)
+    res["_keep"] = (qc, tc)
+    return res

@@ -1,0 +1,150 @@
+"""ctypes binding of libdsa.so: the C ABI of include/dsa.h, same names.
+
+Argument marshalling only; every step of the alignment runs in the HIP
+library.  Loading fails loudly when libdsa.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libdsa.so")
+
+DSA_OK, DSA_E_INVAL, DSA_E_RANGE, DSA_E_WORKSPACE, DSA_E_CAPACITY, DSA_E_DEVICE, DSA_E_NOTSUP = range(7)
+DSA_LOCAL, DSA_GLOBAL, DSA_SEMIGLOBAL = 0, 1, 2
+DSA_QB, DSA_QE, DSA_TB, DSA_TE = 1, 2, 4, 8
+DSA_TRACEBACK, DSA_PLAIN, DSA_FORCE_INT32 = 1, 2, 4
+DSA_ST_INT32, DSA_ST_TRUNCATED = 1, 2
+
+EXPORTS = ["dsa_db_create", "dsa_db_destroy", "dsa_db_info", "dsa_workspace_size",
+           "dsa_cigar_capacity", "dsa_align_batch", "dsa_strerror", "dsa_last_error",
+           "dsa_abi_version"]
+
+
+class DsaError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        super().__init__(f"{where}: status {status}: {detail}")
+
+
+class dsa_args(ctypes.Structure):
+    _fields_ = [
+        ("q_codes", ctypes.c_void_p),
+        ("q_offsets", ctypes.c_void_p),
+        ("n_q", ctypes.c_int64),
+        ("db", ctypes.c_void_p),
+        ("t_codes", ctypes.c_void_p),
+        ("t_offsets", ctypes.c_void_p),
+        ("subst", ctypes.c_void_p),
+        ("alphabet_size", ctypes.c_int32),
+        ("gap_open", ctypes.c_int32),
+        ("gap_extend", ctypes.c_int32),
+        ("mode", ctypes.c_int32),
+        ("free_ends", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("top_k", ctypes.c_int32),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class dsa_out(ctypes.Structure):
+    _fields_ = [
+        ("score", ctypes.c_void_p),
+        ("q_begin", ctypes.c_void_p),
+        ("q_end", ctypes.c_void_p),
+        ("t_begin", ctypes.c_void_p),
+        ("t_end", ctypes.c_void_p),
+        ("t_index", ctypes.c_void_p),
+        ("status", ctypes.c_void_p),
+        ("cigar_off", ctypes.c_void_p),
+        ("cigar_len", ctypes.c_void_p),
+        ("cigar_ops", ctypes.c_void_p),
+        ("cigar_capacity", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdsa.so (built by __graft_entry__.build()); raise if missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        L.dsa_db_create.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_void_p)]
+        L.dsa_db_destroy.argtypes = [P]
+        L.dsa_db_info.argtypes = [P, P, P, P]
+        L.dsa_workspace_size.argtypes = [ctypes.POINTER(dsa_args), ctypes.POINTER(ctypes.c_size_t)]
+        L.dsa_cigar_capacity.argtypes = [ctypes.POINTER(dsa_args), ctypes.POINTER(ctypes.c_int64)]
+        L.dsa_align_batch.argtypes = [ctypes.POINTER(dsa_args), ctypes.POINTER(dsa_out)]
+        L.dsa_strerror.argtypes = [ctypes.c_int]
+        L.dsa_strerror.restype = ctypes.c_char_p
+        L.dsa_last_error.argtypes = []
+        L.dsa_last_error.restype = ctypes.c_char_p
+        L.dsa_abi_version.restype = ctypes.c_int32
+        for name in EXPORTS:
+            if name not in ("dsa_strerror", "dsa_last_error", "dsa_abi_version"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def check(status: int, where: str):
+    if status != DSA_OK:
+        detail = lib().dsa_last_error().decode(errors="replace")
+        raise DsaError(status, where, detail)
+
+
+def dsa_db_create(codes_ptr, offsets_ptr, n_targets, alphabet_size, stream):
+    handle = ctypes.c_void_p()
+    check(lib().dsa_db_create(codes_ptr, offsets_ptr, n_targets, alphabet_size, stream,
+                              ctypes.byref(handle)), "dsa_db_create")
+    return handle.value
+
+
+def dsa_db_destroy(handle):
+    check(lib().dsa_db_destroy(handle), "dsa_db_destroy")
+
+
+def dsa_db_info(handle):
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    check(lib().dsa_db_info(handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "dsa_db_info")
+    return a.value, b.value, c.value
+
+
+def dsa_workspace_size(args: dsa_args) -> int:
+    n = ctypes.c_size_t()
+    check(lib().dsa_workspace_size(ctypes.byref(args), ctypes.byref(n)), "dsa_workspace_size")
+    return n.value
+
+
+def dsa_cigar_capacity(args: dsa_args) -> int:
+    n = ctypes.c_int64()
+    check(lib().dsa_cigar_capacity(ctypes.byref(args), ctypes.byref(n)), "dsa_cigar_capacity")
+    return n.value
+
+
+def dsa_align_batch(args: dsa_args, out: dsa_out) -> int:
+    """Returns the status (DSA_OK or DSA_E_CAPACITY); raises on other errors."""
+    st = lib().dsa_align_batch(ctypes.byref(args), ctypes.byref(out))
+    if st not in (DSA_OK, DSA_E_CAPACITY):
+        check(st, "dsa_align_batch")
+    return st
+
+
+def dsa_strerror(status: int) -> str:
+    return lib().dsa_strerror(status).decode()
+
+
+def dsa_last_error() -> str:
+    return lib().dsa_last_error().decode(errors="replace")
+
+
+def dsa_abi_version() -> int:
+    return int(lib().dsa_abi_version())

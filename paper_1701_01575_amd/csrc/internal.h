@@ -1,0 +1,103 @@
+// Internal types shared by the host runtime and the kernels of libdsa.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dsa {
+
+constexpr int kWave = 64;
+constexpr int kGroup = 128;          // targets per group: 64 lanes x 2 int16 halves
+constexpr int kPadLen = 4;           // group column count is a multiple of this
+constexpr int kMaxAlphabet = 32;
+constexpr int kMaxLen16 = 65532;     // int16 kernels index rows/columns with uint16
+constexpr int kT32 = 16;             // strip height of the int32 kernels
+
+enum Mode { LOCAL = 0, GLOBAL = 1, SEMIGLOBAL = 2 };
+enum Ends { QB = 1, QE = 2, TB = 4, TE = 8 };
+
+// One group of 128 length-sorted targets.
+struct GroupInfo {
+    int64_t off;      // first uint2 of the group's column blocks in `packed`
+    int64_t bnd;      // first uint4 of the group's boundary rows inside one query slot
+    int32_t ncols;    // columns, multiple of 4 (max target length, rounded up)
+    int32_t slot0;    // first slot: slots slot0 .. slot0+127
+};
+
+struct QueryInfo {
+    int64_t off;      // into the query code buffer
+    int32_t len;      // m >= 1
+    int32_t strips;   // ceil(m / T)
+};
+
+// A work unit: one query against ng consecutive groups (one wave per group
+// for the int16 kernel, two for the int32 kernel).
+struct SearchUnit {
+    int32_t q;
+    int32_t g0;
+    int32_t ng;
+    int32_t qslot;    // which query slot of the boundary buffer this unit uses
+};
+
+struct SearchArgs {
+    const uint2 *packed;
+    const GroupInfo *grp;
+    const int32_t *slot_target;   // original index or -1
+    const int32_t *slot_len;
+    const uint8_t *pair_dec;      // AP*AP*2: compact (lo, hi) codes of a pair code
+    const uint8_t *inv_map;       // AP: compact code -> matrix code, 0xff = pad
+    const uint8_t *q_codes;
+    const QueryInfo *qinfo;
+    const int8_t *subst;          // A*A
+    const SearchUnit *units;
+    int32_t n_units;
+    int32_t A, AP, o, e, ends;
+    uint4 *bnd;
+    int64_t bnd_slot_stride;      // uint4 per query slot
+    int32_t *out_score, *out_qend, *out_tend;
+    uint8_t *out_status;
+    int64_t n_t;                  // output row stride (targets per query)
+    int32_t *unit_flags;          // per unit: 1 = rewrite saturated results, 2 = recompute all
+    const int32_t *qflag;         // per query: int16 bound fails (global / semi-global)
+    int32_t *counter;             // persistent-grid work counter
+};
+
+// Launchers (kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_search16(const SearchArgs &a, int T, int mode, int waves_per_block,
+                           int n_blocks, bool persistent, size_t lds_bytes, hipStream_t s);
+hipError_t launch_search32(const SearchArgs &a, int mode, int waves_per_block,
+                           int n_blocks, bool persistent, size_t lds_bytes, hipStream_t s,
+                           int rerun_only);
+
+// Per-query int16 safety for global / semi-global: qflag[q] = 1 when the sum
+// of positive row maxima, or the most negative reachable value, leaves the
+// int16 range.
+struct BoundArgs {
+    const uint8_t *q_codes;
+    const QueryInfo *qinfo;
+    int32_t n_q;
+    const int8_t *subst;
+    int32_t A;
+    const uint8_t *inv_map;
+    int32_t AP;
+    int32_t o, e, min_s;
+    int64_t n_max;
+    int32_t *qflag;
+};
+hipError_t launch_bound16(const BoundArgs &a, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+size_t search16_lds_bytes(int T, int AP);
+size_t search32_lds_bytes(int AP);
+
+// Results for queries of length 0 (closed forms of the boundary rows).
+struct EmptyArgs {
+    int32_t mode, ends, o, e;
+    int64_t n_t;
+    const int64_t *t_len;       // per target (original order)
+    const int32_t *q_rows;      // output rows (query indices) to fill
+    int32_t n_rows;
+    int32_t *out_score, *out_qend, *out_tend, *out_qbeg, *out_tbeg;
+    uint8_t *out_status;
+};
+hipError_t launch_empty_queries(const EmptyArgs &a, hipStream_t s);
+
+}  // namespace dsa

@@ -1,0 +1,603 @@
+// Host runtime of libdsa: argument checks, database packing, work planning
+// and the C ABI declared in include/dsa.h.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "dsa.h"
+#include "internal.h"
+
+using namespace dsa;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                       \
+    do {                                                                                \
+        hipError_t _e = (x);                                                            \
+        if (_e != hipSuccess)                                                           \
+            return fail(DSA_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Pinned staging buffer for the small per-call tables, one per device.
+struct Staging {
+    std::mutex mu;
+    void *buf = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+};
+Staging g_staging[64];
+
+int device_cus(int dev) {
+    static int cache[64] = {0};
+    if (dev < 0 || dev >= 64) return 256;
+    if (!cache[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            v = 256;
+        cache[dev] = v;
+    }
+    return cache[dev];
+}
+
+}  // namespace
+
+struct dsa_db {
+    int device = 0;
+    int32_t A = 0, n_used = 0, AP = 0;
+    uint8_t code_map[kMaxAlphabet];
+    uint8_t inv_map[kMaxAlphabet + 1];
+    int64_t n_targets = 0, n_residues = 0, n_groups = 0, max_len = 0;
+    int64_t bnd_slot_uint4 = 0;  // boundary rows of one query slot (int32 sized)
+    std::vector<int64_t> len;
+    std::vector<GroupInfo> grp;
+    std::vector<int64_t> grp_cells;  // sum of ncols over the group's targets' max (cost)
+    // device
+    uint2 *d_packed = nullptr;
+    GroupInfo *d_grp = nullptr;
+    int32_t *d_slot_target = nullptr, *d_slot_len = nullptr;
+    uint8_t *d_pair_dec = nullptr, *d_inv_map = nullptr;
+    int64_t *d_len = nullptr;
+    int64_t device_bytes = 0;
+};
+
+static void db_free(dsa_db *db) {
+    if (!db) return;
+    hipFree(db->d_packed);
+    hipFree(db->d_grp);
+    hipFree(db->d_slot_target);
+    hipFree(db->d_slot_len);
+    hipFree(db->d_pair_dec);
+    hipFree(db->d_inv_map);
+    hipFree(db->d_len);
+    delete db;
+}
+
+template <typename Tp>
+static int upload(Tp **dst, const Tp *src, size_t count, int64_t *acc) {
+    size_t bytes = std::max<size_t>(count * sizeof(Tp), 16);
+    HIPCHK(hipMalloc((void **)dst, bytes));
+    if (count) HIPCHK(hipMemcpy(*dst, src, count * sizeof(Tp), hipMemcpyHostToDevice));
+    *acc += (int64_t)bytes;
+    return DSA_OK;
+}
+
+extern "C" int dsa_db_create(const uint8_t *codes, const int64_t *offsets, int64_t n_targets,
+                             int32_t alphabet_size, void *stream, dsa_db **out) {
+    if (!out) return fail(DSA_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!offsets || n_targets < 1) return fail(DSA_E_INVAL, "need offsets and n_targets >= 1");
+    if (alphabet_size < 2 || alphabet_size > kMaxAlphabet)
+        return fail(DSA_E_INVAL, "alphabet_size must be in [2, 32]");
+    if (offsets[0] != 0) return fail(DSA_E_INVAL, "offsets[0] must be 0");
+    for (int64_t k = 0; k < n_targets; k++)
+        if (offsets[k + 1] < offsets[k]) return fail(DSA_E_INVAL, "offsets must be non-decreasing");
+    const int64_t total = offsets[n_targets];
+    if (total > 0 && !codes) return fail(DSA_E_INVAL, "codes is NULL");
+    bool used[kMaxAlphabet] = {false};
+    for (int64_t k = 0; k < total; k++) {
+        if (codes[k] >= alphabet_size) return fail(DSA_E_INVAL, "target code >= alphabet_size");
+        used[codes[k]] = true;
+    }
+
+    dsa_db *db = new dsa_db();
+    hipGetDevice(&db->device);
+    db->A = alphabet_size;
+    db->n_targets = n_targets;
+    db->n_residues = total;
+    db->len.resize(n_targets);
+    for (int64_t k = 0; k < n_targets; k++) {
+        db->len[k] = offsets[k + 1] - offsets[k];
+        db->max_len = std::max(db->max_len, db->len[k]);
+    }
+    if (db->max_len > kMaxLen16) {
+        delete db;
+        return fail(DSA_E_NOTSUP, "targets longer than 65532 residues are not supported");
+    }
+    memset(db->code_map, 0xff, sizeof(db->code_map));
+    memset(db->inv_map, 0xff, sizeof(db->inv_map));
+    for (int c = 0; c < alphabet_size; c++)
+        if (used[c]) {
+            db->code_map[c] = (uint8_t)db->n_used;
+            db->inv_map[db->n_used] = (uint8_t)c;
+            db->n_used++;
+        }
+    db->AP = db->n_used + 1;  // compact codes plus the pad code
+    const int AP = db->AP;
+    const uint16_t pad = (uint16_t)db->n_used;
+
+    // length-sorted slots, 128 per group
+    std::vector<int64_t> order(n_targets);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t x, int64_t y) { return db->len[x] < db->len[y]; });
+    db->n_groups = (n_targets + kGroup - 1) / kGroup;
+    std::vector<int32_t> slot_target(db->n_groups * kGroup, -1), slot_len(db->n_groups * kGroup, 0);
+    for (int64_t s = 0; s < n_targets; s++) {
+        slot_target[s] = (int32_t)order[s];
+        slot_len[s] = (int32_t)db->len[order[s]];
+    }
+    db->grp.resize(db->n_groups);
+    int64_t off = 0, bnd = 0;
+    for (int64_t g = 0; g < db->n_groups; g++) {
+        int64_t mx = 0;
+        for (int k = 0; k < kGroup; k++) mx = std::max<int64_t>(mx, slot_len[g * kGroup + k]);
+        GroupInfo &G = db->grp[g];
+        G.ncols = (int32_t)align_up((size_t)mx, kPadLen);
+        G.slot0 = (int32_t)(g * kGroup);
+        G.off = off;
+        G.bnd = bnd;
+        off += (int64_t)(G.ncols / 4) * kWave;
+        bnd += (int64_t)G.ncols * kWave;  // 2 waves x ncols/4 blocks x 64 lanes x 2 uint4
+    }
+    db->bnd_slot_uint4 = bnd;
+    std::vector<uint16_t> packed((size_t)off * 4);
+    for (int64_t g = 0; g < db->n_groups; g++) {
+        const GroupInfo &G = db->grp[g];
+        for (int lane = 0; lane < kWave; lane++) {
+            const int32_t tl = slot_target[G.slot0 + lane], th = slot_target[G.slot0 + 64 + lane];
+            const uint8_t *cl = tl >= 0 ? codes + offsets[tl] : nullptr;
+            const uint8_t *ch = th >= 0 ? codes + offsets[th] : nullptr;
+            const int64_t nl = tl >= 0 ? db->len[tl] : 0, nh = th >= 0 ? db->len[th] : 0;
+            for (int j = 0; j < G.ncols; j++) {
+                const uint16_t lo = j < nl ? db->code_map[cl[j]] : pad;
+                const uint16_t hi = j < nh ? db->code_map[ch[j]] : pad;
+                packed[((size_t)G.off + (size_t)(j / 4) * kWave + lane) * 4 + (j & 3)] =
+                    (uint16_t)(lo * AP + hi);
+            }
+        }
+    }
+    std::vector<uint8_t> pair_dec((size_t)AP * AP * 2);
+    for (int p = 0; p < AP * AP; p++) {
+        pair_dec[2 * p] = (uint8_t)(p / AP);
+        pair_dec[2 * p + 1] = (uint8_t)(p % AP);
+    }
+
+    int rc;
+    if ((rc = upload(reinterpret_cast<uint16_t **>(&db->d_packed), packed.data(), packed.size(),
+                     &db->device_bytes)) ||
+        (rc = upload(&db->d_grp, db->grp.data(), db->grp.size(), &db->device_bytes)) ||
+        (rc = upload(&db->d_slot_target, slot_target.data(), slot_target.size(), &db->device_bytes)) ||
+        (rc = upload(&db->d_slot_len, slot_len.data(), slot_len.size(), &db->device_bytes)) ||
+        (rc = upload(&db->d_pair_dec, pair_dec.data(), pair_dec.size(), &db->device_bytes)) ||
+        (rc = upload(&db->d_inv_map, db->inv_map, (size_t)AP, &db->device_bytes)) ||
+        (rc = upload(&db->d_len, db->len.data(), db->len.size(), &db->device_bytes))) {
+        db_free(db);
+        return rc;
+    }
+    if (stream) {
+        hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess) {
+            db_free(db);
+            return fail(DSA_E_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+        }
+    }
+    *out = db;
+    return DSA_OK;
+}
+
+extern "C" int dsa_db_destroy(dsa_db *db) {
+    db_free(db);
+    return DSA_OK;
+}
+
+extern "C" int dsa_db_info(const dsa_db *db, int64_t *n_targets, int64_t *n_residues,
+                           int64_t *device_bytes) {
+    if (!db) return fail(DSA_E_INVAL, "db is NULL");
+    if (n_targets) *n_targets = db->n_targets;
+    if (n_residues) *n_residues = db->n_residues;
+    if (device_bytes) *device_bytes = db->device_bytes;
+    return DSA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Planning
+
+namespace {
+
+struct Plan {
+    // DB search
+    int T = 32;
+    int wpb16 = 8;                  // waves per block, int16 kernel (one group each)
+    bool persistent = true;
+    bool force32 = false;
+    int mode = 0, ends = 0;
+    std::vector<SearchUnit> units;  // all units; per-query ranges for the plain form
+    std::vector<int64_t> unit_first, unit_count;  // per query (plain form)
+    std::vector<QueryInfo> qinfo;
+    std::vector<int32_t> empty_rows;
+    int n_slots = 1;
+    size_t lds16 = 0, lds32 = 0;
+    // workspace layout (byte offsets)
+    size_t off_units = 0, off_qinfo = 0, off_subst = 0, off_rows = 0, table_bytes = 0;
+    size_t off_flags = 0, off_qflag = 0, off_counter = 0, off_bnd = 0, total = 0;
+    int32_t min_s = 0, max_abs_s = 0;
+};
+
+int check_common(const dsa_args *a) {
+    if (!a) return fail(DSA_E_INVAL, "args is NULL");
+    if (a->n_q < 1) return fail(DSA_E_INVAL, "n_q must be >= 1");
+    if (!a->q_offsets) return fail(DSA_E_INVAL, "q_offsets is NULL");
+    if (!a->subst) return fail(DSA_E_INVAL, "subst is NULL");
+    if (a->alphabet_size < 2 || a->alphabet_size > kMaxAlphabet)
+        return fail(DSA_E_INVAL, "alphabet_size must be in [2, 32]");
+    if (a->mode < DSA_LOCAL || a->mode > DSA_SEMIGLOBAL) return fail(DSA_E_INVAL, "unknown mode");
+    if (a->gap_extend < 0 || a->gap_open < 0 || a->gap_extend > a->gap_open)
+        return fail(DSA_E_INVAL, "need 0 <= gap_extend <= gap_open");
+    if (a->gap_open > 10000) return fail(DSA_E_RANGE, "gap_open too large");
+    if (a->free_ends & ~15) return fail(DSA_E_INVAL, "unknown free_ends bits");
+    if (a->free_ends && a->mode != DSA_SEMIGLOBAL)
+        return fail(DSA_E_INVAL, "free_ends is only valid in semiglobal mode");
+    if (a->flags & ~(DSA_TRACEBACK | DSA_PLAIN | DSA_FORCE_INT32))
+        return fail(DSA_E_INVAL, "unknown flags");
+    if ((a->db != nullptr) == (a->t_codes != nullptr || a->t_offsets != nullptr))
+        return fail(DSA_E_INVAL, "set exactly one of db and (t_codes, t_offsets)");
+    if (a->q_offsets[0] != 0) return fail(DSA_E_INVAL, "q_offsets[0] must be 0");
+    for (int64_t k = 0; k < a->n_q; k++)
+        if (a->q_offsets[k + 1] < a->q_offsets[k])
+            return fail(DSA_E_INVAL, "q_offsets must be non-decreasing");
+    if (a->q_offsets[a->n_q] > 0 && !a->q_codes) return fail(DSA_E_INVAL, "q_codes is NULL");
+    return DSA_OK;
+}
+
+int make_search_plan(const dsa_args *a, Plan &P) {
+    const dsa_db *db = a->db;
+    if (db->A != a->alphabet_size) return fail(DSA_E_INVAL, "alphabet_size differs from the database's");
+    const int ends = a->mode == DSA_SEMIGLOBAL ? (a->free_ends ? a->free_ends : (DSA_TB | DSA_TE)) : 0;
+    if (ends & DSA_QE) return fail(DSA_E_NOTSUP, "free query end (QE) is not supported in database search");
+    if (a->flags & DSA_TRACEBACK) return fail(DSA_E_NOTSUP, "traceback is not supported in database search yet");
+    if (a->top_k != 0) return fail(DSA_E_NOTSUP, "top_k is not supported yet");
+    P.mode = a->mode;
+    P.ends = ends;
+    P.persistent = !(a->flags & DSA_PLAIN);
+    P.force32 = (a->flags & DSA_FORCE_INT32) != 0;
+    const int A = a->alphabet_size;
+    int mn = 0, mx = 0;
+    for (int k = 0; k < A * A; k++) {
+        mn = std::min<int>(mn, a->subst[k]);
+        mx = std::max<int>(mx, std::abs((int)a->subst[k]));
+    }
+    P.min_s = -mn;
+    P.max_abs_s = mx;
+    // pick the strip height from the LDS the pair profile needs
+    P.T = 32;
+    if (search16_lds_bytes(32, db->AP) > 80 * 1024) P.T = 16;
+    P.lds16 = search16_lds_bytes(P.T, db->AP);
+    P.lds32 = search32_lds_bytes(db->AP);
+    if (P.lds16 > 160 * 1024) return fail(DSA_E_NOTSUP, "alphabet too large for the LDS profile");
+
+    const int64_t nq = a->n_q;
+    P.qinfo.resize(nq);
+    P.unit_first.assign(nq, 0);
+    P.unit_count.assign(nq, 0);
+    for (int64_t q = 0; q < nq; q++) {
+        const int64_t m = a->q_offsets[q + 1] - a->q_offsets[q];
+        if (m > kMaxLen16) return fail(DSA_E_NOTSUP, "queries longer than 65532 residues are not supported");
+        // int32 range: max|S| * min(m, n) + 3o + (m + n)e < 2^30
+        const int64_t bound = (int64_t)mx * std::min<int64_t>(m, db->max_len) + 3LL * a->gap_open +
+                              (m + db->max_len + 64) * (int64_t)a->gap_extend;
+        if (bound >= (1LL << 30)) return fail(DSA_E_RANGE, "scores could leave the int32 range");
+        P.qinfo[q].off = a->q_offsets[q];
+        P.qinfo[q].len = (int32_t)m;
+        P.qinfo[q].strips = (int32_t)((m + P.T - 1) / P.T);
+        if (m == 0) P.empty_rows.push_back((int32_t)q);
+    }
+    // int32 kernel uses T = 32 strips: keep one strip count per query for both
+    // by planning int16 with its own T and int32 with 32 (QueryInfo.strips is
+    // rewritten per pass on the device copy; see dsa_align_batch).
+    const int wpb = P.wpb16;
+    for (int64_t q = 0; q < nq; q++) {
+        if (P.qinfo[q].len == 0) continue;
+        P.unit_first[q] = (int64_t)P.units.size();
+        for (int64_t g0 = 0; g0 < db->n_groups; g0 += wpb) {
+            SearchUnit U;
+            U.q = (int32_t)q;
+            U.g0 = (int32_t)g0;
+            U.ng = (int32_t)std::min<int64_t>(wpb, db->n_groups - g0);
+            U.qslot = P.persistent ? (int32_t)q : 0;
+            P.units.push_back(U);
+        }
+        P.unit_count[q] = (int64_t)P.units.size() - P.unit_first[q];
+    }
+    if (P.persistent) {
+        // longest units first: strips x widest group of the unit
+        std::vector<int64_t> cost(P.units.size());
+        for (size_t k = 0; k < P.units.size(); k++) {
+            const SearchUnit &U = P.units[k];
+            cost[k] = (int64_t)P.qinfo[U.q].len * db->grp[U.g0 + U.ng - 1].ncols;
+        }
+        std::vector<size_t> idx(P.units.size());
+        std::iota(idx.begin(), idx.end(), 0);
+        std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+        std::vector<SearchUnit> sorted(P.units.size());
+        for (size_t k = 0; k < idx.size(); k++) sorted[k] = P.units[idx[k]];
+        P.units.swap(sorted);
+        P.n_slots = (int)std::max<int64_t>(1, nq);
+    } else {
+        P.n_slots = 1;
+    }
+
+    // workspace layout
+    size_t o = 0;
+    P.off_units = o; o = align_up(o + std::max<size_t>(P.units.size(), 1) * sizeof(SearchUnit), 256);
+    P.off_qinfo = o; o = align_up(o + 2 * nq * sizeof(QueryInfo), 256);  // int16 and int32 strips
+    P.off_subst = o; o = align_up(o + (size_t)A * A, 256);
+    P.off_rows = o; o = align_up(o + std::max<size_t>(P.empty_rows.size(), 1) * sizeof(int32_t), 256);
+    P.table_bytes = o;
+    P.off_flags = o; o = align_up(o + std::max<size_t>(P.units.size(), 1) * sizeof(int32_t), 256);
+    P.off_qflag = o; o = align_up(o + nq * sizeof(int32_t), 256);
+    P.off_counter = o; o = align_up(o + 2 * sizeof(int32_t), 256);
+    P.off_bnd = o; o = align_up(o + (size_t)P.n_slots * db->bnd_slot_uint4 * 16, 256);
+    P.total = o;
+    return DSA_OK;
+}
+
+int make_plan(const dsa_args *a, Plan &P) {
+    int rc = check_common(a);
+    if (rc) return rc;
+    if (!a->db) return fail(DSA_E_NOTSUP, "pairwise alignment is not supported yet");
+    return make_search_plan(a, P);
+}
+
+}  // namespace
+
+extern "C" int dsa_workspace_size(const dsa_args *args, size_t *bytes) {
+    if (!bytes) return fail(DSA_E_INVAL, "bytes is NULL");
+    Plan P;
+    int rc = make_plan(args, P);
+    if (rc) return rc;
+    *bytes = P.total;
+    return DSA_OK;
+}
+
+extern "C" int dsa_cigar_capacity(const dsa_args *args, int64_t *entries) {
+    if (!entries) return fail(DSA_E_INVAL, "entries is NULL");
+    int rc = check_common(args);
+    if (rc) return rc;
+    int64_t total = 0;
+    if (args->db) {
+        const int64_t nt = args->db->n_targets;
+        const int64_t k = args->top_k ? args->top_k : nt;
+        for (int64_t q = 0; q < args->n_q; q++) {
+            const int64_t m = args->q_offsets[q + 1] - args->q_offsets[q];
+            total += k * (m + args->db->max_len);
+        }
+    } else {
+        for (int64_t q = 0; q < args->n_q; q++)
+            total += (args->q_offsets[q + 1] - args->q_offsets[q]) +
+                     (args->t_offsets[q + 1] - args->t_offsets[q]);
+    }
+    *entries = total;
+    return DSA_OK;
+}
+
+static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
+    const dsa_db *db = a->db;
+    hipStream_t st = (hipStream_t)a->stream;
+    uint8_t *ws = (uint8_t *)a->workspace;
+    const int64_t nq = a->n_q;
+    const int A = a->alphabet_size;
+
+    // tables -> pinned staging -> workspace
+    std::vector<QueryInfo> q32 = P.qinfo;
+    for (auto &q : q32) q.strips = (q.len + kT32 - 1) / kT32;
+    int dev = 0;
+    hipGetDevice(&dev);
+    Staging &S = g_staging[dev & 63];
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        if (S.pending) {
+            HIPCHK(hipEventSynchronize(S.ev));
+            S.pending = false;
+        }
+        if (S.cap < P.table_bytes) {
+            if (S.buf) HIPCHK(hipHostFree(S.buf));
+            S.buf = nullptr;
+            S.cap = 0;
+            HIPCHK(hipHostMalloc(&S.buf, P.table_bytes, hipHostMallocDefault));
+            S.cap = P.table_bytes;
+        }
+        if (!S.ev) HIPCHK(hipEventCreateWithFlags(&S.ev, hipEventDisableTiming));
+        uint8_t *h = (uint8_t *)S.buf;
+        memset(h, 0, P.table_bytes);
+        if (!P.units.empty()) memcpy(h + P.off_units, P.units.data(), P.units.size() * sizeof(SearchUnit));
+        memcpy(h + P.off_qinfo, P.qinfo.data(), nq * sizeof(QueryInfo));
+        memcpy(h + P.off_qinfo + nq * sizeof(QueryInfo), q32.data(), nq * sizeof(QueryInfo));
+        memcpy(h + P.off_subst, a->subst, (size_t)A * A);
+        if (!P.empty_rows.empty())
+            memcpy(h + P.off_rows, P.empty_rows.data(), P.empty_rows.size() * sizeof(int32_t));
+        HIPCHK(hipMemcpyAsync(ws, h, P.table_bytes, hipMemcpyHostToDevice, st));
+        HIPCHK(hipEventRecord(S.ev, st));
+        S.pending = true;
+    }
+
+    SearchArgs K;
+    memset(&K, 0, sizeof(K));
+    K.packed = db->d_packed;
+    K.grp = db->d_grp;
+    K.slot_target = db->d_slot_target;
+    K.slot_len = db->d_slot_len;
+    K.pair_dec = db->d_pair_dec;
+    K.inv_map = db->d_inv_map;
+    K.q_codes = a->q_codes;
+    K.qinfo = (const QueryInfo *)(ws + P.off_qinfo);
+    K.subst = (const int8_t *)(ws + P.off_subst);
+    K.A = A;
+    K.AP = db->AP;
+    K.o = a->gap_open;
+    K.e = a->gap_extend;
+    K.ends = P.ends;
+    K.bnd = (uint4 *)(ws + P.off_bnd);
+    K.bnd_slot_stride = db->bnd_slot_uint4;
+    K.out_score = out->score;
+    K.out_qend = out->q_end;
+    K.out_tend = out->t_end;
+    K.out_status = out->status;
+    K.n_t = db->n_targets;
+    K.unit_flags = (int32_t *)(ws + P.off_flags);
+    K.qflag = (const int32_t *)(ws + P.off_qflag);
+    int32_t *counter = (int32_t *)(ws + P.off_counter);
+
+    const int64_t nunits = (int64_t)P.units.size();
+    HIPCHK(launch_fill_i32(K.unit_flags, 0, std::max<int64_t>(nunits, 1), st));
+    HIPCHK(launch_fill_i32((int32_t *)(ws + P.off_qflag), 0, nq, st));
+    if (P.mode != DSA_LOCAL && !P.force32) {
+        BoundArgs b;
+        b.q_codes = a->q_codes;
+        b.qinfo = K.qinfo;
+        b.n_q = (int32_t)nq;
+        b.subst = K.subst;
+        b.A = A;
+        b.inv_map = db->d_inv_map;
+        b.AP = db->AP;
+        b.o = a->gap_open;
+        b.e = a->gap_extend;
+        b.min_s = P.min_s;
+        b.n_max = db->max_len;
+        b.qflag = (int32_t *)(ws + P.off_qflag);
+        HIPCHK(launch_bound16(b, st));
+    }
+    if (out->q_begin) HIPCHK(launch_fill_i32(out->q_begin, -1, nq * db->n_targets, st));
+    if (out->t_begin) HIPCHK(launch_fill_i32(out->t_begin, -1, nq * db->n_targets, st));
+
+    const int cus = device_cus(dev);
+    const int per_cu16 = std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(P.lds16, 1))));
+    const int wpb32 = 2 * P.wpb16;
+    const SearchUnit *d_units = (const SearchUnit *)(ws + P.off_units);
+    const QueryInfo *qi16 = K.qinfo;
+    const QueryInfo *qi32 = (const QueryInfo *)(ws + P.off_qinfo + nq * sizeof(QueryInfo));
+
+    auto pass = [&](const SearchUnit *units, int64_t n, int rerun) -> int {
+        if (n <= 0) return DSA_OK;
+        SearchArgs k = K;
+        k.units = units;
+        k.n_units = (int32_t)n;
+        k.unit_flags = K.unit_flags + (units - d_units);
+        if (!P.force32 && rerun == 0) {
+            k.qinfo = qi16;
+            int nb = (int)n;
+            if (P.persistent) {
+                k.counter = counter;
+                HIPCHK(launch_fill_i32(counter, 0, 1, st));
+                nb = (int)std::min<int64_t>(n, (int64_t)cus * per_cu16);
+            }
+            HIPCHK(launch_search16(k, P.T, P.mode, P.wpb16, nb, P.persistent, P.lds16, st));
+        } else {
+            k.qinfo = qi32;
+            int nb = (int)n;
+            if (P.persistent) {
+                k.counter = counter + 1;
+                HIPCHK(launch_fill_i32(counter + 1, 0, 1, st));
+                nb = (int)std::min<int64_t>(n, (int64_t)cus * 2);
+            }
+            HIPCHK(launch_search32(k, P.mode, wpb32, nb, P.persistent, P.lds32, st, rerun));
+        }
+        return DSA_OK;
+    };
+
+    int rc;
+    if (P.persistent) {
+        if (!P.force32) {
+            if ((rc = pass(d_units, nunits, 0))) return rc;
+            if ((rc = pass(d_units, nunits, 1))) return rc;
+        } else if ((rc = pass(d_units, nunits, 0))) {
+            return rc;
+        }
+    } else {
+        for (int64_t q = 0; q < nq; q++) {
+            if (P.unit_count[q] == 0) continue;
+            const SearchUnit *u = d_units + P.unit_first[q];
+            if (!P.force32) {
+                if ((rc = pass(u, P.unit_count[q], 0))) return rc;
+                if ((rc = pass(u, P.unit_count[q], 1))) return rc;
+            } else if ((rc = pass(u, P.unit_count[q], 0))) {
+                return rc;
+            }
+        }
+    }
+    if (!P.empty_rows.empty()) {
+        EmptyArgs E;
+        E.mode = P.mode;
+        E.ends = P.ends;
+        E.o = a->gap_open;
+        E.e = a->gap_extend;
+        E.n_t = db->n_targets;
+        E.t_len = db->d_len;
+        E.q_rows = (const int32_t *)(ws + P.off_rows);
+        E.n_rows = (int32_t)P.empty_rows.size();
+        E.out_score = out->score;
+        E.out_qend = out->q_end;
+        E.out_tend = out->t_end;
+        E.out_qbeg = out->q_begin;
+        E.out_tbeg = out->t_begin;
+        E.out_status = out->status;
+        HIPCHK(launch_empty_queries(E, st));
+    }
+    return DSA_OK;
+}
+
+extern "C" int dsa_align_batch(const dsa_args *args, const dsa_out *out) {
+    if (!out || !out->score) return fail(DSA_E_INVAL, "out->score is required");
+    Plan P;
+    int rc = make_plan(args, P);
+    if (rc) return rc;
+    if (!args->workspace && P.total) return fail(DSA_E_INVAL, "workspace is NULL");
+    if (args->workspace_bytes < P.total)
+        return fail(DSA_E_WORKSPACE, "workspace too small: need " + std::to_string(P.total) + " bytes");
+    if (((uintptr_t)args->workspace) & 255) return fail(DSA_E_INVAL, "workspace must be 256-byte aligned");
+    int dev = 0;
+    hipGetDevice(&dev);
+    if (args->db && args->db->device != dev)
+        return fail(DSA_E_INVAL, "database lives on another device");
+    return run_search(args, out, P);
+}
+
+extern "C" const char *dsa_strerror(int status) {
+    switch (status) {
+        case DSA_OK: return "ok";
+        case DSA_E_INVAL: return "invalid argument";
+        case DSA_E_RANGE: return "scores out of range";
+        case DSA_E_WORKSPACE: return "workspace too small";
+        case DSA_E_CAPACITY: return "CIGAR capacity too small";
+        case DSA_E_DEVICE: return "device error";
+        case DSA_E_NOTSUP: return "not supported";
+        default: return "unknown status";
+    }
+}
+
+extern "C" const char *dsa_last_error(void) { return g_err.c_str(); }
+
+extern "C" int32_t dsa_abi_version(void) { return DSA_ABI_VERSION; }

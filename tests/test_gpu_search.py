@@ -1,0 +1,125 @@
+"""GPU parity of database search (every query vs every target) against the
+CPU oracle: score, query end and target end must be bit-identical.
+
+Inputs span several strips and a ragged last strip (query lengths around
+multiples of 16 and 32), empty targets and queries, several groups with a
+ragged last group, every mode, the plain and persistent forms and the int32
+kernel; a scaled matrix forces int16 saturation and the int32 rerun.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import compare_search, gpu_search, log
+from workloads import gen
+from workloads.gen import SeqSet
+
+pytestmark = pytest.mark.gpu
+
+QLENS = [0, 1, 2, 15, 16, 17, 31, 32, 33, 63, 64, 65, 100, 257]
+
+
+def _targets(seed, n, max_len, alphabet=20, extra=()):
+    rng = np.random.default_rng([170101575, 50, seed])
+    lens = list(rng.integers(0, max_len + 1, size=n)) + list(extra)
+    lens[0] = 0
+    return SeqSet.from_list([gen.background_residues(rng, int(L)) % alphabet for L in lens])
+
+
+def _queries(seed, lens):
+    rng = np.random.default_rng([170101575, 51, seed])
+    return SeqSet.from_list([gen.background_residues(rng, int(L)) for L in lens])
+
+
+CASES = [
+    ("local", None), ("global", None), ("semiglobal", None),
+    ("semiglobal", 1 | 4), ("semiglobal", 4), ("semiglobal", 8), ("semiglobal", 1 | 8),
+]
+
+
+@pytest.mark.parametrize("mode,ends", CASES)
+@pytest.mark.parametrize("plain", [False, True], ids=["persistent", "plain"])
+def test_search_modes(mode, ends, plain, blosum):
+    T = _targets(1, 300, 180, extra=[1, 2, 3, 4, 5, 399, 400])
+    Q = _queries(2, QLENS)
+    log(f"search mode={mode} ends={ends} plain={plain} nq={len(Q)} nt={len(T)}")
+    got, _ = gpu_search(Q, T, blosum, 11, 1, mode, ends, plain=plain)
+    exp = oracle.search(Q, T, blosum, 11, 1, mode=mode, ends=ends)
+    compare_search(got, exp, len(Q), len(T), label=f"{mode}/{ends}/{plain}")
+
+
+@pytest.mark.parametrize("mode,ends", CASES[:3])
+def test_search_force_int32(mode, ends, blosum):
+    T = _targets(3, 200, 150)
+    Q = _queries(4, [1, 16, 17, 40, 130])
+    log(f"force_int32 mode={mode}")
+    got, _ = gpu_search(Q, T, blosum, 10, 1, mode, ends, force_int32=True)
+    exp = oracle.search(Q, T, blosum, 10, 1, mode=mode, ends=ends)
+    compare_search(got, exp, len(Q), len(T), label=f"int32 {mode}")
+    assert (got["status"] & 1).all()
+
+
+@pytest.mark.parametrize("mode", ["local", "global", "semiglobal"])
+def test_search_int16_overflow_rerun(mode, blosum):
+    # x5 matrix: self-similar pairs exceed 32767 and must come from the int32 pass
+    S = (blosum.astype(np.int32) * 5).clip(-128, 127).astype(np.int8)
+    rng = np.random.default_rng([170101575, 52])
+    base = gen.background_residues(rng, 1400)
+    seqs = [base[:k] for k in (300, 700, 1400)] + [gen.background_residues(rng, 500) for _ in range(40)]
+    T = SeqSet.from_list(seqs)
+    Q = SeqSet.from_list([base, base[:200]])
+    log(f"overflow mode={mode}")
+    got, _ = gpu_search(Q, T, S, 40, 4, mode)
+    exp = oracle.search(Q, T, S, 40, 4, mode=mode)
+    compare_search(got, exp, len(Q), len(T), label=f"ovf {mode}")
+    if mode == "local":
+        assert exp["score"].max() > 32767
+        big = exp["score"] > 32767
+        assert (got["status"][big] & 1).all()
+
+
+def test_search_dna_alphabet(dna):
+    rng = np.random.default_rng([170101575, 53])
+    T = SeqSet.from_list([rng.integers(0, 5, size=int(L)).astype(np.uint8)
+                          for L in rng.integers(0, 300, size=150)])
+    Q = SeqSet.from_list([rng.integers(0, 4, size=L).astype(np.uint8) for L in (20, 150)])
+    got, _ = gpu_search(Q, T, dna, 5, 2, "local")
+    exp = oracle.search(Q, T, dna, 5, 2, mode="local")
+    compare_search(got, exp, len(Q), len(T), label="dna")
+
+
+def test_cfg1_full_parity():
+    c = gen.cfg1()
+    log("cfg1 full")
+    for plain in (True, False):
+        got, _ = gpu_search(c["queries"], c["targets"], c["matrix"], 11, 1, "local", plain=plain)
+        exp = oracle.search(c["queries"], c["targets"], c["matrix"], 11, 1)
+        compare_search(got, exp, 1, 1000, label=f"cfg1 plain={plain}")
+
+
+def test_cfg2_reduced_full_parity():
+    c = gen.cfg2(n_targets=3000, query_lengths=(144, 464, 1000))
+    log("cfg2 reduced: 3 queries x 3000 targets")
+    got, _ = gpu_search(c["queries"], c["targets"], c["matrix"], 11, 1, "local")
+    exp = oracle.search(c["queries"], c["targets"], c["matrix"], 11, 1)
+    compare_search(got, exp, 3, 3000, label="cfg2 reduced")
+
+
+def test_cfg2_full_size_sampled():
+    """Full-size workload (5 queries x 200,000 targets) in the launch
+    configuration the benchmark times; per query 20 random targets and the 4
+    longest, recomputed by the oracle one by one."""
+    c = gen.cfg2()
+    Q, T = c["queries"], c["targets"]
+    nt = len(T)
+    log("cfg2 full size sampled")
+    got, _ = gpu_search(Q, T, c["matrix"], 11, 1, "local")
+    rng = np.random.default_rng([170101575, 54])
+    longest = np.argsort(T.lengths)[-4:]
+    qi = np.repeat(np.arange(5), 24)
+    ti = np.concatenate([np.concatenate([rng.integers(0, nt, size=20), longest]) for _ in range(5)])
+    exp = oracle.align_index(qi, ti, Q, T, c["matrix"], 11, 1, mode="local")
+    for f in ("score", "q_end", "t_end"):
+        g = got[f].reshape(5, nt)[qi, ti]
+        assert (g == exp[f]).all(), f
+    assert (got["score"] >= 0).all() and (got["score"] < 32767).all()
