@@ -1,0 +1,214 @@
+"""Benchmark: protein database search on one MI355X.
+
+Workload (the database-search configuration): 5 synthetic protein queries of
+lengths 144, 464, 1000, 2000 and 5000 against 200,000 synthetic targets with
+log-normal lengths (median 300, ~70.8 M residues); BLOSUM62, gap open 11 /
+extend 1; local alignment, score + end coordinates; exact (int16 pass with
+an int32 rerun of anything that saturated).
+
+One step = one dsa_align_batch call over all 5 queries (the batched form:
+one persistent launch with length-binned, longest-first work units).  The
+plain form (one launch per query) is timed too.  GCUPS counts the full
+m x n rectangle of every (query, target) pair.
+
+Prints one JSON line (rank 0).  `--gpus N` with N > 1 exits with a message:
+this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_INT16_TOPS = 78.6      # 256 CUs x 4 SIMD x 16 lanes x 2 halves x 2.4 GHz
+OPS_PER_CELL = 10           # local score + end, algorithmic int16 ops per cell
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_hash():
+    p = os.path.join(ROOT, "paper_1701_01575_amd", "csrc", "search.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(cells):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    or None when the kernel changed since it was taken."""
+    p = os.path.join(ROOT, "profiles", "search16_cfg2_pmc.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--targets", type=int, default=200_000)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1701_01575_amd as dsa
+    from paper_1701_01575_amd import binding as B
+    from workloads import gen
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    t0 = time.perf_counter()
+    c = gen.cfg2(n_targets=args.targets)
+    Q, T, S = c["queries"], c["targets"], c["matrix"]
+    log(f"generated workload in {time.perf_counter() - t0:.1f}s: {len(Q)} queries, "
+        f"{len(T)} targets, {int(T.lengths.sum())} residues")
+    t0 = time.perf_counter()
+    db = dsa.Database.from_seqset(T, S.shape[0])
+    torch.cuda.synchronize()
+    pack_s = time.perf_counter() - t0
+    log(f"database packed and resident in {pack_s:.2f}s")
+
+    cells = int(Q.lengths.sum()) * int(T.lengths.sum())
+    qc, qo = dsa.device_queries(Q, dev)
+    nq, nt = len(Q), len(T)
+    stream = torch.cuda.current_stream()
+
+    def prepared(plain):
+        a = dsa.make_args(qc, qo, S, 11, 1, "local", db=db, plain=plain, stream=stream)
+        need = B.dsa_workspace_size(a)
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+        base = (ws.data_ptr() + 255) // 256 * 256
+        a.workspace = base
+        a.workspace_bytes = need
+        outs = {k: torch.empty(nq * nt, dtype=torch.int32, device=dev) for k in ("score", "q_end", "t_end")}
+        outs["status"] = torch.empty(nq * nt, dtype=torch.uint8, device=dev)
+        o = B.dsa_out()
+        for k, v in outs.items():
+            setattr(o, k, v.data_ptr())
+        return a, o, outs, ws
+
+    def run(plain, warmup, steps, timing=False):
+        a, o, outs, ws = prepared(plain)
+        for _ in range(warmup):
+            B.dsa_align_batch(a, o)
+        torch.cuda.synchronize()
+        if timing:
+            B.dsa_timing_read()
+            B.dsa_timing_enable(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            B.dsa_align_batch(a, o)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        kms, nl = (0.0, 0)
+        if timing:
+            kms, nl = B.dsa_timing_read()
+            B.dsa_timing_enable(False)
+        return dt, kms, nl, outs
+
+    log(f"batched: {args.warmup} warmup + {args.steps} timed steps")
+    dt, kms, nl, outs = run(False, args.warmup, args.steps, timing=True)
+    ms_step = dt / args.steps * 1e3
+    gcups = cells / (dt / args.steps) / 1e9
+    log(f"batched: {ms_step:.2f} ms/step, {gcups:.1f} GCUPS; kernel {kms / max(nl, 1):.2f} ms x {nl}")
+
+    log(f"plain: 1 warmup + {args.plain_steps} timed steps")
+    pdt, _, _, _ = run(True, 1, args.plain_steps)
+    plain_ms = pdt / args.plain_steps * 1e3
+    plain_gcups = cells / (pdt / args.plain_steps) / 1e9
+    log(f"plain: {plain_ms:.2f} ms/step, {plain_gcups:.1f} GCUPS")
+
+    kernel_ms = kms / max(nl, 1)
+    achieved = cells * OPS_PER_CELL / (kernel_ms * 1e-3) / 1e12
+    traffic = load_traffic(cells)
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_INT16_TOPS,
+                "unit": "TOP/s (packed int16 VALU ops)", "frac": round(achieved / PEAK_INT16_TOPS, 4),
+                "traffic": traffic, "kernel": "k_search16<T=32,local,persistent>",
+                "kernel_ms": round(kernel_ms, 3), "ops_per_cell": OPS_PER_CELL,
+                "cells_per_launch": cells}
+
+    score = outs["score"].cpu().numpy().reshape(nq, nt)
+    q_end = outs["q_end"].cpu().numpy().reshape(nq, nt)
+    t_end = outs["t_end"].cpu().numpy().reshape(nq, nt)
+    status = outs["status"].cpu().numpy().reshape(nq, nt)
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle  # CPU baseline leg only
+        threads = min(len(os.sched_getaffinity(0)), 16)
+        rng = np.random.default_rng([170101575, 77])
+        done_cells, elapsed, agree, npairs = 0, 0.0, True, 0
+        while elapsed < args.cpu_seconds:
+            qi = np.full(64, 2, np.int64)  # the 1000-residue query
+            ti = rng.integers(0, nt, size=64)
+            t = time.perf_counter()
+            r = oracle.align_index(qi, ti, Q, T, S, 11, 1, mode="local", threads=threads)
+            elapsed += time.perf_counter() - t
+            done_cells += int(Q.lengths[2]) * int(T.lengths[ti].sum())
+            npairs += 64
+            agree &= bool((r["score"] == score[qi, ti]).all() and (r["q_end"] == q_end[qi, ti]).all()
+                          and (r["t_end"] == t_end[qi, ti]).all())
+        cpu = {"value": round(done_cells / elapsed / 1e9, 4), "unit": "GCUPS", "cores": threads,
+               "kind": "oracle",
+               "sample": f"{npairs} pairs: the 1000-residue query vs random targets "
+                         f"({done_cells / 1e9:.2f} G cells in {elapsed:.1f}s)",
+               "agrees_with_gpu": agree}
+        log(f"cpu oracle: {cpu['value']} GCUPS on {threads} threads, agrees={agree}")
+
+    line = {
+        "metric": "GCUPS (cell updates/s) at bit-exact scores, batched vs plain; p50/p99 latency",
+        "value": round(gcups, 2),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i16",
+        "data": "synthetic",
+        "config": {"workload": "protein database search: 5 queries (144, 464, 1000, 2000, 5000) "
+                               f"vs {nt} log-normal targets, BLOSUM62 11/1, local, score + end",
+                   "cells": cells, "queries": nq, "targets": nt,
+                   "residues": int(T.lengths.sum()), "form": "batched (persistent, LPT units)"},
+        "plain": {"value": round(plain_gcups, 2), "unit": "GCUPS", "ms_per_step": round(plain_ms, 3),
+                  "form": "one launch per query"},
+        "batched_over_plain": round(gcups / plain_gcups, 3),
+        "db_pack_s": round(pack_s, 3),
+        "int32_reruns": int((status & 1).sum()),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -174,6 +174,25 @@ int dsa_cigar_capacity(const dsa_args *args, int64_t *entries);
  */
 int dsa_align_batch(const dsa_args *args, const dsa_out *out);
 
+/*
+ * Measurement hooks.  dsa_timing_enable(1) makes dsa_align_batch record a
+ * pair of HIP events on args->stream around every launch of its main
+ * alignment kernel; dsa_timing_read waits for them, returns the summed
+ * kernel time in milliseconds and the launch count, and clears the record.
+ * Used by the benchmark to time the dominant kernel; off by default.
+ */
+int dsa_timing_enable(int on);
+int dsa_timing_read(double *total_ms, int64_t *launches);
+
+/*
+ * dsa_probe - measured ceilings on the current device (blocking; allocates
+ * its own scratch).  which: 0 v_pk_add_i16 (clamp), 1 v_pk_max_i16,
+ * 2 v_pk_sub_u16 (clamp), 3 v_add_u32, 4 v_max_i32 -> *rate = instructions
+ * per second summed over lanes, size = loop iterations; 5 -> HBM copy of
+ * `size` bytes, *rate = bytes read + written per second.
+ */
+int dsa_probe(int which, int64_t size, double *rate);
+
 const char *dsa_strerror(int status);
 const char *dsa_last_error(void);
 int32_t dsa_abi_version(void);

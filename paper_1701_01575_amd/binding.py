@@ -18,8 +18,9 @@ DSA_TRACEBACK, DSA_PLAIN, DSA_FORCE_INT32 = 1, 2, 4
 DSA_ST_INT32, DSA_ST_TRUNCATED = 1, 2
 
 EXPORTS = ["dsa_db_create", "dsa_db_destroy", "dsa_db_info", "dsa_workspace_size",
-           "dsa_cigar_capacity", "dsa_align_batch", "dsa_strerror", "dsa_last_error",
-           "dsa_abi_version"]
+           "dsa_cigar_capacity", "dsa_align_batch", "dsa_timing_enable", "dsa_timing_read",
+           "dsa_probe",
+           "dsa_strerror", "dsa_last_error", "dsa_abi_version"]
 
 
 class DsaError(RuntimeError):
@@ -83,6 +84,9 @@ def lib():
         L.dsa_workspace_size.argtypes = [ctypes.POINTER(dsa_args), ctypes.POINTER(ctypes.c_size_t)]
         L.dsa_cigar_capacity.argtypes = [ctypes.POINTER(dsa_args), ctypes.POINTER(ctypes.c_int64)]
         L.dsa_align_batch.argtypes = [ctypes.POINTER(dsa_args), ctypes.POINTER(dsa_out)]
+        L.dsa_timing_enable.argtypes = [ctypes.c_int]
+        L.dsa_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        L.dsa_probe.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
         L.dsa_strerror.argtypes = [ctypes.c_int]
         L.dsa_strerror.restype = ctypes.c_char_p
         L.dsa_last_error.argtypes = []
@@ -136,6 +140,23 @@ def dsa_align_batch(args: dsa_args, out: dsa_out) -> int:
     if st not in (DSA_OK, DSA_E_CAPACITY):
         check(st, "dsa_align_batch")
     return st
+
+
+def dsa_timing_enable(on: bool):
+    check(lib().dsa_timing_enable(1 if on else 0), "dsa_timing_enable")
+
+
+def dsa_timing_read():
+    """(summed kernel milliseconds, launch count) since the last read."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    check(lib().dsa_timing_read(ctypes.byref(ms), ctypes.byref(n)), "dsa_timing_read")
+    return ms.value, n.value
+
+
+def dsa_probe(which: int, size: int) -> float:
+    r = ctypes.c_double()
+    check(lib().dsa_probe(which, size, ctypes.byref(r)), "dsa_probe")
+    return r.value
 
 
 def dsa_strerror(status: int) -> str:

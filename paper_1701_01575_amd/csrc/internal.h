@@ -18,13 +18,14 @@ enum Ends { QB = 1, QE = 2, TB = 4, TE = 8 };
 // One group of 128 length-sorted targets.
 struct GroupInfo {
     int64_t off;      // first uint2 of the group's column blocks in `packed`
-    int64_t bnd;      // first uint4 of the group's boundary rows inside one query slot
+    int64_t bnd;      // first uint2 of the group's boundary words inside one query slot
     int32_t ncols;    // columns, multiple of 4 (max target length, rounded up)
     int32_t slot0;    // first slot: slots slot0 .. slot0+127
 };
 
 struct QueryInfo {
     int64_t off;      // into the query code buffer
+    int64_t prof;     // first dword of the query's pair profile (int16 pass)
     int32_t len;      // m >= 1
     int32_t strips;   // ceil(m / T)
 };
@@ -51,8 +52,9 @@ struct SearchArgs {
     const SearchUnit *units;
     int32_t n_units;
     int32_t A, AP, o, e, ends;
-    uint4 *bnd;
-    int64_t bnd_slot_stride;      // uint4 per query slot
+    uint2 *bnd;                   // per column and lane: (H of the strip's last row, F leaving it)
+    int64_t bnd_slot_stride;      // uint2 per query slot
+    const uint32_t *prof;         // pair profiles (k_profile16)
     int32_t *out_score, *out_qend, *out_tend;
     uint8_t *out_status;
     int64_t n_t;                  // output row stride (targets per query)
@@ -60,6 +62,50 @@ struct SearchArgs {
     const int32_t *qflag;         // per query: int16 bound fails (global / semi-global)
     int32_t *counter;             // persistent-grid work counter
 };
+
+// Intra-sequence (wavefront) work: long targets of long queries.  Targets
+// of the length-sorted groups from `long_group0` on are also stored as pairs
+// (two consecutive sorted targets, the low and high int16 halves of a lane).
+struct LongPair {
+    int64_t off;      // first uint16 (low code | high code << 8 per column)
+    int64_t bnd;      // first uint2 of the pair's boundary words in one query slot
+    int32_t ncols;    // longer of the two lengths
+    int32_t slot;     // sorted slot of the low target; the high one is slot + 1
+};
+
+struct IntraUnit {
+    int32_t q;
+    int32_t lp0;      // first long pair; one pair per wave
+    int32_t np;       // pairs in this unit (<= waves per block)
+    int32_t runit;    // int32 rerun unit (q, group of these pairs)
+    int32_t qslot;
+    int32_t pad;
+};
+
+struct IntraArgs {
+    const LongPair *pairs;
+    const uint16_t *lcodes;
+    const IntraUnit *units;
+    int32_t n_units;
+    const QueryInfo *qinfo;       // strips counted in rows of kTI
+    const uint8_t *q_codes;
+    const int8_t *subst;
+    const uint8_t *inv_map;
+    int32_t A, AP, o, e, ends;
+    uint2 *bnd;
+    int64_t bnd_slot_stride;      // uint2 per query slot
+    int32_t *out_score, *out_qend, *out_tend;
+    uint8_t *out_status;
+    int64_t n_t;
+    const int32_t *slot_target;
+    const int32_t *slot_len;
+    int32_t *unit_flags;          // indexed by IntraUnit.runit
+    const int32_t *qflag;
+};
+constexpr int kTI = 16;           // rows per lane in the wavefront kernel
+constexpr int kIntraWaves = 4;    // waves (pairs) per block
+hipError_t launch_intra16(const IntraArgs &a, int mode, int n_blocks, size_t lds, hipStream_t s);
+size_t intra16_lds_bytes(int AP, int A);
 
 // Launchers (kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_search16(const SearchArgs &a, int T, int mode, int waves_per_block,
@@ -84,6 +130,19 @@ struct BoundArgs {
     int32_t *qflag;
 };
 hipError_t launch_bound16(const BoundArgs &a, hipStream_t s);
+
+struct ProfileArgs {
+    const uint8_t *q_codes;
+    const QueryInfo *qinfo;       // prof offsets ascending
+    int32_t n_q;
+    const int8_t *subst;
+    int32_t A, AP;
+    const uint8_t *inv_map;
+    const uint8_t *pair_dec;
+    uint32_t *prof;
+    int64_t total_dwords;
+};
+hipError_t launch_profile16(const ProfileArgs &a, int T, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 size_t search16_lds_bytes(int T, int AP);
 size_t search32_lds_bytes(int AP);

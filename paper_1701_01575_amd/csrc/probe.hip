@@ -1,0 +1,110 @@
+// Peak probes: measured issue rate of the VALU instructions the alignment
+// kernels are built from (packed int16 add/sub with clamp, packed max,
+// plain 32-bit ops) and an HBM stream copy.  They give the measured
+// ceilings the roofline fractions are compared against.
+#include <algorithm>
+
+#include "dsa.h"
+#include "internal.h"
+
+namespace dsa {
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+template <int OP>
+__device__ __forceinline__ uint32_t probe_op(uint32_t a, uint32_t b) {
+    if (OP == 0) return __builtin_bit_cast(uint32_t, __builtin_elementwise_add_sat(
+                                              __builtin_bit_cast(s16x2, a), __builtin_bit_cast(s16x2, b)));
+    if (OP == 1) return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(
+                                              __builtin_bit_cast(s16x2, a), __builtin_bit_cast(s16x2, b)));
+    if (OP == 2) return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(
+                                              __builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b)));
+    if (OP == 3) return a + b;
+    return (uint32_t)max((int)a, (int)b);
+}
+
+// 16 independent chains per lane so dependency latency never limits issue.
+template <int OP>
+__global__ void __launch_bounds__(256) k_probe(uint32_t *out, int iters, uint32_t seed) {
+    uint32_t acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) acc[k] = seed * (threadIdx.x + 1) + k;
+    uint32_t b = seed ^ blockIdx.x;
+    for (int it = 0; it < iters; it++) {
+#pragma unroll
+        for (int k = 0; k < 16; k++) acc[k] = probe_op<OP>(acc[k], b);
+        b += 0x00010001u;
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (int k = 0; k < 16; k++) r ^= acc[k];
+    if (r == 0x12345678u) out[blockIdx.x] = r;  // keeps the chains alive
+}
+
+__global__ void k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+}  // namespace dsa
+
+using namespace dsa;
+
+// which: 0 = v_pk_add_i16 clamp, 1 = v_pk_max_i16, 2 = v_pk_sub_u16 clamp,
+// 3 = v_add_u32, 4 = v_max_i32 (result: instructions per second summed over
+// lanes); 5 = HBM copy of `bytes` (result: bytes read + written per second).
+extern "C" int dsa_probe(int which, int64_t size, double *rate) {
+    if (!rate || which < 0 || which > 5 || size <= 0) return DSA_E_INVAL;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return DSA_E_DEVICE;
+    int dev = 0, cus = 256;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int rc = DSA_OK;
+    if (which < 5) {
+        uint32_t *out = nullptr;
+        const int blocks = cus * 8;  // 8 x 4 waves per CU
+        if (hipMalloc(&out, blocks * sizeof(uint32_t)) != hipSuccess) return DSA_E_DEVICE;
+        const int iters = (int)std::min<int64_t>(size, 1 << 30);
+        auto launch = [&]() {
+            switch (which) {
+                case 0: hipLaunchKernelGGL(k_probe<0>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
+                case 1: hipLaunchKernelGGL(k_probe<1>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
+                case 2: hipLaunchKernelGGL(k_probe<2>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
+                case 3: hipLaunchKernelGGL(k_probe<3>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
+                default: hipLaunchKernelGGL(k_probe<4>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
+            }
+        };
+        launch();
+        hipEventRecord(a, 0);
+        launch();
+        hipEventRecord(b, 0);
+        if (hipEventSynchronize(b) != hipSuccess) rc = DSA_E_DEVICE;
+        float ms = 0;
+        hipEventElapsedTime(&ms, a, b);
+        *rate = (double)blocks * 256.0 * 16.0 * iters / (ms * 1e-3);
+        hipFree(out);
+    } else {
+        uint4 *src = nullptr, *dst = nullptr;
+        const int64_t n = size / 16;
+        if (hipMalloc(&src, n * 16) != hipSuccess) return DSA_E_DEVICE;
+        if (hipMalloc(&dst, n * 16) != hipSuccess) { hipFree(src); return DSA_E_DEVICE; }
+        hipMemset(src, 1, n * 16);
+        hipLaunchKernelGGL(k_stream_copy, dim3(cus * 16), dim3(256), 0, 0, src, dst, n);
+        hipEventRecord(a, 0);
+        for (int r = 0; r < 5; r++)
+            hipLaunchKernelGGL(k_stream_copy, dim3(cus * 16), dim3(256), 0, 0, src, dst, n);
+        hipEventRecord(b, 0);
+        if (hipEventSynchronize(b) != hipSuccess) rc = DSA_E_DEVICE;
+        float ms = 0;
+        hipEventElapsedTime(&ms, a, b);
+        *rate = 5.0 * 2.0 * (double)n * 16.0 / (ms * 1e-3);
+        hipFree(src);
+        hipFree(dst);
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    return rc;
+}

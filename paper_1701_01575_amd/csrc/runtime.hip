@@ -1,6 +1,7 @@
 // Host runtime of libdsa: argument checks, database packing, work planning
 // and the C ABI declared in include/dsa.h.
 #include <algorithm>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -41,6 +42,37 @@ struct Staging {
 };
 Staging g_staging[64];
 
+// Optional kernel timing (dsa_timing_enable / dsa_timing_read).
+struct Timing {
+    std::mutex mu;
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+    size_t used = 0;
+};
+Timing g_timing;
+
+int timing_begin(hipStream_t st, size_t *slot) {
+    *slot = SIZE_MAX;
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    if (!g_timing.on) return DSA_OK;
+    if (g_timing.used == g_timing.pool.size()) {
+        hipEvent_t a, b;
+        HIPCHK(hipEventCreate(&a));
+        HIPCHK(hipEventCreate(&b));
+        g_timing.pool.push_back({a, b});
+    }
+    *slot = g_timing.used++;
+    HIPCHK(hipEventRecord(g_timing.pool[*slot].first, st));
+    return DSA_OK;
+}
+
+int timing_end(hipStream_t st, size_t slot) {
+    if (slot == SIZE_MAX) return DSA_OK;
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    HIPCHK(hipEventRecord(g_timing.pool[slot].second, st));
+    return DSA_OK;
+}
+
 int device_cus(int dev) {
     static int cache[64] = {0};
     if (dev < 0 || dev >= 64) return 256;
@@ -61,18 +93,25 @@ struct dsa_db {
     uint8_t code_map[kMaxAlphabet];
     uint8_t inv_map[kMaxAlphabet + 1];
     int64_t n_targets = 0, n_residues = 0, n_groups = 0, max_len = 0;
-    int64_t bnd_slot_uint4 = 0;  // boundary rows of one query slot (int32 sized)
+    int64_t bnd_slot_uint2 = 0;  // boundary words of one query slot (int32 sized)
     std::vector<int64_t> len;
     std::vector<GroupInfo> grp;
-    std::vector<int64_t> grp_cells;  // sum of ncols over the group's targets' max (cost)
+    int64_t long_group0 = 0;         // groups from here on are also stored as long pairs
+    std::vector<LongPair> pairs;     // 64 per long group
+    int64_t long_bnd_slot = 0;       // uint2 boundary words of all long pairs (one query slot)
     // device
     uint2 *d_packed = nullptr;
     GroupInfo *d_grp = nullptr;
     int32_t *d_slot_target = nullptr, *d_slot_len = nullptr;
     uint8_t *d_pair_dec = nullptr, *d_inv_map = nullptr;
     int64_t *d_len = nullptr;
+    LongPair *d_pairs = nullptr;
+    uint16_t *d_lcodes = nullptr;
     int64_t device_bytes = 0;
 };
+
+constexpr int kLongMin = 128;  // groups this wide or wider also get the long-pair layout
+static_assert(kTI == kT32, "the wavefront and int32 kernels share the 16-row strip count");
 
 static void db_free(dsa_db *db) {
     if (!db) return;
@@ -83,6 +122,8 @@ static void db_free(dsa_db *db) {
     hipFree(db->d_pair_dec);
     hipFree(db->d_inv_map);
     hipFree(db->d_len);
+    hipFree(db->d_pairs);
+    hipFree(db->d_lcodes);
     delete db;
 }
 
@@ -161,9 +202,9 @@ extern "C" int dsa_db_create(const uint8_t *codes, const int64_t *offsets, int64
         G.off = off;
         G.bnd = bnd;
         off += (int64_t)(G.ncols / 4) * kWave;
-        bnd += (int64_t)G.ncols * kWave;  // 2 waves x ncols/4 blocks x 64 lanes x 2 uint4
+        bnd += 2LL * G.ncols * kWave;  // (H, F) per column and lane, two waves for int32
     }
-    db->bnd_slot_uint4 = bnd;
+    db->bnd_slot_uint2 = bnd;
     std::vector<uint16_t> packed((size_t)off * 4);
     for (int64_t g = 0; g < db->n_groups; g++) {
         const GroupInfo &G = db->grp[g];
@@ -180,6 +221,30 @@ extern "C" int dsa_db_create(const uint8_t *codes, const int64_t *offsets, int64
             }
         }
     }
+    // long-pair layout: two consecutive sorted targets per wave of the
+    // wavefront kernel, one uint16 (low code | high code << 8) per column
+    db->long_group0 = db->n_groups;
+    for (int64_t g = 0; g < db->n_groups; g++)
+        if (db->grp[g].ncols >= kLongMin) { db->long_group0 = g; break; }
+    std::vector<uint16_t> lcodes;
+    for (int64_t g = db->long_group0; g < db->n_groups; g++) {
+        for (int k = 0; k < kGroup / 2; k++) {
+            LongPair L;
+            L.slot = (int32_t)(g * kGroup + 2 * k);
+            const int32_t tl = slot_target[L.slot], th = slot_target[L.slot + 1];
+            const int64_t nl = tl >= 0 ? db->len[tl] : 0, nh = th >= 0 ? db->len[th] : 0;
+            L.ncols = (int32_t)std::max(nl, nh);
+            L.off = (int64_t)lcodes.size();
+            L.bnd = db->long_bnd_slot;
+            db->long_bnd_slot += L.ncols;
+            for (int64_t j = 0; j < L.ncols; j++) {
+                const uint16_t lo = j < nl ? db->code_map[codes[offsets[tl] + j]] : pad;
+                const uint16_t hi = j < nh ? db->code_map[codes[offsets[th] + j]] : pad;
+                lcodes.push_back((uint16_t)(lo | (hi << 8)));
+            }
+            db->pairs.push_back(L);
+        }
+    }
     std::vector<uint8_t> pair_dec((size_t)AP * AP * 2);
     for (int p = 0; p < AP * AP; p++) {
         pair_dec[2 * p] = (uint8_t)(p / AP);
@@ -194,7 +259,9 @@ extern "C" int dsa_db_create(const uint8_t *codes, const int64_t *offsets, int64
         (rc = upload(&db->d_slot_len, slot_len.data(), slot_len.size(), &db->device_bytes)) ||
         (rc = upload(&db->d_pair_dec, pair_dec.data(), pair_dec.size(), &db->device_bytes)) ||
         (rc = upload(&db->d_inv_map, db->inv_map, (size_t)AP, &db->device_bytes)) ||
-        (rc = upload(&db->d_len, db->len.data(), db->len.size(), &db->device_bytes))) {
+        (rc = upload(&db->d_len, db->len.data(), db->len.size(), &db->device_bytes)) ||
+        (rc = upload(&db->d_pairs, db->pairs.data(), db->pairs.size(), &db->device_bytes)) ||
+        (rc = upload(&db->d_lcodes, lcodes.data(), lcodes.size(), &db->device_bytes))) {
         db_free(db);
         return rc;
     }
@@ -235,15 +302,22 @@ struct Plan {
     bool persistent = true;
     bool force32 = false;
     int mode = 0, ends = 0;
-    std::vector<SearchUnit> units;  // all units; per-query ranges for the plain form
-    std::vector<int64_t> unit_first, unit_count;  // per query (plain form)
+    std::vector<SearchUnit> units;  // int16 inter units, then int32-only rerun units of long groups
+    std::vector<int64_t> unit_first, unit_count, unit_inter;  // per query (plain form)
+    int64_t n_inter = 0;            // persistent form: units[0 .. n_inter) go to the int16 kernel
+    std::vector<IntraUnit> iunits;
+    std::vector<int64_t> iunit_first, iunit_count;
+    int64_t budget = 48000;         // strips x columns above which a group goes to the wavefront kernel
+    size_t ldsI = 0;
     std::vector<QueryInfo> qinfo;
     std::vector<int32_t> empty_rows;
     int n_slots = 1;
     size_t lds16 = 0, lds32 = 0;
     // workspace layout (byte offsets)
     size_t off_units = 0, off_qinfo = 0, off_subst = 0, off_rows = 0, table_bytes = 0;
-    size_t off_flags = 0, off_qflag = 0, off_counter = 0, off_bnd = 0, total = 0;
+    size_t off_flags = 0, off_qflag = 0, off_counter = 0, off_bnd = 0, off_prof = 0, total = 0;
+    size_t off_iunits = 0, off_ibnd = 0;
+    int64_t prof_dwords = 0;
     int32_t min_s = 0, max_abs_s = 0;
 };
 
@@ -295,6 +369,16 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     // pick the strip height from the LDS the pair profile needs
     P.T = 32;
     if (search16_lds_bytes(32, db->AP) > 80 * 1024) P.T = 16;
+    // tuning overrides (used by the autotuning sweeps)
+    if (const char *v = getenv("DSA_STRIP")) {
+        const int t = atoi(v);
+        if (t == 16 || t == 32) P.T = t;
+    }
+    if (const char *v = getenv("DSA_WAVES")) {
+        const int w = atoi(v);
+        if (w >= 1 && w <= 8) P.wpb16 = w;
+    }
+    if (const char *v = getenv("DSA_INTRA_BUDGET")) P.budget = atoll(v);
     P.lds16 = search16_lds_bytes(P.T, db->AP);
     P.lds32 = search32_lds_bytes(db->AP);
     if (P.lds16 > 160 * 1024) return fail(DSA_E_NOTSUP, "alphabet too large for the LDS profile");
@@ -303,6 +387,10 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     P.qinfo.resize(nq);
     P.unit_first.assign(nq, 0);
     P.unit_count.assign(nq, 0);
+    P.unit_inter.assign(nq, 0);
+    P.iunit_first.assign(nq, 0);
+    P.iunit_count.assign(nq, 0);
+    P.ldsI = intra16_lds_bytes(db->AP, A);
     for (int64_t q = 0; q < nq; q++) {
         const int64_t m = a->q_offsets[q + 1] - a->q_offsets[q];
         if (m > kMaxLen16) return fail(DSA_E_NOTSUP, "queries longer than 65532 residues are not supported");
@@ -313,46 +401,103 @@ int make_search_plan(const dsa_args *a, Plan &P) {
         P.qinfo[q].off = a->q_offsets[q];
         P.qinfo[q].len = (int32_t)m;
         P.qinfo[q].strips = (int32_t)((m + P.T - 1) / P.T);
+        P.qinfo[q].prof = P.prof_dwords;
+        P.prof_dwords += (int64_t)P.qinfo[q].strips * db->AP * db->AP * (P.T + 4);
         if (m == 0) P.empty_rows.push_back((int32_t)q);
     }
     // int32 kernel uses T = 32 strips: keep one strip count per query for both
     // by planning int16 with its own T and int32 with 32 (QueryInfo.strips is
     // rewritten per pass on the device copy; see dsa_align_batch).
     const int wpb = P.wpb16;
+    std::vector<SearchUnit> inter, rerun;
     for (int64_t q = 0; q < nq; q++) {
         if (P.qinfo[q].len == 0) continue;
-        P.unit_first[q] = (int64_t)P.units.size();
-        for (int64_t g0 = 0; g0 < db->n_groups; g0 += wpb) {
+        // groups from gc on go to the wavefront kernel: their inter-sequence
+        // unit would be one long sequential task (strips x columns > budget)
+        int64_t gc = db->n_groups;
+        for (int64_t g = db->long_group0; g < db->n_groups; g++)
+            if ((int64_t)P.qinfo[q].strips * db->grp[g].ncols > P.budget) { gc = g; break; }
+        const int32_t qslot = P.persistent ? (int32_t)q : 0;
+        const int64_t first_inter = (int64_t)inter.size();
+        for (int64_t g0 = 0; g0 < gc; g0 += wpb) {
             SearchUnit U;
             U.q = (int32_t)q;
             U.g0 = (int32_t)g0;
-            U.ng = (int32_t)std::min<int64_t>(wpb, db->n_groups - g0);
-            U.qslot = P.persistent ? (int32_t)q : 0;
-            P.units.push_back(U);
+            U.ng = (int32_t)std::min<int64_t>(wpb, gc - g0);
+            U.qslot = qslot;
+            inter.push_back(U);
         }
-        P.unit_count[q] = (int64_t)P.units.size() - P.unit_first[q];
+        const int64_t first_rerun = (int64_t)rerun.size();
+        P.iunit_first[q] = (int64_t)P.iunits.size();
+        for (int64_t g = gc; g < db->n_groups; g++) {
+            SearchUnit R;
+            R.q = (int32_t)q;
+            R.g0 = (int32_t)g;
+            R.ng = 1;
+            R.qslot = qslot;
+            const int32_t ridx = (int32_t)rerun.size();
+            rerun.push_back(R);
+            const int64_t pbase = (g - db->long_group0) * (kGroup / 2);
+            for (int k = 0; k < kGroup / 2; k += kIntraWaves) {
+                IntraUnit I;
+                I.q = (int32_t)q;
+                I.lp0 = (int32_t)(pbase + k);
+                I.np = kIntraWaves;
+                I.runit = ridx;  // made absolute below
+                I.qslot = qslot;
+                I.pad = 0;
+                P.iunits.push_back(I);
+            }
+        }
+        P.iunit_count[q] = (int64_t)P.iunits.size() - P.iunit_first[q];
+        P.unit_inter[q] = (int64_t)inter.size() - first_inter;
+        P.unit_count[q] = P.unit_inter[q] + ((int64_t)rerun.size() - first_rerun);
+        P.unit_first[q] = first_inter;  // provisional (plain layout fixed below)
+        (void)first_rerun;
     }
     if (P.persistent) {
-        // longest units first: strips x widest group of the unit
-        std::vector<int64_t> cost(P.units.size());
-        for (size_t k = 0; k < P.units.size(); k++) {
-            const SearchUnit &U = P.units[k];
+        // longest inter units first (strips x widest group); rerun units after
+        std::vector<int64_t> cost(inter.size());
+        for (size_t k = 0; k < inter.size(); k++) {
+            const SearchUnit &U = inter[k];
             cost[k] = (int64_t)P.qinfo[U.q].len * db->grp[U.g0 + U.ng - 1].ncols;
         }
-        std::vector<size_t> idx(P.units.size());
+        std::vector<size_t> idx(inter.size());
         std::iota(idx.begin(), idx.end(), 0);
         std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
-        std::vector<SearchUnit> sorted(P.units.size());
-        for (size_t k = 0; k < idx.size(); k++) sorted[k] = P.units[idx[k]];
-        P.units.swap(sorted);
+        for (size_t k = 0; k < idx.size(); k++) P.units.push_back(inter[idx[k]]);
+        P.n_inter = (int64_t)P.units.size();
+        for (auto &R : rerun) P.units.push_back(R);
+        for (auto &I : P.iunits) I.runit += (int32_t)P.n_inter;
+        // wavefront units: longest pairs first
+        std::stable_sort(P.iunits.begin(), P.iunits.end(), [&](const IntraUnit &x, const IntraUnit &y) {
+            const int64_t cx = (int64_t)P.qinfo[x.q].len * db->pairs[x.lp0 + x.np - 1].ncols;
+            const int64_t cy = (int64_t)P.qinfo[y.q].len * db->pairs[y.lp0 + y.np - 1].ncols;
+            return cx > cy;
+        });
         P.n_slots = (int)std::max<int64_t>(1, nq);
     } else {
+        // per query: its inter units, then its rerun units
+        size_t ii = 0, rr = 0;
+        for (int64_t q = 0; q < nq; q++) {
+            P.unit_first[q] = (int64_t)P.units.size();
+            for (int64_t k = 0; k < P.unit_inter[q]; k++) P.units.push_back(inter[ii++]);
+            const int64_t rbase = (int64_t)P.units.size();
+            const int64_t nr = P.unit_count[q] - P.unit_inter[q];
+            for (int64_t k = 0; k < nr; k++) P.units.push_back(rerun[rr + k]);
+            for (int64_t k = 0; k < P.iunit_count[q]; k++) {
+                IntraUnit &I = P.iunits[P.iunit_first[q] + k];
+                I.runit = (int32_t)(rbase + (I.runit - (int32_t)rr));
+            }
+            rr += nr;
+        }
         P.n_slots = 1;
     }
 
     // workspace layout
     size_t o = 0;
     P.off_units = o; o = align_up(o + std::max<size_t>(P.units.size(), 1) * sizeof(SearchUnit), 256);
+    P.off_iunits = o; o = align_up(o + std::max<size_t>(P.iunits.size(), 1) * sizeof(IntraUnit), 256);
     P.off_qinfo = o; o = align_up(o + 2 * nq * sizeof(QueryInfo), 256);  // int16 and int32 strips
     P.off_subst = o; o = align_up(o + (size_t)A * A, 256);
     P.off_rows = o; o = align_up(o + std::max<size_t>(P.empty_rows.size(), 1) * sizeof(int32_t), 256);
@@ -360,7 +505,9 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     P.off_flags = o; o = align_up(o + std::max<size_t>(P.units.size(), 1) * sizeof(int32_t), 256);
     P.off_qflag = o; o = align_up(o + nq * sizeof(int32_t), 256);
     P.off_counter = o; o = align_up(o + 2 * sizeof(int32_t), 256);
-    P.off_bnd = o; o = align_up(o + (size_t)P.n_slots * db->bnd_slot_uint4 * 16, 256);
+    P.off_bnd = o; o = align_up(o + (size_t)P.n_slots * db->bnd_slot_uint2 * 8, 256);
+    P.off_prof = o; o = align_up(o + (size_t)std::max<int64_t>(P.prof_dwords, 1) * 4, 256);
+    P.off_ibnd = o; o = align_up(o + (size_t)P.n_slots * std::max<int64_t>(db->long_bnd_slot, 1) * 8, 256);
     P.total = o;
     return DSA_OK;
 }
@@ -434,6 +581,8 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
         uint8_t *h = (uint8_t *)S.buf;
         memset(h, 0, P.table_bytes);
         if (!P.units.empty()) memcpy(h + P.off_units, P.units.data(), P.units.size() * sizeof(SearchUnit));
+        if (!P.iunits.empty())
+            memcpy(h + P.off_iunits, P.iunits.data(), P.iunits.size() * sizeof(IntraUnit));
         memcpy(h + P.off_qinfo, P.qinfo.data(), nq * sizeof(QueryInfo));
         memcpy(h + P.off_qinfo + nq * sizeof(QueryInfo), q32.data(), nq * sizeof(QueryInfo));
         memcpy(h + P.off_subst, a->subst, (size_t)A * A);
@@ -460,8 +609,9 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
     K.o = a->gap_open;
     K.e = a->gap_extend;
     K.ends = P.ends;
-    K.bnd = (uint4 *)(ws + P.off_bnd);
-    K.bnd_slot_stride = db->bnd_slot_uint4;
+    K.bnd = (uint2 *)(ws + P.off_bnd);
+    K.bnd_slot_stride = db->bnd_slot_uint2;
+    K.prof = (const uint32_t *)(ws + P.off_prof);
     K.out_score = out->score;
     K.out_qend = out->q_end;
     K.out_tend = out->t_end;
@@ -490,6 +640,20 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
         b.qflag = (int32_t *)(ws + P.off_qflag);
         HIPCHK(launch_bound16(b, st));
     }
+    if (!P.force32) {
+        ProfileArgs pa;
+        pa.q_codes = a->q_codes;
+        pa.qinfo = K.qinfo;
+        pa.n_q = (int32_t)nq;
+        pa.subst = K.subst;
+        pa.A = A;
+        pa.AP = db->AP;
+        pa.inv_map = db->d_inv_map;
+        pa.pair_dec = db->d_pair_dec;
+        pa.prof = (uint32_t *)(ws + P.off_prof);
+        pa.total_dwords = P.prof_dwords;
+        HIPCHK(launch_profile16(pa, P.T, st));
+    }
     if (out->q_begin) HIPCHK(launch_fill_i32(out->q_begin, -1, nq * db->n_targets, st));
     if (out->t_begin) HIPCHK(launch_fill_i32(out->t_begin, -1, nq * db->n_targets, st));
 
@@ -514,7 +678,11 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
                 HIPCHK(launch_fill_i32(counter, 0, 1, st));
                 nb = (int)std::min<int64_t>(n, (int64_t)cus * per_cu16);
             }
+            size_t slot;
+            int trc = timing_begin(st, &slot);
+            if (trc) return trc;
             HIPCHK(launch_search16(k, P.T, P.mode, P.wpb16, nb, P.persistent, P.lds16, st));
+            if ((trc = timing_end(st, slot))) return trc;
         } else {
             k.qinfo = qi32;
             int nb = (int)n;
@@ -528,10 +696,45 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
         return DSA_OK;
     };
 
+    IntraArgs I;
+    memset(&I, 0, sizeof(I));
+    I.pairs = db->d_pairs;
+    I.lcodes = db->d_lcodes;
+    I.qinfo = qi32;
+    I.q_codes = a->q_codes;
+    I.subst = K.subst;
+    I.inv_map = db->d_inv_map;
+    I.A = A;
+    I.AP = db->AP;
+    I.o = a->gap_open;
+    I.e = a->gap_extend;
+    I.ends = P.ends;
+    I.bnd = (uint2 *)(ws + P.off_ibnd);
+    I.bnd_slot_stride = db->long_bnd_slot;
+    I.out_score = out->score;
+    I.out_qend = out->q_end;
+    I.out_tend = out->t_end;
+    I.out_status = out->status;
+    I.n_t = db->n_targets;
+    I.slot_target = db->d_slot_target;
+    I.slot_len = db->d_slot_len;
+    I.qflag = K.qflag;
+    const IntraUnit *d_iunits = (const IntraUnit *)(ws + P.off_iunits);
+    auto intra = [&](const IntraUnit *units, int64_t n, int32_t *flags_base) -> int {
+        if (n <= 0 || P.force32) return DSA_OK;
+        IntraArgs x = I;
+        x.units = units;
+        x.n_units = (int32_t)n;
+        x.unit_flags = flags_base;
+        HIPCHK(launch_intra16(x, P.mode, (int)n, P.ldsI, st));
+        return DSA_OK;
+    };
+
     int rc;
     if (P.persistent) {
         if (!P.force32) {
-            if ((rc = pass(d_units, nunits, 0))) return rc;
+            if ((rc = intra(d_iunits, (int64_t)P.iunits.size(), K.unit_flags))) return rc;
+            if ((rc = pass(d_units, P.n_inter, 0))) return rc;
             if ((rc = pass(d_units, nunits, 1))) return rc;
         } else if ((rc = pass(d_units, nunits, 0))) {
             return rc;
@@ -541,7 +744,8 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
             if (P.unit_count[q] == 0) continue;
             const SearchUnit *u = d_units + P.unit_first[q];
             if (!P.force32) {
-                if ((rc = pass(u, P.unit_count[q], 0))) return rc;
+                if ((rc = intra(d_iunits + P.iunit_first[q], P.iunit_count[q], K.unit_flags))) return rc;
+                if ((rc = pass(u, P.unit_inter[q], 0))) return rc;
                 if ((rc = pass(u, P.unit_count[q], 1))) return rc;
             } else if ((rc = pass(u, P.unit_count[q], 0))) {
                 return rc;
@@ -583,6 +787,27 @@ extern "C" int dsa_align_batch(const dsa_args *args, const dsa_out *out) {
     if (args->db && args->db->device != dev)
         return fail(DSA_E_INVAL, "database lives on another device");
     return run_search(args, out, P);
+}
+
+extern "C" int dsa_timing_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    g_timing.on = on != 0;
+    return DSA_OK;
+}
+
+extern "C" int dsa_timing_read(double *total_ms, int64_t *launches) {
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    double tot = 0.0;
+    for (size_t k = 0; k < g_timing.used; k++) {
+        HIPCHK(hipEventSynchronize(g_timing.pool[k].second));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, g_timing.pool[k].first, g_timing.pool[k].second));
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = (int64_t)g_timing.used;
+    g_timing.used = 0;
+    return DSA_OK;
 }
 
 extern "C" const char *dsa_strerror(int status) {

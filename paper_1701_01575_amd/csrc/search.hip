@@ -29,60 +29,12 @@
 // a strictly-greater running best; when a column improves it, the first row
 // reaching the column maximum is located.  Strips are then merged
 // lexicographically (score desc, j asc, i asc).
+#include <algorithm>
+
 #include "internal.h"
+#include "pk16.h"
 
 namespace dsa {
-
-typedef short s16x2 __attribute__((ext_vector_type(2)));
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ s16x2 S2(uint32_t x) { return __builtin_bit_cast(s16x2, x); }
-__device__ __forceinline__ u16x2 U2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
-__device__ __forceinline__ uint32_t Bs(s16x2 x) { return __builtin_bit_cast(uint32_t, x); }
-__device__ __forceinline__ uint32_t Bu(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
-
-__device__ __forceinline__ uint32_t adds(uint32_t a, uint32_t b) { return Bs(__builtin_elementwise_add_sat(S2(a), S2(b))); }
-__device__ __forceinline__ uint32_t subs(uint32_t a, uint32_t b) { return Bs(__builtin_elementwise_sub_sat(S2(a), S2(b))); }
-__device__ __forceinline__ uint32_t maxs(uint32_t a, uint32_t b) { return Bs(__builtin_elementwise_max(S2(a), S2(b))); }
-__device__ __forceinline__ uint32_t subu(uint32_t a, uint32_t b) { return Bu(__builtin_elementwise_sub_sat(U2(a), U2(b))); }
-__device__ __forceinline__ uint32_t maxu(uint32_t a, uint32_t b) { return Bu(__builtin_elementwise_max(U2(a), U2(b))); }
-__device__ __forceinline__ uint32_t minu(uint32_t a, uint32_t b) { return Bu(__builtin_elementwise_min(U2(a), U2(b))); }
-__device__ __forceinline__ uint32_t addu(uint32_t a, uint32_t b) { return Bu(U2(a) + U2(b)); }
-__device__ __forceinline__ uint32_t mulu(uint32_t a, uint32_t b) { return Bu(U2(a) * U2(b)); }
-
-__device__ __forceinline__ uint32_t pack2(int lo, int hi) {
-    return (uint32_t)(uint16_t)lo | ((uint32_t)(uint16_t)hi << 16);
-}
-__device__ __forceinline__ uint32_t dup(int v) { return pack2(v, v); }
-__device__ __forceinline__ int lo16(uint32_t x) { return (int)(short)(x & 0xffffu); }
-__device__ __forceinline__ int hi16(uint32_t x) { return (int)(short)(x >> 16); }
-__device__ __forceinline__ uint32_t bfi(uint32_t mask, uint32_t a, uint32_t b) { return (a & mask) | (b & ~mask); }
-// 0xffff in each half of x that is nonzero, 0 elsewhere
-__device__ __forceinline__ uint32_t nzmask(uint32_t x) {
-    return Bu((u16x2)0 - __builtin_elementwise_min(U2(x), (u16x2)1));
-}
-
-constexpr int NEG16 = -32768;
-constexpr int PAD32 = -(1 << 30);
-
-// H[i][0]: the left boundary column (i >= 0).
-__device__ __forceinline__ int left_value(int mode, int ends, int o, int e, int i) {
-    if (i == 0 || mode == LOCAL || (ends & QB)) return 0;
-    return -(o + (i - 1) * e);
-}
-// H[0][j]: the top boundary row (j >= 0).
-__device__ __forceinline__ int top_value(int mode, int ends, int o, int e, int j) {
-    if (j == 0 || mode == LOCAL || (ends & TB)) return 0;
-    return -(o + (j - 1) * e);
-}
-
-template <int T>
-__device__ __forceinline__ uint32_t pick_row(const uint32_t (&H)[T], int r) {
-    uint32_t v = H[0];
-#pragma unroll
-    for (int k = 1; k < T; k++) v = (k == r) ? H[k] : v;
-    return v;
-}
 
 template <int T>
 __device__ __forceinline__ void load_profile(const uint32_t *lds, uint32_t off, uint32_t (&sc)[T]) {
@@ -94,57 +46,63 @@ __device__ __forceinline__ void load_profile(const uint32_t *lds, uint32_t off, 
     }
 }
 
-// One column of a strip, local mode, packed int16 (E, F clamped at 0).
-// Returns the column maximum.
-template <int T>
-__device__ __forceinline__ uint32_t column16_local(const uint32_t (&sc)[T], uint32_t (&H)[T],
-                                                   uint32_t (&E)[T], uint32_t Hd, uint32_t &F,
-                                                   uint32_t o2, uint32_t e2) {
-    uint32_t cm = 0;
-#pragma unroll
-    for (int r = 0; r < T; r++) {
-        const uint32_t t = adds(Hd, sc[r]);
-        Hd = H[r];
-        const uint32_t h = maxs(maxs(t, E[r]), F);
-        cm = maxs(cm, h);
-        const uint32_t ho = subu(h, o2);
-        E[r] = maxu(subu(E[r], e2), ho);
-        F = maxu(subu(F, e2), ho);
-        H[r] = h;
-    }
-    return cm;
-}
-
-// One column, global / semi-global, packed int16 with signed saturation.
-template <int T>
-__device__ __forceinline__ void column16_global(const uint32_t (&sc)[T], uint32_t (&H)[T],
-                                                uint32_t (&E)[T], uint32_t Hd, uint32_t &F,
-                                                uint32_t o2, uint32_t e2) {
-#pragma unroll
-    for (int r = 0; r < T; r++) {
-        const uint32_t t = adds(Hd, sc[r]);
-        Hd = H[r];
-        const uint32_t h = maxs(maxs(t, E[r]), F);
-        const uint32_t ho = subs(h, o2);
-        E[r] = maxs(subs(E[r], e2), ho);
-        F = maxs(subs(F, e2), ho);
-        H[r] = h;
-    }
-}
-
 size_t search16_lds_bytes(int T, int AP) { return (size_t)AP * AP * (T + 4) * 4; }
 size_t search32_lds_bytes(int AP) { return (size_t)AP * (kT32 + 4) * 4 + (size_t)AP * AP * 2 + 16; }
 
+// Pair profile of every strip of every query, built once per call in the
+// same padded layout the search kernel keeps in LDS, so each strip is a
+// straight 16-byte copy: prof[Q.prof + s*AP*AP*SP + p*SP + r].
+template <int T>
+__global__ void k_profile16(ProfileArgs a) {
+    constexpr int SP = T + 4;
+    const int AP = a.AP, A = a.A;
+    const int64_t per_strip = (int64_t)AP * AP * SP;
+    const int64_t total = a.total_dwords;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        // locate the query: strip_base is ascending
+        int lo = 0, hi = a.n_q - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.qinfo[mid].prof <= k) lo = mid; else hi = mid - 1;
+        }
+        const QueryInfo Q = a.qinfo[lo];
+        const int64_t rel = k - Q.prof;
+        const int s = (int)(rel / per_strip);
+        const int w = (int)(rel - (int64_t)s * per_strip);
+        const int p = w / SP, r = w - p * SP;
+        const int i = s * T + r;
+        int slo = NEG16, shi = NEG16;
+        if (r < T && i < Q.len) {
+            const int c = min((int)a.q_codes[Q.off + i], A - 1);  // codes >= A are caller errors
+            const int clo = a.inv_map[a.pair_dec[2 * p]], chi = a.inv_map[a.pair_dec[2 * p + 1]];
+            if (clo != 0xff) slo = a.subst[c * A + clo];
+            if (chi != 0xff) shi = a.subst[c * A + chi];
+        }
+        a.prof[k] = pack2(slo, shi);
+    }
+}
+
+hipError_t launch_profile16(const ProfileArgs &a, int T, hipStream_t s) {
+    if (a.total_dwords <= 0) return hipSuccess;
+    const int bs = 256;
+    const int64_t nb = std::min<int64_t>((a.total_dwords + bs - 1) / bs, 65536);
+    if (T == 16) hipLaunchKernelGGL(k_profile16<16>, dim3((unsigned)nb), dim3(bs), 0, s, a);
+    else hipLaunchKernelGGL(k_profile16<32>, dim3((unsigned)nb), dim3(bs), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int T, int MODE, bool PERSIST>
-__global__ void __launch_bounds__(512) k_search16(SearchArgs P) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(T <= 16 ? 4 : 2)))
+k_search16(SearchArgs P) {
     extern __shared__ uint4 lds4[];
     uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
     constexpr int SP = T + 4;  // dwords per profile row, a 16-byte multiple
     __shared__ int s_unit;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int o = P.o, e = P.e, ends = P.ends, A = P.A, AP = P.AP;
+    const int o = P.o, e = P.e, ends = P.ends, AP = P.AP;
     const uint32_t o2 = dup(o), e2 = dup(e);
-    const int nprof = AP * AP * T;
+    const int strip4 = AP * AP * SP / 4;  // uint4 per strip profile
 
     for (int iter = 0;; iter++) {
         int u;
@@ -168,7 +126,6 @@ __global__ void __launch_bounds__(512) k_search16(SearchArgs P) {
         GroupInfo G = {0, 0, 0, 0};
         if (active) G = P.grp[U.g0 + wave];
         const int m = Q.len, S = Q.strips;
-        const uint8_t *qc = P.q_codes + Q.off;
         int n_lo = 0, n_hi = 0;
         if (active) {
             n_lo = P.slot_len[G.slot0 + lane];
@@ -176,7 +133,8 @@ __global__ void __launch_bounds__(512) k_search16(SearchArgs P) {
         }
         const uint32_t nn = pack2(n_lo, n_hi);
         const uint2 *pk = P.packed + G.off + lane;
-        uint4 *bnd = P.bnd + (int64_t)U.qslot * P.bnd_slot_stride + G.bnd + 2 * lane;
+        uint2 *bnd = P.bnd + (int64_t)U.qslot * P.bnd_slot_stride + G.bnd + lane;
+        const uint4 *qprof = reinterpret_cast<const uint4 *>(P.prof + Q.prof);
 
         // best so far over finished strips (local), or the result (global / semi)
         uint32_t Gs = 0, Gj = 0, Gi = 0;
@@ -184,17 +142,9 @@ __global__ void __launch_bounds__(512) k_search16(SearchArgs P) {
         for (int s = 0; s < S; s++) {
             const int i0 = s * T;
             __syncthreads();
-            for (int idx = tid; idx < nprof; idx += blockDim.x) {
-                const int p = idx / T, r = idx - p * T;
-                const int i = i0 + r;
-                int slo = NEG16, shi = NEG16;
-                if (i < m) {
-                    const int a = min((int)qc[i], A - 1);  // codes >= A are caller errors
-                    const int clo = P.inv_map[p / AP], chi = P.inv_map[p % AP];
-                    if (clo != 0xff) slo = P.subst[a * A + clo];
-                    if (chi != 0xff) shi = P.subst[a * A + chi];
-                }
-                lds[p * SP + r] = pack2(slo, shi);
+            {
+                const uint4 *src = qprof + (int64_t)s * strip4;
+                for (int k = tid; k < strip4; k += blockDim.x) lds4[k] = src[k];
             }
             __syncthreads();
             if (!active) continue;
@@ -222,15 +172,30 @@ __global__ void __launch_bounds__(512) k_search16(SearchArgs P) {
             }
 
             const int nblk = G.ncols >> 2;
-            for (int c4 = 0; c4 < nblk; c4++) {
-                const uint2 cd = pk[(int64_t)c4 * 64];
-                uint32_t hf[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            // software pipeline: the next block's codes and boundary words are
+            // in flight while the current block computes
+            uint2 cd_n = make_uint2(0, 0), hf_n[4];
+#pragma unroll
+            for (int c = 0; c < 4; c++) hf_n[c] = make_uint2(0, 0);
+            if (nblk > 0) {
+                cd_n = pk[0];
                 if (!first) {
-                    const uint4 b0 = bnd[(int64_t)c4 * 128], b1 = bnd[(int64_t)c4 * 128 + 1];
-                    hf[0] = b0.x; hf[1] = b0.y; hf[2] = b0.z; hf[3] = b0.w;
-                    hf[4] = b1.x; hf[5] = b1.y; hf[6] = b1.z; hf[7] = b1.w;
+#pragma unroll
+                    for (int c = 0; c < 4; c++) hf_n[c] = bnd[(int64_t)c * 64];
                 }
-                uint32_t ob[8];
+            }
+            for (int c4 = 0; c4 < nblk; c4++) {
+                const uint2 cd = cd_n;
+                uint2 hf[4];
+#pragma unroll
+                for (int c = 0; c < 4; c++) hf[c] = hf_n[c];
+                if (c4 + 1 < nblk) {
+                    cd_n = pk[(int64_t)(c4 + 1) * 64];
+                    if (!first) {
+#pragma unroll
+                        for (int c = 0; c < 4; c++) hf_n[c] = bnd[(int64_t)(4 * c4 + 4 + c) * 64];
+                    }
+                }
 #pragma unroll
                 for (int c = 0; c < 4; c++) {
                     const int j = c4 * 4 + c + 1;
@@ -241,8 +206,8 @@ __global__ void __launch_bounds__(512) k_search16(SearchArgs P) {
                         Hup = dup(tv);
                         F = (MODE == LOCAL) ? 0u : subs(Hup, o2);
                     } else {
-                        Hup = hf[2 * c];
-                        F = hf[2 * c + 1];
+                        Hup = hf[c].x;
+                        F = hf[c].y;
                     }
                     const uint32_t Hd = Hd_top;
                     Hd_top = Hup;
@@ -255,12 +220,7 @@ __global__ void __launch_bounds__(512) k_search16(SearchArgs P) {
                             // some half improved: find the first row reaching
                             // the column maximum
                             const uint32_t mask = nzmask(nb ^ B);
-                            uint32_t idx = 0xffffffffu;
-#pragma unroll
-                            for (int r = 0; r < T; r++) {
-                                const uint32_t z = minu(H[r] ^ cm, 0x00010001u);
-                                idx = minu(idx, addu(mulu(z, 0x80008000u), dup(r)));
-                            }
+                            const uint32_t idx = first_row_of<T>(H, cm);
                             Bi = bfi(mask, addu(idx, dup(i0 + 1)), Bi);
                             Bj = bfi(mask, dup(j), Bj);
                             B = nb;
@@ -280,31 +240,24 @@ __global__ void __launch_bounds__(512) k_search16(SearchArgs P) {
                             }
                         }
                     }
-                    ob[2 * c] = H[T - 1];
-                    ob[2 * c + 1] = F;
-                }
-                if (!last) {
-                    bnd[(int64_t)c4 * 128] = make_uint4(ob[0], ob[1], ob[2], ob[3]);
-                    bnd[(int64_t)c4 * 128 + 1] = make_uint4(ob[4], ob[5], ob[6], ob[7]);
+                    if (!last) bnd[(int64_t)(j - 1) * 64] = make_uint2(H[T - 1], F);
                 }
             }
 
             if (MODE == LOCAL) {
-                int g[2] = {lo16(Gs), hi16(Gs)};
-                int gj[2] = {(int)(Gj & 0xffff), (int)(Gj >> 16)};
-                int gi[2] = {(int)(Gi & 0xffff), (int)(Gi >> 16)};
                 const int b[2] = {lo16(B), hi16(B)};
                 const int bj[2] = {(int)(Bj & 0xffff), (int)(Bj >> 16)};
                 const int bi[2] = {(int)(Bi & 0xffff), (int)(Bi >> 16)};
+                uint64_t gk[2] = {end_key(lo16(Gs), (int)(Gj & 0xffff), (int)(Gi & 0xffff)),
+                                  end_key(hi16(Gs), (int)(Gj >> 16), (int)(Gi >> 16))};
 #pragma unroll
                 for (int h = 0; h < 2; h++) {
-                    if (b[h] > 0 && (b[h] > g[h] || (b[h] == g[h] && bj[h] < gj[h]))) {
-                        g[h] = b[h]; gj[h] = bj[h]; gi[h] = bi[h];
-                    }
+                    const uint64_t kk = end_key(b[h], bj[h], bi[h]);
+                    gk[h] = (b[h] > 0) ? umax64(gk[h], kk) : gk[h];
                 }
-                Gs = pack2(g[0], g[1]);
-                Gj = pack2(gj[0], gj[1]);
-                Gi = pack2(gi[0], gi[1]);
+                Gs = pack2(key_score(gk[0]), key_score(gk[1]));
+                Gj = pack2(key_j(gk[0]), key_j(gk[1]));
+                Gi = pack2(key_i(gk[0]), key_i(gk[1]));
             } else if (last) {
                 if (ends & TE) { Gs = Ls; Gj = Lj; }
                 else { Gs = res; Gj = nn; }
@@ -387,8 +340,8 @@ __global__ void __launch_bounds__(1024) k_search32(SearchArgs P, int rerun_only)
         const int slot = G.slot0 + half * 64 + lane;
         const int nt = active ? P.slot_len[slot] : 0;
         const uint2 *pk = P.packed + G.off + lane;
-        uint4 *bnd = P.bnd + (int64_t)U.qslot * P.bnd_slot_stride + G.bnd +
-                     (int64_t)half * (G.ncols >> 2) * 128 + 2 * lane;
+        uint2 *bnd = P.bnd + (int64_t)U.qslot * P.bnd_slot_stride + G.bnd +
+                     (int64_t)half * G.ncols * 64 + lane;
 
         int Gs = (MODE == LOCAL) ? 0 : PAD32, Gj = 0, Gi = 0;
         for (int s = 0; s < S; s++) {
@@ -423,11 +376,13 @@ __global__ void __launch_bounds__(1024) k_search32(SearchArgs P, int rerun_only)
                 const uint2 cd = pk[(int64_t)c4 * 64];
                 int hf[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                 if (!first) {
-                    const uint4 b0 = bnd[(int64_t)c4 * 128], b1 = bnd[(int64_t)c4 * 128 + 1];
-                    hf[0] = b0.x; hf[1] = b0.y; hf[2] = b0.z; hf[3] = b0.w;
-                    hf[4] = b1.x; hf[5] = b1.y; hf[6] = b1.z; hf[7] = b1.w;
+#pragma unroll
+                    for (int c = 0; c < 4; c++) {
+                        const uint2 b = bnd[(int64_t)(4 * c4 + c) * 64];
+                        hf[2 * c] = (int)b.x;
+                        hf[2 * c + 1] = (int)b.y;
+                    }
                 }
-                int ob[8];
 #pragma unroll
                 for (int c = 0; c < 4; c++) {
                     const int j = c4 * 4 + c + 1;
@@ -473,16 +428,12 @@ __global__ void __launch_bounds__(1024) k_search32(SearchArgs P, int rerun_only)
                             Ls = vl; Lj = j;
                         }
                     }
-                    ob[2 * c] = H[T - 1];
-                    ob[2 * c + 1] = F;
-                }
-                if (!last) {
-                    bnd[(int64_t)c4 * 128] = make_uint4(ob[0], ob[1], ob[2], ob[3]);
-                    bnd[(int64_t)c4 * 128 + 1] = make_uint4(ob[4], ob[5], ob[6], ob[7]);
+                    if (!last) bnd[(int64_t)(j - 1) * 64] = make_uint2((uint32_t)H[T - 1], (uint32_t)F);
                 }
             }
             if (MODE == LOCAL) {
-                if (B > 0 && (B > Gs || (B == Gs && Bj < Gj))) { Gs = B; Gj = Bj; Gi = Bi; }
+                const uint64_t gk = umax64(end_key(Gs, Gj, Gi), end_key(B, Bj, Bi));
+                if (B > 0) { Gs = key_score(gk); Gj = key_j(gk); Gi = key_i(gk); }
             } else if (last) {
                 if (ends & TE) { Gs = Ls; Gj = Lj; }
                 else { Gs = res; Gj = nt; }

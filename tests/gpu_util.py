@@ -33,6 +33,11 @@ def compare_search(got, exp, nq, nt, fields=("score", "q_end", "t_end"), label="
         bad = np.argwhere(g != x)
         if len(bad):
             q, t = bad[0]
+            for qq, tt in bad[:6]:
+                print(f"  mismatch q={qq} t={tt}: gpu " +
+                      str([int(got[k].reshape(nq, nt)[qq, tt]) for k in ("score", "q_end", "t_end")]) +
+                      " oracle " + str([int(np.asarray(exp[k]).reshape(nq, nt)[qq, tt])
+                                        for k in ("score", "q_end", "t_end")]), flush=True)
             raise AssertionError(
                 f"{label} field {f}: {len(bad)} mismatches; first at query {q} target {t}: "
                 f"gpu {g[q, t]} oracle {x[q, t]} (score gpu {got['score'].reshape(nq, nt)[q, t]} "

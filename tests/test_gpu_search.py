@@ -39,7 +39,8 @@ CASES = [
 
 @pytest.mark.parametrize("mode,ends", CASES)
 @pytest.mark.parametrize("plain", [False, True], ids=["persistent", "plain"])
-def test_search_modes(mode, ends, plain, blosum):
+def test_search_modes(mode, ends, plain, blosum, monkeypatch):
+    monkeypatch.setenv("DSA_INTRA_BUDGET", "1000000000")  # inter-sequence kernel only
     T = _targets(1, 300, 180, extra=[1, 2, 3, 4, 5, 399, 400])
     Q = _queries(2, QLENS)
     log(f"search mode={mode} ends={ends} plain={plain} nq={len(Q)} nt={len(T)}")
@@ -123,3 +124,37 @@ def test_cfg2_full_size_sampled():
         g = got[f].reshape(5, nt)[qi, ti]
         assert (g == exp[f]).all(), f
     assert (got["score"] >= 0).all() and (got["score"] < 32767).all()
+
+
+INTRA_QLENS = [1, 15, 16, 17, 100, 700, 1023, 1024, 1025, 2100]
+
+
+@pytest.mark.parametrize("mode,ends", CASES)
+@pytest.mark.parametrize("budget", ["1", None], ids=["all-long-groups-wavefront", "default-routing"])
+def test_search_wavefront_long_targets(mode, ends, budget, blosum, monkeypatch):
+    """Long targets of long queries go through the wavefront kernel (lanes =
+    16-row strips, up to three 1024-row passes); the routing budget 1 sends
+    every group wider than 128 columns there."""
+    if budget is not None:
+        monkeypatch.setenv("DSA_INTRA_BUDGET", budget)
+    T = _targets(5, 260, 1500, extra=[1, 2, 1501, 1777, 2001])
+    Q = _queries(6, INTRA_QLENS)
+    log(f"wavefront mode={mode} ends={ends} budget={budget}")
+    for plain in (False, True):
+        got, _ = gpu_search(Q, T, blosum, 11, 1, mode, ends, plain=plain)
+        exp = oracle.search(Q, T, blosum, 11, 1, mode=mode, ends=ends)
+        compare_search(got, exp, len(Q), len(T), label=f"wavefront {mode}/{ends}/{plain}")
+
+
+def test_search_wavefront_overflow_rerun(blosum, monkeypatch):
+    monkeypatch.setenv("DSA_INTRA_BUDGET", "1")
+    S = (blosum.astype(np.int32) * 5).clip(-128, 127).astype(np.int8)
+    rng = np.random.default_rng([170101575, 55])
+    base = gen.background_residues(rng, 1600)
+    seqs = [base[:k] for k in (600, 1600)] + [gen.background_residues(rng, 900) for _ in range(130)]
+    T = SeqSet.from_list(seqs)
+    Q = SeqSet.from_list([base, base[:300]])
+    got, _ = gpu_search(Q, T, S, 40, 4, "local")
+    exp = oracle.search(Q, T, S, 40, 4, mode="local")
+    compare_search(got, exp, len(Q), len(T), label="wavefront ovf")
+    assert exp["score"].max() > 32767
