@@ -119,7 +119,7 @@ def main():
             B.dsa_align_batch(a, o)
         torch.cuda.synchronize()
         if timing:
-            B.dsa_timing_read()
+            B.dsa_timing_reset()
             B.dsa_timing_enable(True)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -127,31 +127,41 @@ def main():
             B.dsa_align_batch(a, o)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
-        kms, nl = (0.0, 0)
+        tm = {}
         if timing:
-            kms, nl = B.dsa_timing_read()
+            for name, kind in (("span", B.TIMING_SPAN), ("inter", B.TIMING_INTER), ("intra", B.TIMING_INTRA)):
+                tm[name] = B.dsa_timing_read(kind)
             B.dsa_timing_enable(False)
-        return dt, kms, nl, outs
+            B.dsa_timing_reset()
+        return dt, tm, outs
 
     log(f"batched: {args.warmup} warmup + {args.steps} timed steps")
-    dt, kms, nl, outs = run(False, args.warmup, args.steps, timing=True)
+    dt, tm, outs = run(False, args.warmup, args.steps, timing=True)
     ms_step = dt / args.steps * 1e3
     gcups = cells / (dt / args.steps) / 1e9
-    log(f"batched: {ms_step:.2f} ms/step, {gcups:.1f} GCUPS; kernel {kms / max(nl, 1):.2f} ms x {nl}")
+    span_ms = tm["span"][0] / max(tm["span"][1], 1)
+    log(f"batched: {ms_step:.2f} ms/step, {gcups:.1f} GCUPS; search span {span_ms:.2f} ms, "
+        f"inter {tm['inter'][0] / max(tm['inter'][1], 1):.2f} ms x {tm['inter'][1]}, "
+        f"wavefront {tm['intra'][0] / max(tm['intra'][1], 1):.2f} ms x {tm['intra'][1]}")
 
     log(f"plain: 1 warmup + {args.plain_steps} timed steps")
-    pdt, _, _, _ = run(True, 1, args.plain_steps)
+    pdt, _, _ = run(True, 1, args.plain_steps)
     plain_ms = pdt / args.plain_steps * 1e3
     plain_gcups = cells / (pdt / args.plain_steps) / 1e9
     log(f"plain: {plain_ms:.2f} ms/step, {plain_gcups:.1f} GCUPS")
 
-    kernel_ms = kms / max(nl, 1)
-    achieved = cells * OPS_PER_CELL / (kernel_ms * 1e-3) / 1e12
+    achieved = cells * OPS_PER_CELL / (span_ms * 1e-3) / 1e12
     traffic = load_traffic(cells)
+    per_kernel = {}
+    for name, label in (("inter", "k_search16<32,local,persistent>"), ("intra", "k_intra16<local>")):
+        tot, n = tm[name]
+        per_kernel[label] = {"avg_ms": round(tot / max(n, 1), 3), "launches_per_step": n // args.steps}
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_INT16_TOPS,
                 "unit": "TOP/s (packed int16 VALU ops)", "frac": round(achieved / PEAK_INT16_TOPS, 4),
-                "traffic": traffic, "kernel": "k_search16<T=32,local,persistent>",
-                "kernel_ms": round(kernel_ms, 3), "ops_per_cell": OPS_PER_CELL,
+                "traffic": traffic,
+                "kernel": "search phase: k_search16 (inter-sequence) with k_intra16 (wavefront) "
+                          "concurrently on a second stream",
+                "span_ms": round(span_ms, 3), "kernels": per_kernel, "ops_per_cell": OPS_PER_CELL,
                 "cells_per_launch": cells}
 
     score = outs["score"].cpu().numpy().reshape(nq, nt)

@@ -175,14 +175,18 @@ int dsa_cigar_capacity(const dsa_args *args, int64_t *entries);
 int dsa_align_batch(const dsa_args *args, const dsa_out *out);
 
 /*
- * Measurement hooks.  dsa_timing_enable(1) makes dsa_align_batch record a
- * pair of HIP events on args->stream around every launch of its main
- * alignment kernel; dsa_timing_read waits for them, returns the summed
- * kernel time in milliseconds and the launch count, and clears the record.
- * Used by the benchmark to time the dominant kernel; off by default.
+ * Measurement hooks.  dsa_timing_enable(1) makes dsa_align_batch record HIP
+ * event pairs on the stream each kernel is launched on: kind 0 = the whole
+ * search phase on args->stream (both search kernels, from the fork to the
+ * join), 1 = each launch of the inter-sequence kernel, 2 = each launch of
+ * the wavefront kernel (on the library's auxiliary stream).
+ * dsa_timing_read(kind, ...) waits for that kind's events and returns the
+ * summed milliseconds and the launch count; dsa_timing_reset clears the
+ * record.  Used by the benchmark to time the dominant kernels; off by default.
  */
 int dsa_timing_enable(int on);
-int dsa_timing_read(double *total_ms, int64_t *launches);
+int dsa_timing_read(int kind, double *total_ms, int64_t *launches);
+int dsa_timing_reset(void);
 
 /*
  * dsa_probe - measured ceilings on the current device (blocking; allocates

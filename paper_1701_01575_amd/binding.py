@@ -19,6 +19,7 @@ DSA_ST_INT32, DSA_ST_TRUNCATED = 1, 2
 
 EXPORTS = ["dsa_db_create", "dsa_db_destroy", "dsa_db_info", "dsa_workspace_size",
            "dsa_cigar_capacity", "dsa_align_batch", "dsa_timing_enable", "dsa_timing_read",
+           "dsa_timing_reset",
            "dsa_probe",
            "dsa_strerror", "dsa_last_error", "dsa_abi_version"]
 
@@ -85,7 +86,9 @@ def lib():
         L.dsa_cigar_capacity.argtypes = [ctypes.POINTER(dsa_args), ctypes.POINTER(ctypes.c_int64)]
         L.dsa_align_batch.argtypes = [ctypes.POINTER(dsa_args), ctypes.POINTER(dsa_out)]
         L.dsa_timing_enable.argtypes = [ctypes.c_int]
-        L.dsa_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        L.dsa_timing_read.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int64)]
+        L.dsa_timing_reset.argtypes = []
         L.dsa_probe.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
         L.dsa_strerror.argtypes = [ctypes.c_int]
         L.dsa_strerror.restype = ctypes.c_char_p
@@ -146,11 +149,18 @@ def dsa_timing_enable(on: bool):
     check(lib().dsa_timing_enable(1 if on else 0), "dsa_timing_enable")
 
 
-def dsa_timing_read():
-    """(summed kernel milliseconds, launch count) since the last read."""
+TIMING_SPAN, TIMING_INTER, TIMING_INTRA = 0, 1, 2
+
+
+def dsa_timing_read(kind: int = TIMING_SPAN):
+    """(summed milliseconds, launch count) of one timing kind."""
     ms, n = ctypes.c_double(), ctypes.c_int64()
-    check(lib().dsa_timing_read(ctypes.byref(ms), ctypes.byref(n)), "dsa_timing_read")
+    check(lib().dsa_timing_read(kind, ctypes.byref(ms), ctypes.byref(n)), "dsa_timing_read")
     return ms.value, n.value
+
+
+def dsa_timing_reset():
+    check(lib().dsa_timing_reset(), "dsa_timing_reset")
 
 
 def dsa_probe(which: int, size: int) -> float:

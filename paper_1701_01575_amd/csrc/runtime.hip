@@ -42,16 +42,19 @@ struct Staging {
 };
 Staging g_staging[64];
 
-// Optional kernel timing (dsa_timing_enable / dsa_timing_read).
+// Optional kernel timing (dsa_timing_enable / dsa_timing_read): event pairs
+// recorded on the stream a kernel is launched on, grouped by kind.
+enum TimingKind { TK_SPAN = 0, TK_INTER = 1, TK_INTRA = 2, TK_KINDS = 3 };
 struct Timing {
     std::mutex mu;
     bool on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+    std::vector<int> kind;
     size_t used = 0;
 };
 Timing g_timing;
 
-int timing_begin(hipStream_t st, size_t *slot) {
+int timing_begin(hipStream_t st, int kind, size_t *slot) {
     *slot = SIZE_MAX;
     std::lock_guard<std::mutex> lk(g_timing.mu);
     if (!g_timing.on) return DSA_OK;
@@ -60,8 +63,10 @@ int timing_begin(hipStream_t st, size_t *slot) {
         HIPCHK(hipEventCreate(&a));
         HIPCHK(hipEventCreate(&b));
         g_timing.pool.push_back({a, b});
+        g_timing.kind.push_back(0);
     }
     *slot = g_timing.used++;
+    g_timing.kind[*slot] = kind;
     HIPCHK(hipEventRecord(g_timing.pool[*slot].first, st));
     return DSA_OK;
 }
@@ -70,6 +75,28 @@ int timing_end(hipStream_t st, size_t slot) {
     if (slot == SIZE_MAX) return DSA_OK;
     std::lock_guard<std::mutex> lk(g_timing.mu);
     HIPCHK(hipEventRecord(g_timing.pool[slot].second, st));
+    return DSA_OK;
+}
+
+// Auxiliary stream per device for the wavefront kernel, which runs
+// concurrently with the inter-sequence kernel (fork / join with events on
+// the caller's stream; default priority).
+struct Aux {
+    std::mutex mu;
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+Aux g_aux[64];
+
+int aux_get(int dev, Aux **out) {
+    Aux &A = g_aux[dev & 63];
+    std::lock_guard<std::mutex> lk(A.mu);
+    if (!A.s) {
+        HIPCHK(hipStreamCreateWithFlags(&A.s, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&A.fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&A.join, hipEventDisableTiming));
+    }
+    *out = &A;
     return DSA_OK;
 }
 
@@ -307,7 +334,7 @@ struct Plan {
     int64_t n_inter = 0;            // persistent form: units[0 .. n_inter) go to the int16 kernel
     std::vector<IntraUnit> iunits;
     std::vector<int64_t> iunit_first, iunit_count;
-    int64_t budget = 48000;         // strips x columns above which a group goes to the wavefront kernel
+    int64_t budget = 64000;         // strips x columns above which a group goes to the wavefront kernel
     size_t ldsI = 0;
     std::vector<QueryInfo> qinfo;
     std::vector<int32_t> empty_rows;
@@ -378,6 +405,9 @@ int make_search_plan(const dsa_args *a, Plan &P) {
         const int w = atoi(v);
         if (w >= 1 && w <= 8) P.wpb16 = w;
     }
+    // the plain form runs one query at a time, so the wavefront kernel has to
+    // take more of each query's work to keep the GPU busy
+    P.budget = P.persistent ? 64000 : 16000;
     if (const char *v = getenv("DSA_INTRA_BUDGET")) P.budget = atoll(v);
     P.lds16 = search16_lds_bytes(P.T, db->AP);
     P.lds32 = search32_lds_bytes(db->AP);
@@ -679,7 +709,7 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
                 nb = (int)std::min<int64_t>(n, (int64_t)cus * per_cu16);
             }
             size_t slot;
-            int trc = timing_begin(st, &slot);
+            int trc = timing_begin(st, TK_INTER, &slot);
             if (trc) return trc;
             HIPCHK(launch_search16(k, P.T, P.mode, P.wpb16, nb, P.persistent, P.lds16, st));
             if ((trc = timing_end(st, slot))) return trc;
@@ -720,21 +750,46 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
     I.slot_len = db->d_slot_len;
     I.qflag = K.qflag;
     const IntraUnit *d_iunits = (const IntraUnit *)(ws + P.off_iunits);
+    // the wavefront kernel runs on the auxiliary stream, forked from and
+    // joined back into the caller's stream around each search pass
+    Aux *aux = nullptr;
+    {
+        const int arc = aux_get(dev, &aux);
+        if (arc) return arc;
+    }
     auto intra = [&](const IntraUnit *units, int64_t n, int32_t *flags_base) -> int {
         if (n <= 0 || P.force32) return DSA_OK;
         IntraArgs x = I;
         x.units = units;
         x.n_units = (int32_t)n;
         x.unit_flags = flags_base;
-        HIPCHK(launch_intra16(x, P.mode, (int)n, P.ldsI, st));
+        HIPCHK(hipEventRecord(aux->fork, st));
+        HIPCHK(hipStreamWaitEvent(aux->s, aux->fork, 0));
+        size_t slot;
+        int trc = timing_begin(aux->s, TK_INTRA, &slot);
+        if (trc) return trc;
+        HIPCHK(launch_intra16(x, P.mode, (int)n, P.ldsI, aux->s));
+        if ((trc = timing_end(aux->s, slot))) return trc;
         return DSA_OK;
     };
+    auto join = [&](int64_t n) -> int {
+        if (n <= 0 || P.force32) return DSA_OK;
+        HIPCHK(hipEventRecord(aux->join, aux->s));
+        HIPCHK(hipStreamWaitEvent(st, aux->join, 0));
+        return DSA_OK;
+    };
+    size_t span_slot;
+    {
+        const int trc = timing_begin(st, TK_SPAN, &span_slot);
+        if (trc) return trc;
+    }
 
     int rc;
     if (P.persistent) {
         if (!P.force32) {
             if ((rc = intra(d_iunits, (int64_t)P.iunits.size(), K.unit_flags))) return rc;
             if ((rc = pass(d_units, P.n_inter, 0))) return rc;
+            if ((rc = join((int64_t)P.iunits.size()))) return rc;
             if ((rc = pass(d_units, nunits, 1))) return rc;
         } else if ((rc = pass(d_units, nunits, 0))) {
             return rc;
@@ -746,11 +801,16 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
             if (!P.force32) {
                 if ((rc = intra(d_iunits + P.iunit_first[q], P.iunit_count[q], K.unit_flags))) return rc;
                 if ((rc = pass(u, P.unit_inter[q], 0))) return rc;
+                if ((rc = join(P.iunit_count[q]))) return rc;
                 if ((rc = pass(u, P.unit_count[q], 1))) return rc;
             } else if ((rc = pass(u, P.unit_count[q], 0))) {
                 return rc;
             }
         }
+    }
+    {
+        const int trc = timing_end(st, span_slot);
+        if (trc) return trc;
     }
     if (!P.empty_rows.empty()) {
         EmptyArgs E;
@@ -795,17 +855,27 @@ extern "C" int dsa_timing_enable(int on) {
     return DSA_OK;
 }
 
-extern "C" int dsa_timing_read(double *total_ms, int64_t *launches) {
+extern "C" int dsa_timing_read(int kind, double *total_ms, int64_t *launches) {
+    if (kind < 0 || kind >= TK_KINDS) return fail(DSA_E_INVAL, "unknown timing kind");
     std::lock_guard<std::mutex> lk(g_timing.mu);
     double tot = 0.0;
+    int64_t n = 0;
     for (size_t k = 0; k < g_timing.used; k++) {
+        if (g_timing.kind[k] != kind) continue;
         HIPCHK(hipEventSynchronize(g_timing.pool[k].second));
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, g_timing.pool[k].first, g_timing.pool[k].second));
         tot += ms;
+        n++;
     }
     if (total_ms) *total_ms = tot;
-    if (launches) *launches = (int64_t)g_timing.used;
+    if (launches) *launches = n;
+    return DSA_OK;
+}
+
+extern "C" int dsa_timing_reset(void) {
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    for (size_t k = 0; k < g_timing.used; k++) HIPCHK(hipEventSynchronize(g_timing.pool[k].second));
     g_timing.used = 0;
     return DSA_OK;
 }
