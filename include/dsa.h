@@ -160,7 +160,12 @@ int dsa_workspace_size(const dsa_args *args, size_t *bytes);
 
 /*
  * dsa_cigar_capacity - uint32 entries dsa_out.cigar_ops needs so that no
- * CIGAR can be truncated (sum over results of query + target length).
+ * CIGAR can be truncated (sum over results of query + target length + 1).
+ * Each result owns a region of that size in result order; its runs are
+ * written at the end of the region and cigar_off / cigar_len locate them.
+ * With less capacity the results that do not fit get an empty region, the
+ * DSA_ST_TRUNCATED status bit and dsa_align_batch returns DSA_E_CAPACITY
+ * (scores and coordinates stay valid).
  */
 int dsa_cigar_capacity(const dsa_args *args, int64_t *entries);
 

@@ -135,7 +135,7 @@ def make_args(q_codes, q_offsets, matrix, gap_open, gap_extend, mode="local", db
     return a
 
 
-def align_args(a, device, n_results, want_coords=True, want_begin=True):
+def align_args(a, device, n_results, want_coords=True, want_begin=True, cigar_capacity=None):
     """Allocate outputs + workspace and call dsa_align_batch; returns tensors."""
     torch = _torch()
     need = B.dsa_workspace_size(a)
@@ -144,26 +144,42 @@ def align_args(a, device, n_results, want_coords=True, want_begin=True):
     a.workspace_bytes = ws_bytes
     out = B.dsa_out()
     i32 = dict(dtype=torch.int32, device=device)
-    res = {"score": torch.empty(max(n_results, 1), **i32)}
+    nr = max(n_results, 1)
+    res = {"score": torch.empty(nr, **i32)}
     if want_coords:
-        res["q_end"] = torch.empty(max(n_results, 1), **i32)
-        res["t_end"] = torch.empty(max(n_results, 1), **i32)
+        res["q_end"] = torch.empty(nr, **i32)
+        res["t_end"] = torch.empty(nr, **i32)
     if want_begin:
-        res["q_begin"] = torch.empty(max(n_results, 1), **i32)
-        res["t_begin"] = torch.empty(max(n_results, 1), **i32)
-    res["status"] = torch.empty(max(n_results, 1), dtype=torch.uint8, device=device)
-    for k in ("score", "q_begin", "q_end", "t_begin", "t_end", "status"):
+        res["q_begin"] = torch.empty(nr, **i32)
+        res["t_begin"] = torch.empty(nr, **i32)
+    res["status"] = torch.empty(nr, dtype=torch.uint8, device=device)
+    if a.flags & DSA_TRACEBACK:
+        cap = B.dsa_cigar_capacity(a) if cigar_capacity is None else int(cigar_capacity)
+        res["cigar_off"] = torch.empty(nr, dtype=torch.int64, device=device)
+        res["cigar_len"] = torch.empty(nr, **i32)
+        res["cigar_ops"] = torch.empty(max(cap, 1), dtype=torch.int32, device=device)
+        out.cigar_capacity = cap
+    for k in ("score", "q_begin", "q_end", "t_begin", "t_end", "status", "cigar_off", "cigar_len",
+              "cigar_ops", "t_index"):
         if k in res:
             setattr(out, k, res[k].data_ptr())
     st = B.dsa_align_batch(a, out)
-    res = {k: v[:n_results] for k, v in res.items()}
+    res = {k: (v[:n_results] if k != "cigar_ops" else v) for k, v in res.items()}
     res["capacity_ok"] = st == B.DSA_OK
     return res
 
 
+def cigars(res) -> list:
+    """Per-result CIGAR runs (uint32 numpy arrays, (len << 4) | op) on the host."""
+    ops = res["cigar_ops"].cpu().numpy().view(np.uint32)
+    off = res["cigar_off"].cpu().numpy()
+    ln = res["cigar_len"].cpu().numpy()
+    return [ops[int(o):int(o) + int(n)].copy() for o, n in zip(off, ln)]
+
+
 def align(queries, db: Database = None, targets=None, matrix=None, gap_open=11, gap_extend=1,
           mode="local", free_ends=None, traceback=False, top_k=0, plain=False,
-          force_int32=False, stream=None) -> dict:
+          force_int32=False, stream=None, cigar_capacity=None) -> dict:
     """Align a SeqSet of queries against a Database (every query vs every
     target, query-major results) or against a SeqSet of targets pairwise.
     Returns a dict of device tensors (score, q_begin, q_end, t_begin, t_end,
@@ -180,6 +196,6 @@ def align(queries, db: Database = None, targets=None, matrix=None, gap_open=11, 
     n = nq * (db.n_targets if db is not None else 1) if not top_k else nq * top_k
     if targets is not None:
         n = nq
-    res = align_args(a, device, n)
+    res = align_args(a, device, n, cigar_capacity=cigar_capacity)
     res["_keep"] = (qc, tc)
     return res

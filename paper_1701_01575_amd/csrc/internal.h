@@ -107,6 +107,53 @@ constexpr int kIntraWaves = 4;    // waves (pairs) per block
 hipError_t launch_intra16(const IntraArgs &a, int mode, int n_blocks, size_t lds, hipStream_t s);
 size_t intra16_lds_bytes(int AP, int A);
 
+// Pairwise alignment (query k against target k): one pair per lane, pairs
+// sorted by (strips, target length) into groups of 64 so a wave's lanes share
+// the strip count.
+constexpr int kTP = 16;           // rows per strip in the pairwise kernel
+constexpr int kPairWaves = 4;     // waves (groups) per block
+
+struct PairInfo {
+    int64_t q_off, t_off;         // into the query / target code buffers
+    int64_t cig_off;              // first uint32 of this pair's CIGAR region
+    int32_t m, n;
+    int32_t res;                  // output index (caller order)
+    int32_t cig_cap;              // CIGAR region capacity (uint32 runs)
+};
+
+struct PairGroup {
+    int64_t tb;       // first uint32 of the group's direction codes (chunk-relative)
+    int64_t bnd;      // first uint2 of the group's boundary words
+    int64_t tpk;      // first uint32 of the group's interleaved target codes
+    int32_t ncols;    // longest target, rounded up to 4
+    int32_t strips;   // shared strip count
+    int32_t p0;       // first pair slot
+    int32_t np;       // pairs (<= 64)
+};
+
+struct PairArgs {
+    const PairInfo *pairs;
+    const PairGroup *groups;
+    int32_t n_groups;
+    const uint8_t *q_codes, *t_codes;
+    const int8_t *subst;
+    int32_t A, o, e, ends;
+    int32_t traceback;
+    uint32_t *tb;                 // direction codes, 4 bits per cell
+    uint2 *bnd;
+    uint32_t *tpk;                // interleaved target codes (4 per uint32)
+    int32_t *out_score, *out_qend, *out_tend, *out_qbeg, *out_tbeg;
+    uint8_t *out_status;
+    int32_t *end_i, *end_j;       // per slot: 1-based end cell for the walk
+    int64_t *cig_off_out;
+    int32_t *cig_len_out;
+    uint32_t *cigar;
+};
+hipError_t launch_pack_targets(const PairArgs &a, int64_t n_words, hipStream_t s);
+hipError_t launch_pair32(const PairArgs &a, int mode, hipStream_t s);
+hipError_t launch_walk(const PairArgs &a, int mode, int64_t slot0, int64_t n_slots, hipStream_t s);
+size_t pair32_lds_bytes(int A);
+
 // Launchers (kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_search16(const SearchArgs &a, int T, int mode, int waves_per_block,
                            int n_blocks, bool persistent, size_t lds_bytes, hipStream_t s);

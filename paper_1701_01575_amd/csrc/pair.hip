@@ -1,0 +1,319 @@
+// Pairwise alignment with traceback: query k against target k.
+//
+// Fill (k_pair32): one pair per lane, exact int32, the same recurrence, modes,
+// boundaries and end-cell rule as the database kernels.  Pairs are sorted by
+// strip count and target length into groups of 64 so that a wave's lanes
+// share the strip count; the query is cut into 16-row strips held in VGPRs,
+// the boundary row between strips goes through HBM, and each lane reads its
+// substitution scores from an (A+1) x (A+1) copy of the matrix in LDS (the
+// extra row and column score padding as -2^30).
+//
+// Traceback: while filling, every cell gets a 4-bit direction code
+//   bits 0-1  where H came from, in the fixed priority
+//             0 = zero (local, stop), 1 = diagonal, 2 = E (gap in query, D),
+//             3 = F (gap in target, I)
+//   bit 2     E[i][j] extends E[i][j-1] (it is not H[i][j-1] - o; open wins ties)
+//   bit 3     F[i][j] extends F[i-1][j]
+// packed 8 cells per uint32 per lane.  Two bits of H source alone do not
+// determine an affine-gap path; the extend bits make the walk exact.  The
+// walk (k_walk, one thread per pair) starts at the end cell in state H and
+// follows the codes back, run-length encoding the CIGAR into the pair's
+// region from its end backwards, so the runs read forward in order.
+#include <algorithm>
+
+#include "internal.h"
+#include "pk16.h"
+
+namespace dsa {
+
+size_t pair32_lds_bytes(int A) { return (size_t)(A + 1) * (A + 1) * 4 + 16; }
+
+// Interleave target codes per group: word (c4, lane) holds columns
+// 4*c4 .. 4*c4+3 of the lane's target (code A past its end).
+__global__ void k_pack_targets(PairArgs P, int64_t n_words) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_words;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = P.n_groups - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (P.groups[mid].tpk <= k) lo = mid; else hi = mid - 1;
+        }
+        const PairGroup G = P.groups[lo];
+        const int64_t rel = k - G.tpk;
+        const int c4 = (int)(rel / kWave), lane = (int)(rel % kWave);
+        uint32_t w = 0;
+        const PairInfo I = P.pairs[(int64_t)lo * kWave + lane];
+        for (int c = 0; c < 4; c++) {
+            const int j = 4 * c4 + c;
+            uint32_t code = (uint32_t)P.A;
+            if (lane < G.np && j < I.n) code = min((uint32_t)P.t_codes[I.t_off + j], (uint32_t)(P.A - 1));
+            w |= code << (8 * c);
+        }
+        P.tpk[k] = w;
+    }
+}
+
+hipError_t launch_pack_targets(const PairArgs &a, int64_t n_words, hipStream_t s) {
+    if (n_words <= 0) return hipSuccess;
+    const int bs = 256;
+    const int64_t nb = std::min<int64_t>((n_words + bs - 1) / bs, 65536);
+    hipLaunchKernelGGL(k_pack_targets, dim3((unsigned)nb), dim3(bs), 0, s, a, n_words);
+    return hipGetLastError();
+}
+
+template <int MODE, bool TB>
+__global__ void __launch_bounds__(kPairWaves * kWave) k_pair32(PairArgs P) {
+    constexpr int T = kTP;
+    extern __shared__ int32_t sm[];
+    const int A = P.A, SS = P.A + 1;
+    for (int k = threadIdx.x; k < SS * SS; k += blockDim.x) {
+        const int r = k / SS, c = k - r * SS;
+        sm[k] = (r < A && c < A) ? (int)P.subst[r * A + c] : PAD32;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = blockIdx.x * kPairWaves + wave;
+    if (g >= P.n_groups) return;  // no block barrier below this point
+    const PairGroup G = P.groups[g];
+    const int slot = g * kWave + lane;
+    const bool act = lane < G.np;
+    PairInfo I = {0, 0, 0, 0, 0, -1, 0};
+    if (act) I = P.pairs[slot];
+    const int o = P.o, e = P.e, ends = P.ends;
+    const int m = I.m, n = I.n, S = G.strips;
+    const uint8_t *qc = P.q_codes + I.q_off;
+    const uint32_t *tw = P.tpk + G.tpk + lane;
+    uint2 *bnd = P.bnd + G.bnd + lane;
+    uint32_t *tb = P.tb + G.tb + lane;
+    const int ncols = G.ncols;
+
+    int Gs = (MODE == LOCAL) ? 0 : PAD32, Gj = 0, Gi = 0;
+    for (int s = 0; s < S; s++) {
+        const int i0 = s * T;
+        const bool first = (s == 0), last = (s == S - 1);
+        int rowb[T], H[T], E[T];
+#pragma unroll
+        for (int r = 0; r < T; r++) {
+            const int i = i0 + r;
+            rowb[r] = (i < m ? min((int)qc[i], A - 1) : A) * SS;
+            H[r] = left_value(MODE, ends, o, e, i + 1);
+            E[r] = H[r] - o;
+        }
+        int Hd_top = left_value(MODE, ends, o, e, i0);
+        int B = (MODE == LOCAL) ? max(Gs - 1, 0) : 0, Bj = 0, Bi = 0;
+        const int rlast = m - 1 - i0;
+        int res = 0, Ls = 0, Lj = 0;
+        if (MODE != LOCAL && last) { res = left_value(MODE, ends, o, e, m); Ls = res; }
+
+        for (int c4 = 0; c4 < (ncols >> 2); c4++) {
+            const uint32_t w4 = tw[(int64_t)c4 * kWave];
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                const int j = 4 * c4 + c + 1;
+                const int b = (w4 >> (8 * c)) & 0xff;
+                int Hup, F;
+                if (first) {
+                    Hup = top_value(MODE, ends, o, e, j);
+                    F = Hup - o;
+                } else {
+                    const uint2 bw = bnd[(int64_t)(j - 1) * kWave];
+                    Hup = (int)bw.x;
+                    F = (int)bw.y;
+                }
+                int Hd = Hd_top;
+                Hd_top = Hup;
+                int ho_up = Hup - o;
+                int cm = 0;
+                uint32_t acc = 0;
+#pragma unroll
+                for (int r = 0; r < T; r++) {
+                    const int t = Hd + sm[rowb[r] + b];
+                    const int Hold = H[r];
+                    Hd = Hold;
+                    const int Ein = E[r], Fin = F;
+                    int h = max(max(t, Ein), Fin);
+                    if (MODE == LOCAL) { h = max(h, 0); cm = max(cm, h); }
+                    const int ho = h - o;
+                    E[r] = max(Ein - e, ho);
+                    F = max(Fin - e, ho);
+                    H[r] = h;
+                    if (TB) {
+                        uint32_t src = (h == t) ? 1u : ((h == Ein) ? 2u : 3u);
+                        if (MODE == LOCAL && h == 0) src = 0u;
+                        const uint32_t eext = (Ein != Hold - o) ? 4u : 0u;
+                        const uint32_t fext = (Fin != ho_up) ? 8u : 0u;
+                        acc |= (src | eext | fext) << (4 * (r & 7));
+                        if ((r & 7) == 7) {
+                            tb[(((int64_t)s * ncols + (j - 1)) * 2 + (r >> 3)) * kWave] = acc;
+                            acc = 0;
+                        }
+                    }
+                    ho_up = ho;
+                }
+                if (MODE == LOCAL) {
+                    if (cm > B) {
+                        int rr = 0;
+#pragma unroll
+                        for (int r = T - 1; r >= 0; r--) rr = (H[r] == cm) ? r : rr;
+                        B = cm; Bj = j; Bi = i0 + rr + 1;
+                    }
+                } else if (last && j <= n) {
+                    int vl = H[0];
+#pragma unroll
+                    for (int k = 1; k < T; k++) vl = (k == rlast) ? H[k] : vl;
+                    if (!(ends & TE)) {
+                        if (j == n) res = vl;
+                    } else if (vl > Ls) {
+                        Ls = vl; Lj = j;
+                    }
+                }
+                if (!last) bnd[(int64_t)(j - 1) * kWave] = make_uint2((uint32_t)H[T - 1], (uint32_t)F);
+            }
+        }
+        if (MODE == LOCAL) {
+            const uint64_t gk = umax64(end_key(Gs, Gj, Gi), end_key(B, Bj, Bi));
+            if (B > 0) { Gs = key_score(gk); Gj = key_j(gk); Gi = key_i(gk); }
+        } else if (last) {
+            if (ends & TE) { Gs = Ls; Gj = Lj; }
+            else { Gs = res; Gj = n; }
+            Gi = m;
+        }
+    }
+    if (!act) return;
+    if (S == 0) {  // empty query: the last row is the top boundary row
+        if (MODE == LOCAL) { Gs = 0; }
+        else if (MODE == SEMIGLOBAL && (ends & TE)) { Gs = 0; Gj = 0; }
+        else { Gs = top_value(MODE, ends, o, e, n); Gj = n; }
+        Gi = 0;
+    }
+    int qe, te;
+    if (MODE == LOCAL) { qe = Gs > 0 ? Gi - 1 : -1; te = Gs > 0 ? Gj - 1 : -1; }
+    else { qe = m - 1; te = Gj - 1; }
+    P.out_score[I.res] = Gs;
+    if (P.out_qend) P.out_qend[I.res] = qe;
+    if (P.out_tend) P.out_tend[I.res] = te;
+    if (P.out_status) P.out_status[I.res] = 1;  // DSA_ST_INT32: exact int32 fill
+    if (TB) {
+        P.end_i[slot] = (MODE == LOCAL && Gs == 0) ? -1 : Gi;
+        P.end_j[slot] = Gj;
+    } else {
+        if (P.out_qbeg) P.out_qbeg[I.res] = -1;
+        if (P.out_tbeg) P.out_tbeg[I.res] = -1;
+    }
+}
+
+hipError_t launch_pair32(const PairArgs &a, int mode, hipStream_t s) {
+    if (a.n_groups <= 0) return hipSuccess;
+    const int nb = (a.n_groups + kPairWaves - 1) / kPairWaves;
+    const size_t lds = pair32_lds_bytes(a.A);
+#define LP(MODE, TBV) hipLaunchKernelGGL((k_pair32<MODE, TBV>), dim3(nb), dim3(kPairWaves * kWave), lds, s, a)
+    if (a.traceback) {
+        if (mode == LOCAL) LP(LOCAL, true); else if (mode == GLOBAL) LP(GLOBAL, true); else LP(SEMIGLOBAL, true);
+    } else {
+        if (mode == LOCAL) LP(LOCAL, false); else if (mode == GLOBAL) LP(GLOBAL, false); else LP(SEMIGLOBAL, false);
+    }
+#undef LP
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Traceback walk: one thread per pair slot.
+
+struct RunWriter {
+    uint32_t *out;
+    int64_t lo, pos;  // region [lo, hi); runs are written downwards from hi
+    uint32_t op = 0, len = 0;
+    bool truncated = false;
+    __device__ void flush() {
+        if (len == 0) return;
+        if (pos > lo) out[--pos] = (len << 4) | op;
+        else truncated = true;
+        len = 0;
+    }
+    __device__ void emit(uint32_t o, uint32_t count) {
+        if (count == 0) return;
+        if (o != op) { flush(); op = o; }
+        len += count;
+    }
+};
+
+constexpr uint32_t OP_I = 1, OP_D = 2, OP_EQ = 7, OP_X = 8;
+
+template <int MODE>
+__global__ void k_walk(PairArgs P, int64_t slot0, int64_t n_slots) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_slots) return;
+    const int64_t slot = slot0 + k;
+    const int g = (int)(slot / kWave), lane = (int)(slot % kWave);
+    const PairGroup G = P.groups[g];
+    if (lane >= G.np) return;
+    const PairInfo I = P.pairs[slot];
+    const int ends = P.ends;
+    int i = P.end_i[slot], j = P.end_j[slot];
+    RunWriter W{P.cigar, I.cig_off, I.cig_off + I.cig_cap};
+    if (i < 0) {  // local alignment of score 0: nothing to trace
+        if (P.out_qbeg) P.out_qbeg[I.res] = -1;
+        if (P.out_tbeg) P.out_tbeg[I.res] = -1;
+        P.cig_off_out[I.res] = I.cig_off;
+        P.cig_len_out[I.res] = 0;
+        return;
+    }
+    const uint8_t *qc = P.q_codes + I.q_off, *tc = P.t_codes + I.t_off;
+    const uint32_t *tb = P.tb + G.tb + lane;
+    const int ncols = G.ncols;
+    auto code = [&](int ii, int jj) -> uint32_t {
+        const int s = (ii - 1) / kTP, r = (ii - 1) % kTP;
+        const uint32_t w = tb[(((int64_t)s * ncols + (jj - 1)) * 2 + (r >> 3)) * kWave];
+        return (w >> (4 * (r & 7))) & 15u;
+    };
+    int state = 0;  // 0 = H, 1 = E, 2 = F
+    const int max_steps = I.m + I.n + 2;
+    for (int step = 0; step < max_steps; step++) {
+        if (state == 0) {
+            if (i == 0 || j == 0) {
+                if (MODE == LOCAL) break;
+                if (i == 0 && j > 0 && !(ends & TB)) { W.emit(OP_D, (uint32_t)j); j = 0; }
+                else if (j == 0 && i > 0 && !(ends & QB)) { W.emit(OP_I, (uint32_t)i); i = 0; }
+                break;
+            }
+            const uint32_t src = code(i, j) & 3u;
+            if (src == 0u) break;
+            if (src == 1u) {
+                W.emit(qc[i - 1] == tc[j - 1] ? OP_EQ : OP_X, 1);
+                i--; j--;
+            } else {
+                state = (src == 2u) ? 1 : 2;
+            }
+        } else if (state == 1) {
+            if (j <= 0 || i <= 0) break;  // codes never lead here; keeps reads in bounds
+            const uint32_t ext = (code(i, j) >> 2) & 1u;
+            W.emit(OP_D, 1);
+            j--;
+            if (!ext) state = 0;
+        } else {
+            if (j <= 0 || i <= 0) break;
+            const uint32_t ext = (code(i, j) >> 3) & 1u;
+            W.emit(OP_I, 1);
+            i--;
+            if (!ext) state = 0;
+        }
+    }
+    W.flush();
+    if (P.out_qbeg) P.out_qbeg[I.res] = i;
+    if (P.out_tbeg) P.out_tbeg[I.res] = j;
+    P.cig_off_out[I.res] = W.pos;
+    P.cig_len_out[I.res] = (int32_t)(I.cig_off + I.cig_cap - W.pos);
+    if (W.truncated && P.out_status) P.out_status[I.res] |= 2;  // DSA_ST_TRUNCATED
+}
+
+hipError_t launch_walk(const PairArgs &a, int mode, int64_t slot0, int64_t n_slots, hipStream_t s) {
+    if (n_slots <= 0) return hipSuccess;
+    const int bs = 64;
+    const unsigned nb = (unsigned)((n_slots + bs - 1) / bs);
+    if (mode == LOCAL) hipLaunchKernelGGL(k_walk<LOCAL>, dim3(nb), dim3(bs), 0, s, a, slot0, n_slots);
+    else if (mode == GLOBAL) hipLaunchKernelGGL(k_walk<GLOBAL>, dim3(nb), dim3(bs), 0, s, a, slot0, n_slots);
+    else hipLaunchKernelGGL(k_walk<SEMIGLOBAL>, dim3(nb), dim3(bs), 0, s, a, slot0, n_slots);
+    return hipGetLastError();
+}
+
+}  // namespace dsa

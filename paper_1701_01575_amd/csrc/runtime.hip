@@ -4,6 +4,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -542,10 +543,126 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     return DSA_OK;
 }
 
+// Pairwise plan: pairs sorted by (strips, target length), longest first,
+// into groups of 64 lanes sharing a strip count; direction codes chunked to a
+// byte budget (fill then walk per chunk).
+struct PairPlan {
+    int mode = 0, ends = 0;
+    bool traceback = false;
+    std::vector<PairInfo> slots;    // n_groups * 64, empty lanes have res = -1
+    std::vector<PairGroup> groups;
+    std::vector<int64_t> chunk_first;  // first group of each chunk (+ end)
+    int64_t tb_max = 0;             // uint32 codes of the largest chunk
+    int64_t bnd_total = 0, tpk_total = 0;
+    bool capacity_short = false;
+    size_t off_slots = 0, off_groups = 0, off_subst = 0, table_bytes = 0;
+    size_t off_end = 0, off_bnd = 0, off_tpk = 0, off_tb = 0, total = 0;
+};
+
+int make_pair_plan(const dsa_args *a, const dsa_out *out, PairPlan &P) {
+    if (!a->t_codes || !a->t_offsets) return fail(DSA_E_INVAL, "pairwise needs t_codes and t_offsets");
+    if (a->t_offsets[0] != 0) return fail(DSA_E_INVAL, "t_offsets[0] must be 0");
+    const int64_t n = a->n_q;
+    for (int64_t k = 0; k < n; k++)
+        if (a->t_offsets[k + 1] < a->t_offsets[k]) return fail(DSA_E_INVAL, "t_offsets must be non-decreasing");
+    if (a->t_offsets[n] > 0 && !a->t_codes) return fail(DSA_E_INVAL, "t_codes is NULL");
+    if (a->top_k) return fail(DSA_E_INVAL, "top_k applies to database search only");
+    P.mode = a->mode;
+    P.ends = a->mode == DSA_SEMIGLOBAL ? (a->free_ends ? a->free_ends : (DSA_TB | DSA_TE)) : 0;
+    if (P.ends & DSA_QE) return fail(DSA_E_NOTSUP, "free query end (QE) is not supported");
+    P.traceback = (a->flags & DSA_TRACEBACK) != 0;
+    int mx = 0;
+    for (int k = 0; k < a->alphabet_size * a->alphabet_size; k++) mx = std::max(mx, std::abs((int)a->subst[k]));
+    std::vector<int64_t> m(n), len(n);
+    for (int64_t k = 0; k < n; k++) {
+        m[k] = a->q_offsets[k + 1] - a->q_offsets[k];
+        len[k] = a->t_offsets[k + 1] - a->t_offsets[k];
+        if (m[k] > kMaxLen16 || len[k] > kMaxLen16)
+            return fail(DSA_E_NOTSUP, "sequences longer than 65532 residues are not supported");
+        const int64_t bound = (int64_t)mx * std::min(m[k], len[k]) + 3LL * a->gap_open +
+                              (m[k] + len[k] + 64) * (int64_t)a->gap_extend;
+        if (bound >= (1LL << 30)) return fail(DSA_E_RANGE, "scores could leave the int32 range");
+    }
+    std::vector<int64_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    auto strips = [&](int64_t k) { return (m[k] + kTP - 1) / kTP; };
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+        if (strips(x) != strips(y)) return strips(x) > strips(y);
+        return len[x] > len[y];
+    });
+    // CIGAR regions in caller order: m + n + 1 runs each while capacity lasts
+    std::vector<int64_t> cig_off(n, 0), cig_cap(n, 0);
+    {
+        int64_t acc = 0;
+        const int64_t cap = (P.traceback && out) ? out->cigar_capacity : 0;
+        for (int64_t k = 0; k < n; k++) {
+            const int64_t need = m[k] + len[k] + 1;
+            cig_off[k] = acc;
+            if (P.traceback && acc + need <= cap) { cig_cap[k] = need; acc += need; }
+            else if (P.traceback) { P.capacity_short = true; }
+        }
+    }
+    int64_t tb_budget = (int64_t)4 << 30;  // bytes of direction codes per chunk
+    if (const char *v = getenv("DSA_TB_BUDGET")) tb_budget = std::max<int64_t>(atoll(v), 1 << 20);
+    int64_t chunk_tb = 0;
+    for (int64_t k = 0; k < n;) {
+        const int64_t S = strips(order[k]);
+        int64_t e = k;
+        while (e < n && e - k < kWave && strips(order[e]) == S) e++;
+        PairGroup G;
+        G.ncols = (int32_t)align_up((size_t)len[order[k]], kPadLen);
+        G.strips = (int32_t)S;
+        G.p0 = (int32_t)(P.groups.size() * kWave);
+        G.np = (int32_t)(e - k);
+        G.bnd = P.bnd_total;
+        G.tpk = P.tpk_total;
+        P.bnd_total += (int64_t)G.ncols * kWave;
+        P.tpk_total += (int64_t)(G.ncols / 4) * kWave;
+        const int64_t tb_words = P.traceback ? (int64_t)S * G.ncols * 2 * kWave : 0;
+        if (P.groups.empty() || (chunk_tb > 0 && (chunk_tb + tb_words) * 4 > tb_budget)) {
+            P.chunk_first.push_back((int64_t)P.groups.size());
+            chunk_tb = 0;
+        }
+        G.tb = chunk_tb;
+        chunk_tb += tb_words;
+        P.tb_max = std::max(P.tb_max, chunk_tb);
+        P.groups.push_back(G);
+        for (int lane = 0; lane < kWave; lane++) {
+            PairInfo I;
+            memset(&I, 0, sizeof(I));
+            I.res = -1;
+            if (k + lane < e) {
+                const int64_t q = order[k + lane];
+                I.q_off = a->q_offsets[q];
+                I.t_off = a->t_offsets[q];
+                I.m = (int32_t)m[q];
+                I.n = (int32_t)len[q];
+                I.res = (int32_t)q;
+                I.cig_off = cig_off[q];
+                I.cig_cap = (int32_t)cig_cap[q];
+            }
+            P.slots.push_back(I);
+        }
+        k = e;
+    }
+    P.chunk_first.push_back((int64_t)P.groups.size());
+    const int A = a->alphabet_size;
+    size_t o = 0;
+    P.off_slots = o; o = align_up(o + std::max<size_t>(P.slots.size(), 1) * sizeof(PairInfo), 256);
+    P.off_groups = o; o = align_up(o + std::max<size_t>(P.groups.size(), 1) * sizeof(PairGroup), 256);
+    P.off_subst = o; o = align_up(o + (size_t)A * A, 256);
+    P.table_bytes = o;
+    P.off_end = o; o = align_up(o + std::max<size_t>(P.slots.size(), 1) * 8, 256);
+    P.off_bnd = o; o = align_up(o + (size_t)std::max<int64_t>(P.bnd_total, 1) * 8, 256);
+    P.off_tpk = o; o = align_up(o + (size_t)std::max<int64_t>(P.tpk_total, 1) * 4, 256);
+    P.off_tb = o; o = align_up(o + (size_t)std::max<int64_t>(P.tb_max, 1) * 4, 256);
+    P.total = o;
+    return DSA_OK;
+}
+
 int make_plan(const dsa_args *a, Plan &P) {
     int rc = check_common(a);
     if (rc) return rc;
-    if (!a->db) return fail(DSA_E_NOTSUP, "pairwise alignment is not supported yet");
     return make_search_plan(a, P);
 }
 
@@ -553,11 +670,102 @@ int make_plan(const dsa_args *a, Plan &P) {
 
 extern "C" int dsa_workspace_size(const dsa_args *args, size_t *bytes) {
     if (!bytes) return fail(DSA_E_INVAL, "bytes is NULL");
-    Plan P;
-    int rc = make_plan(args, P);
+    int rc = check_common(args);
     if (rc) return rc;
+    if (!args->db) {
+        PairPlan PP;
+        if ((rc = make_pair_plan(args, nullptr, PP))) return rc;
+        *bytes = PP.total;
+        return DSA_OK;
+    }
+    Plan P;
+    if ((rc = make_plan(args, P))) return rc;
     *bytes = P.total;
     return DSA_OK;
+}
+
+static int upload_tables(hipStream_t st, void *dst, size_t bytes,
+                         const std::function<void(uint8_t *)> &fill) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    Staging &S = g_staging[dev & 63];
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (S.pending) {
+        HIPCHK(hipEventSynchronize(S.ev));
+        S.pending = false;
+    }
+    if (S.cap < bytes) {
+        if (S.buf) HIPCHK(hipHostFree(S.buf));
+        S.buf = nullptr;
+        S.cap = 0;
+        HIPCHK(hipHostMalloc(&S.buf, bytes, hipHostMallocDefault));
+        S.cap = bytes;
+    }
+    if (!S.ev) HIPCHK(hipEventCreateWithFlags(&S.ev, hipEventDisableTiming));
+    memset(S.buf, 0, bytes);
+    fill((uint8_t *)S.buf);
+    HIPCHK(hipMemcpyAsync(dst, S.buf, bytes, hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(S.ev, st));
+    S.pending = true;
+    return DSA_OK;
+}
+
+static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P) {
+    hipStream_t st = (hipStream_t)a->stream;
+    uint8_t *ws = (uint8_t *)a->workspace;
+    const int A = a->alphabet_size;
+    if (P.traceback && (!out->cigar_ops || !out->cigar_off || !out->cigar_len))
+        return fail(DSA_E_INVAL, "traceback needs cigar_ops, cigar_off and cigar_len");
+    int rc = upload_tables(st, ws, P.table_bytes, [&](uint8_t *h) {
+        memcpy(h + P.off_slots, P.slots.data(), P.slots.size() * sizeof(PairInfo));
+        memcpy(h + P.off_groups, P.groups.data(), P.groups.size() * sizeof(PairGroup));
+        memcpy(h + P.off_subst, a->subst, (size_t)A * A);
+    });
+    if (rc) return rc;
+    PairArgs K;
+    memset(&K, 0, sizeof(K));
+    K.pairs = (const PairInfo *)(ws + P.off_slots);
+    K.q_codes = a->q_codes;
+    K.t_codes = a->t_codes;
+    K.subst = (const int8_t *)(ws + P.off_subst);
+    K.A = A;
+    K.o = a->gap_open;
+    K.e = a->gap_extend;
+    K.ends = P.ends;
+    K.traceback = P.traceback ? 1 : 0;
+    K.tb = (uint32_t *)(ws + P.off_tb);
+    K.bnd = (uint2 *)(ws + P.off_bnd);
+    K.tpk = (uint32_t *)(ws + P.off_tpk);
+    K.out_score = out->score;
+    K.out_qend = out->q_end;
+    K.out_tend = out->t_end;
+    K.out_qbeg = out->q_begin;
+    K.out_tbeg = out->t_begin;
+    K.out_status = out->status;
+    K.end_i = (int32_t *)(ws + P.off_end);
+    K.end_j = K.end_i + P.slots.size();
+    K.cig_off_out = out->cigar_off;
+    K.cig_len_out = out->cigar_len;
+    K.cigar = out->cigar_ops;
+    // pack every group's targets once
+    {
+        PairArgs k = K;
+        k.groups = (const PairGroup *)(ws + P.off_groups);
+        k.n_groups = (int32_t)P.groups.size();
+        HIPCHK(launch_pack_targets(k, P.tpk_total, st));
+    }
+    for (size_t c = 0; c + 1 < P.chunk_first.size(); c++) {
+        const int64_t g0 = P.chunk_first[c], g1 = P.chunk_first[c + 1];
+        PairArgs k = K;
+        k.groups = (const PairGroup *)(ws + P.off_groups) + g0;
+        k.n_groups = (int32_t)(g1 - g0);
+        k.pairs = K.pairs + g0 * kWave;
+        k.end_i = K.end_i + g0 * kWave;
+        k.end_j = K.end_j + g0 * kWave;
+        HIPCHK(launch_pair32(k, P.mode, st));
+        if (P.traceback) HIPCHK(launch_walk(k, P.mode, 0, (g1 - g0) * kWave, st));
+    }
+    return P.capacity_short ? fail(DSA_E_CAPACITY, "CIGAR capacity too small; see status bit 1") : DSA_OK;
 }
 
 extern "C" int dsa_cigar_capacity(const dsa_args *args, int64_t *entries) {
@@ -570,12 +778,13 @@ extern "C" int dsa_cigar_capacity(const dsa_args *args, int64_t *entries) {
         const int64_t k = args->top_k ? args->top_k : nt;
         for (int64_t q = 0; q < args->n_q; q++) {
             const int64_t m = args->q_offsets[q + 1] - args->q_offsets[q];
-            total += k * (m + args->db->max_len);
+            total += k * (m + args->db->max_len + 1);
         }
     } else {
+        if (!args->t_offsets) return fail(DSA_E_INVAL, "t_offsets is NULL");
         for (int64_t q = 0; q < args->n_q; q++)
             total += (args->q_offsets[q + 1] - args->q_offsets[q]) +
-                     (args->t_offsets[q + 1] - args->t_offsets[q]);
+                     (args->t_offsets[q + 1] - args->t_offsets[q]) + 1;
     }
     *entries = total;
     return DSA_OK;
@@ -835,8 +1044,19 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
 
 extern "C" int dsa_align_batch(const dsa_args *args, const dsa_out *out) {
     if (!out || !out->score) return fail(DSA_E_INVAL, "out->score is required");
+    int rc = check_common(args);
+    if (rc) return rc;
+    if (!args->db) {
+        PairPlan PP;
+        if ((rc = make_pair_plan(args, out, PP))) return rc;
+        if (!args->workspace && PP.total) return fail(DSA_E_INVAL, "workspace is NULL");
+        if (args->workspace_bytes < PP.total)
+            return fail(DSA_E_WORKSPACE, "workspace too small: need " + std::to_string(PP.total) + " bytes");
+        if (((uintptr_t)args->workspace) & 255) return fail(DSA_E_INVAL, "workspace must be 256-byte aligned");
+        return run_pairs(args, out, PP);
+    }
     Plan P;
-    int rc = make_plan(args, P);
+    rc = make_plan(args, P);
     if (rc) return rc;
     if (!args->workspace && P.total) return fail(DSA_E_INVAL, "workspace is NULL");
     if (args->workspace_bytes < P.total)
