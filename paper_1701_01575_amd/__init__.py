@@ -153,6 +153,8 @@ def align_args(a, device, n_results, want_coords=True, want_begin=True, cigar_ca
         res["q_begin"] = torch.empty(nr, **i32)
         res["t_begin"] = torch.empty(nr, **i32)
     res["status"] = torch.empty(nr, dtype=torch.uint8, device=device)
+    if a.top_k:
+        res["t_index"] = torch.empty(nr, dtype=torch.int64, device=device)
     if a.flags & DSA_TRACEBACK:
         cap = B.dsa_cigar_capacity(a) if cigar_capacity is None else int(cigar_capacity)
         res["cigar_off"] = torch.empty(nr, dtype=torch.int64, device=device)

@@ -154,6 +154,18 @@ hipError_t launch_pair32(const PairArgs &a, int mode, hipStream_t s);
 hipError_t launch_walk(const PairArgs &a, int mode, int64_t slot0, int64_t n_slots, hipStream_t s);
 size_t pair32_lds_bytes(int A);
 
+struct TopkArgs {
+    const int32_t *score, *qend, *tend;   // full results, n_q x n_t
+    const uint8_t *status;
+    int64_t n_t;
+    int32_t n_q, K, positive_only;
+    int32_t *out_score, *out_qend, *out_tend;
+    int64_t *out_tindex;
+    uint8_t *out_status;
+    int32_t *hit_t;                       // n_q x K hit target indices (-1 = none)
+};
+hipError_t launch_topk(const TopkArgs &a, hipStream_t s);
+
 // Launchers (kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_search16(const SearchArgs &a, int T, int mode, int waves_per_block,
                            int n_blocks, bool persistent, size_t lds_bytes, hipStream_t s);

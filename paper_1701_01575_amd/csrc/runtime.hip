@@ -135,6 +135,8 @@ struct dsa_db {
     int64_t *d_len = nullptr;
     LongPair *d_pairs = nullptr;
     uint16_t *d_lcodes = nullptr;
+    uint8_t *d_codes = nullptr;      // targets in original order (traceback of hits)
+    std::vector<int64_t> offsets;    // host copy of the target offsets
     int64_t device_bytes = 0;
 };
 
@@ -152,6 +154,7 @@ static void db_free(dsa_db *db) {
     hipFree(db->d_len);
     hipFree(db->d_pairs);
     hipFree(db->d_lcodes);
+    hipFree(db->d_codes);
     delete db;
 }
 
@@ -188,6 +191,7 @@ extern "C" int dsa_db_create(const uint8_t *codes, const int64_t *offsets, int64
     db->n_targets = n_targets;
     db->n_residues = total;
     db->len.resize(n_targets);
+    db->offsets.assign(offsets, offsets + n_targets + 1);
     for (int64_t k = 0; k < n_targets; k++) {
         db->len[k] = offsets[k + 1] - offsets[k];
         db->max_len = std::max(db->max_len, db->len[k]);
@@ -289,7 +293,8 @@ extern "C" int dsa_db_create(const uint8_t *codes, const int64_t *offsets, int64
         (rc = upload(&db->d_inv_map, db->inv_map, (size_t)AP, &db->device_bytes)) ||
         (rc = upload(&db->d_len, db->len.data(), db->len.size(), &db->device_bytes)) ||
         (rc = upload(&db->d_pairs, db->pairs.data(), db->pairs.size(), &db->device_bytes)) ||
-        (rc = upload(&db->d_lcodes, lcodes.data(), lcodes.size(), &db->device_bytes))) {
+        (rc = upload(&db->d_lcodes, lcodes.data(), lcodes.size(), &db->device_bytes)) ||
+        (rc = upload(&db->d_codes, codes, (size_t)total, &db->device_bytes))) {
         db_free(db);
         return rc;
     }
@@ -345,6 +350,11 @@ struct Plan {
     size_t off_units = 0, off_qinfo = 0, off_subst = 0, off_rows = 0, table_bytes = 0;
     size_t off_flags = 0, off_qflag = 0, off_counter = 0, off_bnd = 0, off_prof = 0, total = 0;
     size_t off_iunits = 0, off_ibnd = 0;
+    // top-K: full per-target results, hit list, pairwise workspace for traceback
+    int K = 0;
+    bool traceback = false;
+    size_t off_full = 0, off_hits = 0, off_pairws = 0, pairws_bytes = 0;
+    int64_t pair_tb_cap = 0;
     int64_t prof_dwords = 0;
     int32_t min_s = 0, max_abs_s = 0;
 };
@@ -375,13 +385,162 @@ int check_common(const dsa_args *a) {
     return DSA_OK;
 }
 
+// Pairwise plan: pairs sorted by (strips, target length), longest first,
+// into groups of 64 lanes sharing a strip count; direction codes chunked to a
+// byte budget (fill then walk per chunk).
+struct PairPlan {
+    int mode = 0, ends = 0;
+    bool traceback = false;
+    std::vector<PairInfo> slots;    // n_groups * 64, empty lanes have res = -1
+    std::vector<PairGroup> groups;
+    std::vector<int64_t> chunk_first;  // first group of each chunk (+ end)
+    int64_t tb_max = 0;             // uint32 codes of the largest chunk
+    int64_t tb_total = 0, tb_group_max = 0;
+    int64_t bnd_total = 0, tpk_total = 0;
+    bool capacity_short = false;
+    size_t off_slots = 0, off_groups = 0, off_subst = 0, table_bytes = 0;
+    size_t off_end = 0, off_bnd = 0, off_tpk = 0, off_tb = 0, total = 0;
+};
+
+struct PairSpec {
+    int64_t q_off, t_off, m, n;
+    int32_t res;
+};
+
+int64_t tb_budget_bytes() {
+    int64_t b = (int64_t)4 << 30;  // bytes of direction codes per chunk
+    if (const char *v = getenv("DSA_TB_BUDGET")) b = std::max<int64_t>(atoll(v), 1 << 20);
+    return b;
+}
+
+// Group and lay out a list of pairs.  n_results sizes the CIGAR regions (one
+// per result index, in result order); tb_cap caps the codes of one chunk.
+void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mode, int ends,
+                     bool traceback, int64_t cigar_capacity, int A, int64_t tb_cap, PairPlan &P) {
+    const int64_t n = (int64_t)sp.size();
+    P.mode = mode;
+    P.ends = ends;
+    P.traceback = traceback;
+    std::vector<int64_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    auto strips = [&](int64_t k) { return (sp[k].m + kTP - 1) / kTP; };
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+        if (strips(x) != strips(y)) return strips(x) > strips(y);
+        return sp[x].n > sp[y].n;
+    });
+    // CIGAR regions in result order: m + n + 1 runs each while capacity lasts
+    std::vector<int64_t> need(std::max<int64_t>(n_results, 1), 0), roff(need.size(), 0), rcap(need.size(), 0);
+    for (const auto &x : sp) need[x.res] = x.m + x.n + 1;
+    {
+        int64_t acc = 0;
+        for (int64_t r = 0; r < n_results; r++) {
+            roff[r] = acc;
+            if (!traceback || need[r] == 0) continue;
+            if (acc + need[r] <= cigar_capacity) { rcap[r] = need[r]; acc += need[r]; }
+            else P.capacity_short = true;
+        }
+    }
+    int64_t chunk_tb = 0;
+    for (int64_t k = 0; k < n;) {
+        const int64_t S = strips(order[k]);
+        int64_t e = k;
+        while (e < n && e - k < kWave && strips(order[e]) == S) e++;
+        PairGroup G;
+        G.ncols = (int32_t)align_up((size_t)sp[order[k]].n, kPadLen);
+        G.strips = (int32_t)S;
+        G.p0 = (int32_t)(P.groups.size() * kWave);
+        G.np = (int32_t)(e - k);
+        G.bnd = P.bnd_total;
+        G.tpk = P.tpk_total;
+        P.bnd_total += (int64_t)G.ncols * kWave;
+        P.tpk_total += (int64_t)(G.ncols / 4) * kWave;
+        const int64_t tb_words = traceback ? (int64_t)S * G.ncols * 2 * kWave : 0;
+        if (P.groups.empty() || (chunk_tb > 0 && (chunk_tb + tb_words) * 4 > tb_cap)) {
+            P.chunk_first.push_back((int64_t)P.groups.size());
+            chunk_tb = 0;
+        }
+        G.tb = chunk_tb;
+        chunk_tb += tb_words;
+        P.tb_max = std::max(P.tb_max, chunk_tb);
+        P.tb_total += tb_words;
+        P.tb_group_max = std::max(P.tb_group_max, tb_words);
+        P.groups.push_back(G);
+        for (int lane = 0; lane < kWave; lane++) {
+            PairInfo I;
+            memset(&I, 0, sizeof(I));
+            I.res = -1;
+            if (k + lane < e) {
+                const PairSpec &x = sp[order[k + lane]];
+                I.q_off = x.q_off;
+                I.t_off = x.t_off;
+                I.m = (int32_t)x.m;
+                I.n = (int32_t)x.n;
+                I.res = x.res;
+                I.cig_off = roff[x.res];
+                I.cig_cap = (int32_t)rcap[x.res];
+            }
+            P.slots.push_back(I);
+        }
+        k = e;
+    }
+    P.chunk_first.push_back((int64_t)P.groups.size());
+    size_t o = 0;
+    P.off_slots = o; o = align_up(o + std::max<size_t>(P.slots.size(), 1) * sizeof(PairInfo), 256);
+    P.off_groups = o; o = align_up(o + std::max<size_t>(P.groups.size(), 1) * sizeof(PairGroup), 256);
+    P.off_subst = o; o = align_up(o + (size_t)A * A, 256);
+    P.table_bytes = o;
+    P.off_end = o; o = align_up(o + std::max<size_t>(P.slots.size(), 1) * 8, 256);
+    P.off_bnd = o; o = align_up(o + (size_t)std::max<int64_t>(P.bnd_total, 1) * 8, 256);
+    P.off_tpk = o; o = align_up(o + (size_t)std::max<int64_t>(P.tpk_total, 1) * 4, 256);
+    P.off_tb = o; o = align_up(o + (size_t)std::max<int64_t>(P.tb_max, 1) * 4, 256);
+    P.total = o;
+}
+
+int check_pair_range(const dsa_args *a, int64_t m, int64_t n) {
+    if (m > kMaxLen16 || n > kMaxLen16)
+        return fail(DSA_E_NOTSUP, "sequences longer than 65532 residues are not supported");
+    int mx = 0;
+    for (int k = 0; k < a->alphabet_size * a->alphabet_size; k++) mx = std::max(mx, std::abs((int)a->subst[k]));
+    const int64_t bound = (int64_t)mx * std::min(m, n) + 3LL * a->gap_open + (m + n + 64) * (int64_t)a->gap_extend;
+    if (bound >= (1LL << 30)) return fail(DSA_E_RANGE, "scores could leave the int32 range");
+    return DSA_OK;
+}
+
+int make_pair_plan(const dsa_args *a, const dsa_out *out, PairPlan &P) {
+    if (!a->t_codes || !a->t_offsets) return fail(DSA_E_INVAL, "pairwise needs t_codes and t_offsets");
+    if (a->t_offsets[0] != 0) return fail(DSA_E_INVAL, "t_offsets[0] must be 0");
+    const int64_t n = a->n_q;
+    for (int64_t k = 0; k < n; k++)
+        if (a->t_offsets[k + 1] < a->t_offsets[k]) return fail(DSA_E_INVAL, "t_offsets must be non-decreasing");
+    if (a->top_k) return fail(DSA_E_INVAL, "top_k applies to database search only");
+    const int ends = a->mode == DSA_SEMIGLOBAL ? (a->free_ends ? a->free_ends : (DSA_TB | DSA_TE)) : 0;
+    if (ends & DSA_QE) return fail(DSA_E_NOTSUP, "free query end (QE) is not supported");
+    std::vector<PairSpec> sp(n);
+    for (int64_t k = 0; k < n; k++) {
+        sp[k].q_off = a->q_offsets[k];
+        sp[k].t_off = a->t_offsets[k];
+        sp[k].m = a->q_offsets[k + 1] - a->q_offsets[k];
+        sp[k].n = a->t_offsets[k + 1] - a->t_offsets[k];
+        sp[k].res = (int32_t)k;
+        const int rc = check_pair_range(a, sp[k].m, sp[k].n);
+        if (rc) return rc;
+    }
+    const bool tb = (a->flags & DSA_TRACEBACK) != 0;
+    build_pair_plan(sp, n, a->mode, ends, tb, (tb && out) ? out->cigar_capacity : 0, a->alphabet_size,
+                    tb_budget_bytes(), P);
+    return DSA_OK;
+}
+
 int make_search_plan(const dsa_args *a, Plan &P) {
     const dsa_db *db = a->db;
     if (db->A != a->alphabet_size) return fail(DSA_E_INVAL, "alphabet_size differs from the database's");
     const int ends = a->mode == DSA_SEMIGLOBAL ? (a->free_ends ? a->free_ends : (DSA_TB | DSA_TE)) : 0;
     if (ends & DSA_QE) return fail(DSA_E_NOTSUP, "free query end (QE) is not supported in database search");
-    if (a->flags & DSA_TRACEBACK) return fail(DSA_E_NOTSUP, "traceback is not supported in database search yet");
-    if (a->top_k != 0) return fail(DSA_E_NOTSUP, "top_k is not supported yet");
+    if (a->top_k < 0 || a->top_k > 64) return fail(DSA_E_INVAL, "top_k must be in [0, 64]");
+    if ((a->flags & DSA_TRACEBACK) && a->top_k == 0)
+        return fail(DSA_E_NOTSUP, "database-search traceback needs top_k (trace the hits)");
+    P.K = a->top_k;
+    P.traceback = (a->flags & DSA_TRACEBACK) != 0;
     P.mode = a->mode;
     P.ends = ends;
     P.persistent = !(a->flags & DSA_PLAIN);
@@ -539,123 +698,32 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     P.off_bnd = o; o = align_up(o + (size_t)P.n_slots * db->bnd_slot_uint2 * 8, 256);
     P.off_prof = o; o = align_up(o + (size_t)std::max<int64_t>(P.prof_dwords, 1) * 4, 256);
     P.off_ibnd = o; o = align_up(o + (size_t)P.n_slots * std::max<int64_t>(db->long_bnd_slot, 1) * 8, 256);
-    P.total = o;
-    return DSA_OK;
-}
-
-// Pairwise plan: pairs sorted by (strips, target length), longest first,
-// into groups of 64 lanes sharing a strip count; direction codes chunked to a
-// byte budget (fill then walk per chunk).
-struct PairPlan {
-    int mode = 0, ends = 0;
-    bool traceback = false;
-    std::vector<PairInfo> slots;    // n_groups * 64, empty lanes have res = -1
-    std::vector<PairGroup> groups;
-    std::vector<int64_t> chunk_first;  // first group of each chunk (+ end)
-    int64_t tb_max = 0;             // uint32 codes of the largest chunk
-    int64_t bnd_total = 0, tpk_total = 0;
-    bool capacity_short = false;
-    size_t off_slots = 0, off_groups = 0, off_subst = 0, table_bytes = 0;
-    size_t off_end = 0, off_bnd = 0, off_tpk = 0, off_tb = 0, total = 0;
-};
-
-int make_pair_plan(const dsa_args *a, const dsa_out *out, PairPlan &P) {
-    if (!a->t_codes || !a->t_offsets) return fail(DSA_E_INVAL, "pairwise needs t_codes and t_offsets");
-    if (a->t_offsets[0] != 0) return fail(DSA_E_INVAL, "t_offsets[0] must be 0");
-    const int64_t n = a->n_q;
-    for (int64_t k = 0; k < n; k++)
-        if (a->t_offsets[k + 1] < a->t_offsets[k]) return fail(DSA_E_INVAL, "t_offsets must be non-decreasing");
-    if (a->t_offsets[n] > 0 && !a->t_codes) return fail(DSA_E_INVAL, "t_codes is NULL");
-    if (a->top_k) return fail(DSA_E_INVAL, "top_k applies to database search only");
-    P.mode = a->mode;
-    P.ends = a->mode == DSA_SEMIGLOBAL ? (a->free_ends ? a->free_ends : (DSA_TB | DSA_TE)) : 0;
-    if (P.ends & DSA_QE) return fail(DSA_E_NOTSUP, "free query end (QE) is not supported");
-    P.traceback = (a->flags & DSA_TRACEBACK) != 0;
-    int mx = 0;
-    for (int k = 0; k < a->alphabet_size * a->alphabet_size; k++) mx = std::max(mx, std::abs((int)a->subst[k]));
-    std::vector<int64_t> m(n), len(n);
-    for (int64_t k = 0; k < n; k++) {
-        m[k] = a->q_offsets[k + 1] - a->q_offsets[k];
-        len[k] = a->t_offsets[k + 1] - a->t_offsets[k];
-        if (m[k] > kMaxLen16 || len[k] > kMaxLen16)
-            return fail(DSA_E_NOTSUP, "sequences longer than 65532 residues are not supported");
-        const int64_t bound = (int64_t)mx * std::min(m[k], len[k]) + 3LL * a->gap_open +
-                              (m[k] + len[k] + 64) * (int64_t)a->gap_extend;
-        if (bound >= (1LL << 30)) return fail(DSA_E_RANGE, "scores could leave the int32 range");
+    if (P.K > 0) {
+        const size_t nres = (size_t)nq * db->n_targets;
+        P.off_full = o; o = align_up(o + nres * 13, 256);  // score, q_end, t_end (int32), status (u8)
+        P.off_hits = o; o = align_up(o + (size_t)nq * P.K * 4, 256);
     }
-    std::vector<int64_t> order(n);
-    std::iota(order.begin(), order.end(), 0);
-    auto strips = [&](int64_t k) { return (m[k] + kTP - 1) / kTP; };
-    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
-        if (strips(x) != strips(y)) return strips(x) > strips(y);
-        return len[x] > len[y];
-    });
-    // CIGAR regions in caller order: m + n + 1 runs each while capacity lasts
-    std::vector<int64_t> cig_off(n, 0), cig_cap(n, 0);
-    {
-        int64_t acc = 0;
-        const int64_t cap = (P.traceback && out) ? out->cigar_capacity : 0;
-        for (int64_t k = 0; k < n; k++) {
-            const int64_t need = m[k] + len[k] + 1;
-            cig_off[k] = acc;
-            if (P.traceback && acc + need <= cap) { cig_cap[k] = need; acc += need; }
-            else if (P.traceback) { P.capacity_short = true; }
-        }
-    }
-    int64_t tb_budget = (int64_t)4 << 30;  // bytes of direction codes per chunk
-    if (const char *v = getenv("DSA_TB_BUDGET")) tb_budget = std::max<int64_t>(atoll(v), 1 << 20);
-    int64_t chunk_tb = 0;
-    for (int64_t k = 0; k < n;) {
-        const int64_t S = strips(order[k]);
-        int64_t e = k;
-        while (e < n && e - k < kWave && strips(order[e]) == S) e++;
-        PairGroup G;
-        G.ncols = (int32_t)align_up((size_t)len[order[k]], kPadLen);
-        G.strips = (int32_t)S;
-        G.p0 = (int32_t)(P.groups.size() * kWave);
-        G.np = (int32_t)(e - k);
-        G.bnd = P.bnd_total;
-        G.tpk = P.tpk_total;
-        P.bnd_total += (int64_t)G.ncols * kWave;
-        P.tpk_total += (int64_t)(G.ncols / 4) * kWave;
-        const int64_t tb_words = P.traceback ? (int64_t)S * G.ncols * 2 * kWave : 0;
-        if (P.groups.empty() || (chunk_tb > 0 && (chunk_tb + tb_words) * 4 > tb_budget)) {
-            P.chunk_first.push_back((int64_t)P.groups.size());
-            chunk_tb = 0;
-        }
-        G.tb = chunk_tb;
-        chunk_tb += tb_words;
-        P.tb_max = std::max(P.tb_max, chunk_tb);
-        P.groups.push_back(G);
-        for (int lane = 0; lane < kWave; lane++) {
-            PairInfo I;
-            memset(&I, 0, sizeof(I));
-            I.res = -1;
-            if (k + lane < e) {
-                const int64_t q = order[k + lane];
-                I.q_off = a->q_offsets[q];
-                I.t_off = a->t_offsets[q];
-                I.m = (int32_t)m[q];
-                I.n = (int32_t)len[q];
-                I.res = (int32_t)q;
-                I.cig_off = cig_off[q];
-                I.cig_cap = (int32_t)cig_cap[q];
+    if (P.K > 0 && P.traceback) {
+        // worst case for the hits: K per query, each as long as the longest target
+        std::vector<PairSpec> sp;
+        for (int64_t q = 0; q < nq; q++)
+            for (int k = 0; k < P.K; k++) {
+                PairSpec x;
+                x.q_off = 0; x.t_off = 0;
+                x.m = P.qinfo[q].len;
+                x.n = db->max_len;
+                x.res = (int32_t)(q * P.K + k);
+                sp.push_back(x);
+                const int rc = check_pair_range(a, x.m, x.n);
+                if (rc) return rc;
             }
-            P.slots.push_back(I);
-        }
-        k = e;
+        PairPlan B;
+        build_pair_plan(sp, nq * P.K, P.mode, P.ends, true, 0, A, tb_budget_bytes(), B);
+        const int64_t words = std::max(B.tb_max, std::min(tb_budget_bytes() / 4, B.tb_total));
+        P.pair_tb_cap = words * 4;
+        P.pairws_bytes = align_up(B.off_tb + (size_t)std::max<int64_t>(words, 1) * 4, 256);
+        P.off_pairws = o; o = align_up(o + P.pairws_bytes, 256);
     }
-    P.chunk_first.push_back((int64_t)P.groups.size());
-    const int A = a->alphabet_size;
-    size_t o = 0;
-    P.off_slots = o; o = align_up(o + std::max<size_t>(P.slots.size(), 1) * sizeof(PairInfo), 256);
-    P.off_groups = o; o = align_up(o + std::max<size_t>(P.groups.size(), 1) * sizeof(PairGroup), 256);
-    P.off_subst = o; o = align_up(o + (size_t)A * A, 256);
-    P.table_bytes = o;
-    P.off_end = o; o = align_up(o + std::max<size_t>(P.slots.size(), 1) * 8, 256);
-    P.off_bnd = o; o = align_up(o + (size_t)std::max<int64_t>(P.bnd_total, 1) * 8, 256);
-    P.off_tpk = o; o = align_up(o + (size_t)std::max<int64_t>(P.tpk_total, 1) * 4, 256);
-    P.off_tb = o; o = align_up(o + (size_t)std::max<int64_t>(P.tb_max, 1) * 4, 256);
     P.total = o;
     return DSA_OK;
 }
@@ -710,9 +778,9 @@ static int upload_tables(hipStream_t st, void *dst, size_t bytes,
     return DSA_OK;
 }
 
-static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P) {
+static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t *ws,
+                     const uint8_t *t_codes) {
     hipStream_t st = (hipStream_t)a->stream;
-    uint8_t *ws = (uint8_t *)a->workspace;
     const int A = a->alphabet_size;
     if (P.traceback && (!out->cigar_ops || !out->cigar_off || !out->cigar_len))
         return fail(DSA_E_INVAL, "traceback needs cigar_ops, cigar_off and cigar_len");
@@ -726,7 +794,7 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P) {
     memset(&K, 0, sizeof(K));
     K.pairs = (const PairInfo *)(ws + P.off_slots);
     K.q_codes = a->q_codes;
-    K.t_codes = a->t_codes;
+    K.t_codes = t_codes;
     K.subst = (const int8_t *)(ws + P.off_subst);
     K.A = A;
     K.o = a->gap_open;
@@ -796,6 +864,18 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
     uint8_t *ws = (uint8_t *)a->workspace;
     const int64_t nq = a->n_q;
     const int A = a->alphabet_size;
+    // with top_k the search writes every target's result into the workspace
+    // and the top-K kernel fills the caller's n_q x K outputs
+    dsa_out so = *out;
+    if (P.K > 0) {
+        const size_t nres = (size_t)nq * db->n_targets;
+        so.score = (int32_t *)(ws + P.off_full);
+        so.q_end = so.score + nres;
+        so.t_end = so.q_end + nres;
+        so.status = (uint8_t *)(so.t_end + nres);
+        so.q_begin = nullptr;
+        so.t_begin = nullptr;
+    }
 
     // tables -> pinned staging -> workspace
     std::vector<QueryInfo> q32 = P.qinfo;
@@ -851,10 +931,10 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
     K.bnd = (uint2 *)(ws + P.off_bnd);
     K.bnd_slot_stride = db->bnd_slot_uint2;
     K.prof = (const uint32_t *)(ws + P.off_prof);
-    K.out_score = out->score;
-    K.out_qend = out->q_end;
-    K.out_tend = out->t_end;
-    K.out_status = out->status;
+    K.out_score = so.score;
+    K.out_qend = so.q_end;
+    K.out_tend = so.t_end;
+    K.out_status = so.status;
     K.n_t = db->n_targets;
     K.unit_flags = (int32_t *)(ws + P.off_flags);
     K.qflag = (const int32_t *)(ws + P.off_qflag);
@@ -893,8 +973,8 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
         pa.total_dwords = P.prof_dwords;
         HIPCHK(launch_profile16(pa, P.T, st));
     }
-    if (out->q_begin) HIPCHK(launch_fill_i32(out->q_begin, -1, nq * db->n_targets, st));
-    if (out->t_begin) HIPCHK(launch_fill_i32(out->t_begin, -1, nq * db->n_targets, st));
+    if (so.q_begin) HIPCHK(launch_fill_i32(so.q_begin, -1, nq * db->n_targets, st));
+    if (so.t_begin) HIPCHK(launch_fill_i32(so.t_begin, -1, nq * db->n_targets, st));
 
     const int cus = device_cus(dev);
     const int per_cu16 = std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(P.lds16, 1))));
@@ -950,10 +1030,10 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
     I.ends = P.ends;
     I.bnd = (uint2 *)(ws + P.off_ibnd);
     I.bnd_slot_stride = db->long_bnd_slot;
-    I.out_score = out->score;
-    I.out_qend = out->q_end;
-    I.out_tend = out->t_end;
-    I.out_status = out->status;
+    I.out_score = so.score;
+    I.out_qend = so.q_end;
+    I.out_tend = so.t_end;
+    I.out_status = so.status;
     I.n_t = db->n_targets;
     I.slot_target = db->d_slot_target;
     I.slot_len = db->d_slot_len;
@@ -1031,13 +1111,64 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
         E.t_len = db->d_len;
         E.q_rows = (const int32_t *)(ws + P.off_rows);
         E.n_rows = (int32_t)P.empty_rows.size();
-        E.out_score = out->score;
-        E.out_qend = out->q_end;
-        E.out_tend = out->t_end;
-        E.out_qbeg = out->q_begin;
-        E.out_tbeg = out->t_begin;
-        E.out_status = out->status;
+        E.out_score = so.score;
+        E.out_qend = so.q_end;
+        E.out_tend = so.t_end;
+        E.out_qbeg = so.q_begin;
+        E.out_tbeg = so.t_begin;
+        E.out_status = so.status;
         HIPCHK(launch_empty_queries(E, st));
+    }
+    if (P.K > 0) {
+        TopkArgs t;
+        memset(&t, 0, sizeof(t));
+        t.score = so.score;
+        t.qend = so.q_end;
+        t.tend = so.t_end;
+        t.status = so.status;
+        t.n_t = db->n_targets;
+        t.n_q = (int32_t)nq;
+        t.K = P.K;
+        t.positive_only = P.mode == DSA_LOCAL ? 1 : 0;
+        t.out_score = out->score;
+        t.out_qend = out->q_end;
+        t.out_tend = out->t_end;
+        t.out_tindex = out->t_index;
+        t.out_status = out->status;
+        t.hit_t = (int32_t *)(ws + P.off_hits);
+        if (!t.out_tindex) return fail(DSA_E_INVAL, "top_k needs out->t_index");
+        HIPCHK(launch_topk(t, st));
+        if (!P.traceback) {
+            if (out->q_begin) HIPCHK(launch_fill_i32(out->q_begin, -1, nq * P.K, st));
+            if (out->t_begin) HIPCHK(launch_fill_i32(out->t_begin, -1, nq * P.K, st));
+            return DSA_OK;
+        }
+        // traceback of the hits: read the hit list back (this waits for the
+        // search), then align each (query, hit) pair with the pairwise path
+        std::vector<int32_t> hits((size_t)nq * P.K);
+        HIPCHK(hipMemcpyAsync(hits.data(), t.hit_t, hits.size() * 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::vector<PairSpec> sp;
+        for (int64_t q = 0; q < nq; q++)
+            for (int k = 0; k < P.K; k++) {
+                const int32_t tg = hits[(size_t)q * P.K + k];
+                if (tg < 0) continue;
+                PairSpec x;
+                x.q_off = a->q_offsets[q];
+                x.m = a->q_offsets[q + 1] - a->q_offsets[q];
+                x.t_off = db->offsets[tg];
+                x.n = db->len[tg];
+                x.res = (int32_t)(q * P.K + k);
+                sp.push_back(x);
+            }
+        if (out->q_begin) HIPCHK(launch_fill_i32(out->q_begin, -1, nq * P.K, st));
+        if (out->t_begin) HIPCHK(launch_fill_i32(out->t_begin, -1, nq * P.K, st));
+        if (out->cigar_len) HIPCHK(launch_fill_i32(out->cigar_len, 0, nq * P.K, st));
+        if (sp.empty()) return DSA_OK;
+        PairPlan PP;
+        build_pair_plan(sp, nq * P.K, P.mode, P.ends, true, out->cigar_capacity, A, P.pair_tb_cap, PP);
+        if (PP.total > P.pairws_bytes) return fail(DSA_E_WORKSPACE, "hit traceback plan exceeds its workspace bound");
+        return run_pairs(a, out, PP, ws + P.off_pairws, db->d_codes);
     }
     return DSA_OK;
 }
@@ -1053,7 +1184,7 @@ extern "C" int dsa_align_batch(const dsa_args *args, const dsa_out *out) {
         if (args->workspace_bytes < PP.total)
             return fail(DSA_E_WORKSPACE, "workspace too small: need " + std::to_string(PP.total) + " bytes");
         if (((uintptr_t)args->workspace) & 255) return fail(DSA_E_INVAL, "workspace must be 256-byte aligned");
-        return run_pairs(args, out, PP);
+        return run_pairs(args, out, PP, (uint8_t *)args->workspace, args->t_codes);
     }
     Plan P;
     rc = make_plan(args, P);
