@@ -79,19 +79,18 @@ int timing_end(hipStream_t st, size_t slot) {
     return DSA_OK;
 }
 
-// Auxiliary stream per device for the wavefront kernel, which runs
-// concurrently with the inter-sequence kernel (fork / join with events on
-// the caller's stream; default priority).
+// Auxiliary stream for the wavefront kernel, which runs concurrently with the
+// inter-sequence kernel (fork / join with events on the caller's stream;
+// default priority).  One per calling thread and device, so concurrent
+// calls from different threads never share fork / join events.
 struct Aux {
-    std::mutex mu;
     hipStream_t s = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
 };
-Aux g_aux[64];
+thread_local Aux t_aux[64];
 
 int aux_get(int dev, Aux **out) {
-    Aux &A = g_aux[dev & 63];
-    std::lock_guard<std::mutex> lk(A.mu);
+    Aux &A = t_aux[dev & 63];
     if (!A.s) {
         HIPCHK(hipStreamCreateWithFlags(&A.s, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&A.fork, hipEventDisableTiming));
@@ -328,6 +327,11 @@ extern "C" int dsa_db_info(const dsa_db *db, int64_t *n_targets, int64_t *n_resi
 
 namespace {
 
+struct Round {
+    int64_t first = 0, inter = 0, count = 0;  // units [first, first + count), inter first
+    int64_t ifirst = 0, icount = 0;           // wavefront units
+};
+
 struct Plan {
     // DB search
     int T = 32;
@@ -335,11 +339,9 @@ struct Plan {
     bool persistent = true;
     bool force32 = false;
     int mode = 0, ends = 0;
-    std::vector<SearchUnit> units;  // int16 inter units, then int32-only rerun units of long groups
-    std::vector<int64_t> unit_first, unit_count, unit_inter;  // per query (plain form)
-    int64_t n_inter = 0;            // persistent form: units[0 .. n_inter) go to the int16 kernel
+    std::vector<SearchUnit> units;  // per round: int16 inter units, then int32-only rerun units
     std::vector<IntraUnit> iunits;
-    std::vector<int64_t> iunit_first, iunit_count;
+    std::vector<Round> rounds;
     int64_t budget = 64000;         // strips x columns above which a group goes to the wavefront kernel
     size_t ldsI = 0;
     std::vector<QueryInfo> qinfo;
@@ -575,11 +577,6 @@ int make_search_plan(const dsa_args *a, Plan &P) {
 
     const int64_t nq = a->n_q;
     P.qinfo.resize(nq);
-    P.unit_first.assign(nq, 0);
-    P.unit_count.assign(nq, 0);
-    P.unit_inter.assign(nq, 0);
-    P.iunit_first.assign(nq, 0);
-    P.iunit_count.assign(nq, 0);
     P.ldsI = intra16_lds_bytes(db->AP, A);
     for (int64_t q = 0; q < nq; q++) {
         const int64_t m = a->q_offsets[q + 1] - a->q_offsets[q];
@@ -595,93 +592,86 @@ int make_search_plan(const dsa_args *a, Plan &P) {
         P.prof_dwords += (int64_t)P.qinfo[q].strips * db->AP * db->AP * (P.T + 4);
         if (m == 0) P.empty_rows.push_back((int32_t)q);
     }
-    // int32 kernel uses T = 32 strips: keep one strip count per query for both
-    // by planning int16 with its own T and int32 with 32 (QueryInfo.strips is
-    // rewritten per pass on the device copy; see dsa_align_batch).
+    // Queries run in rounds that share the boundary-row buffers (one query
+    // slot per query of the round), bounding that memory independently of
+    // n_q.  The plain form uses rounds of one query and one launch per pass.
     const int wpb = P.wpb16;
-    std::vector<SearchUnit> inter, rerun;
-    for (int64_t q = 0; q < nq; q++) {
-        if (P.qinfo[q].len == 0) continue;
-        // groups from gc on go to the wavefront kernel: their inter-sequence
-        // unit would be one long sequential task (strips x columns > budget)
-        int64_t gc = db->n_groups;
-        for (int64_t g = db->long_group0; g < db->n_groups; g++)
-            if ((int64_t)P.qinfo[q].strips * db->grp[g].ncols > P.budget) { gc = g; break; }
-        const int32_t qslot = P.persistent ? (int32_t)q : 0;
-        const int64_t first_inter = (int64_t)inter.size();
-        for (int64_t g0 = 0; g0 < gc; g0 += wpb) {
-            SearchUnit U;
-            U.q = (int32_t)q;
-            U.g0 = (int32_t)g0;
-            U.ng = (int32_t)std::min<int64_t>(wpb, gc - g0);
-            U.qslot = qslot;
-            inter.push_back(U);
-        }
-        const int64_t first_rerun = (int64_t)rerun.size();
-        P.iunit_first[q] = (int64_t)P.iunits.size();
-        for (int64_t g = gc; g < db->n_groups; g++) {
-            SearchUnit R;
-            R.q = (int32_t)q;
-            R.g0 = (int32_t)g;
-            R.ng = 1;
-            R.qslot = qslot;
-            const int32_t ridx = (int32_t)rerun.size();
-            rerun.push_back(R);
-            const int64_t pbase = (g - db->long_group0) * (kGroup / 2);
-            for (int k = 0; k < kGroup / 2; k += kIntraWaves) {
-                IntraUnit I;
-                I.q = (int32_t)q;
-                I.lp0 = (int32_t)(pbase + k);
-                I.np = kIntraWaves;
-                I.runit = ridx;  // made absolute below
-                I.qslot = qslot;
-                I.pad = 0;
-                P.iunits.push_back(I);
+    const int64_t slot_bytes = db->bnd_slot_uint2 * 8 + std::max<int64_t>(db->long_bnd_slot, 1) * 8;
+    int64_t cap_bytes = (int64_t)8 << 30;
+    if (const char *v = getenv("DSA_BND_BUDGET")) cap_bytes = std::max<int64_t>(atoll(v), 1);
+    int64_t QS = P.persistent ? std::max<int64_t>(1, std::min<int64_t>(nq, cap_bytes / std::max<int64_t>(slot_bytes, 1))) : 1;
+    P.n_slots = (int)QS;
+    for (int64_t q0 = 0; q0 < nq; q0 += QS) {
+        const int64_t q1 = std::min(nq, q0 + QS);
+        std::vector<SearchUnit> inter, rerun;
+        std::vector<IntraUnit> iu;
+        for (int64_t q = q0; q < q1; q++) {
+            if (P.qinfo[q].len == 0) continue;
+            // groups from gc on go to the wavefront kernel: their inter-sequence
+            // unit would be one long sequential task (strips x columns > budget)
+            int64_t gc = db->n_groups;
+            for (int64_t g = db->long_group0; g < db->n_groups; g++)
+                if ((int64_t)P.qinfo[q].strips * db->grp[g].ncols > P.budget) { gc = g; break; }
+            const int32_t qslot = (int32_t)(q - q0);
+            for (int64_t g0 = 0; g0 < gc; g0 += wpb) {
+                SearchUnit U;
+                U.q = (int32_t)q;
+                U.g0 = (int32_t)g0;
+                U.ng = (int32_t)std::min<int64_t>(wpb, gc - g0);
+                U.qslot = qslot;
+                inter.push_back(U);
+            }
+            for (int64_t g = gc; g < db->n_groups; g++) {
+                SearchUnit R;
+                R.q = (int32_t)q;
+                R.g0 = (int32_t)g;
+                R.ng = 1;
+                R.qslot = qslot;
+                const int32_t ridx = (int32_t)rerun.size();
+                rerun.push_back(R);
+                const int64_t pbase = (g - db->long_group0) * (kGroup / 2);
+                for (int k = 0; k < kGroup / 2; k += kIntraWaves) {
+                    IntraUnit I;
+                    I.q = (int32_t)q;
+                    I.lp0 = (int32_t)(pbase + k);
+                    I.np = kIntraWaves;
+                    I.runit = ridx;  // made absolute below
+                    I.qslot = qslot;
+                    I.pad = 0;
+                    iu.push_back(I);
+                }
             }
         }
-        P.iunit_count[q] = (int64_t)P.iunits.size() - P.iunit_first[q];
-        P.unit_inter[q] = (int64_t)inter.size() - first_inter;
-        P.unit_count[q] = P.unit_inter[q] + ((int64_t)rerun.size() - first_rerun);
-        P.unit_first[q] = first_inter;  // provisional (plain layout fixed below)
-        (void)first_rerun;
-    }
-    if (P.persistent) {
-        // longest inter units first (strips x widest group); rerun units after
-        std::vector<int64_t> cost(inter.size());
-        for (size_t k = 0; k < inter.size(); k++) {
-            const SearchUnit &U = inter[k];
-            cost[k] = (int64_t)P.qinfo[U.q].len * db->grp[U.g0 + U.ng - 1].ncols;
+        if (P.persistent) {
+            // longest inter-sequence units first (strips x widest group)
+            std::vector<int64_t> cost(inter.size());
+            for (size_t k = 0; k < inter.size(); k++)
+                cost[k] = (int64_t)P.qinfo[inter[k].q].len * db->grp[inter[k].g0 + inter[k].ng - 1].ncols;
+            std::vector<size_t> idx(inter.size());
+            std::iota(idx.begin(), idx.end(), 0);
+            std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+            std::vector<SearchUnit> sorted;
+            for (size_t k : idx) sorted.push_back(inter[k]);
+            inter.swap(sorted);
+            std::stable_sort(iu.begin(), iu.end(), [&](const IntraUnit &x, const IntraUnit &y) {
+                const int64_t cx = (int64_t)P.qinfo[x.q].len * db->pairs[x.lp0 + x.np - 1].ncols;
+                const int64_t cy = (int64_t)P.qinfo[y.q].len * db->pairs[y.lp0 + y.np - 1].ncols;
+                return cx > cy;
+            });
         }
-        std::vector<size_t> idx(inter.size());
-        std::iota(idx.begin(), idx.end(), 0);
-        std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
-        for (size_t k = 0; k < idx.size(); k++) P.units.push_back(inter[idx[k]]);
-        P.n_inter = (int64_t)P.units.size();
-        for (auto &R : rerun) P.units.push_back(R);
-        for (auto &I : P.iunits) I.runit += (int32_t)P.n_inter;
-        // wavefront units: longest pairs first
-        std::stable_sort(P.iunits.begin(), P.iunits.end(), [&](const IntraUnit &x, const IntraUnit &y) {
-            const int64_t cx = (int64_t)P.qinfo[x.q].len * db->pairs[x.lp0 + x.np - 1].ncols;
-            const int64_t cy = (int64_t)P.qinfo[y.q].len * db->pairs[y.lp0 + y.np - 1].ncols;
-            return cx > cy;
-        });
-        P.n_slots = (int)std::max<int64_t>(1, nq);
-    } else {
-        // per query: its inter units, then its rerun units
-        size_t ii = 0, rr = 0;
-        for (int64_t q = 0; q < nq; q++) {
-            P.unit_first[q] = (int64_t)P.units.size();
-            for (int64_t k = 0; k < P.unit_inter[q]; k++) P.units.push_back(inter[ii++]);
-            const int64_t rbase = (int64_t)P.units.size();
-            const int64_t nr = P.unit_count[q] - P.unit_inter[q];
-            for (int64_t k = 0; k < nr; k++) P.units.push_back(rerun[rr + k]);
-            for (int64_t k = 0; k < P.iunit_count[q]; k++) {
-                IntraUnit &I = P.iunits[P.iunit_first[q] + k];
-                I.runit = (int32_t)(rbase + (I.runit - (int32_t)rr));
-            }
-            rr += nr;
+        Round R;
+        R.first = (int64_t)P.units.size();
+        R.inter = (int64_t)inter.size();
+        R.count = R.inter + (int64_t)rerun.size();
+        for (auto &U : inter) P.units.push_back(U);
+        for (auto &U : rerun) P.units.push_back(U);
+        R.ifirst = (int64_t)P.iunits.size();
+        R.icount = (int64_t)iu.size();
+        for (auto &I : iu) {
+            I.runit += (int32_t)(R.first + R.inter);
+            P.iunits.push_back(I);
         }
-        P.n_slots = 1;
+        if (R.count > 0) P.rounds.push_back(R);
     }
 
     // workspace layout
@@ -1074,27 +1064,15 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
     }
 
     int rc;
-    if (P.persistent) {
+    for (const Round &R : P.rounds) {
+        const SearchUnit *u = d_units + R.first;
         if (!P.force32) {
-            if ((rc = intra(d_iunits, (int64_t)P.iunits.size(), K.unit_flags))) return rc;
-            if ((rc = pass(d_units, P.n_inter, 0))) return rc;
-            if ((rc = join((int64_t)P.iunits.size()))) return rc;
-            if ((rc = pass(d_units, nunits, 1))) return rc;
-        } else if ((rc = pass(d_units, nunits, 0))) {
+            if ((rc = intra(d_iunits + R.ifirst, R.icount, K.unit_flags))) return rc;
+            if ((rc = pass(u, R.inter, 0))) return rc;
+            if ((rc = join(R.icount))) return rc;
+            if ((rc = pass(u, R.count, 1))) return rc;
+        } else if ((rc = pass(u, R.count, 0))) {
             return rc;
-        }
-    } else {
-        for (int64_t q = 0; q < nq; q++) {
-            if (P.unit_count[q] == 0) continue;
-            const SearchUnit *u = d_units + P.unit_first[q];
-            if (!P.force32) {
-                if ((rc = intra(d_iunits + P.iunit_first[q], P.iunit_count[q], K.unit_flags))) return rc;
-                if ((rc = pass(u, P.unit_inter[q], 0))) return rc;
-                if ((rc = join(P.iunit_count[q]))) return rc;
-                if ((rc = pass(u, P.unit_count[q], 1))) return rc;
-            } else if ((rc = pass(u, P.unit_count[q], 0))) {
-                return rc;
-            }
         }
     }
     {

@@ -158,3 +158,15 @@ def test_search_wavefront_overflow_rerun(blosum, monkeypatch):
     exp = oracle.search(Q, T, S, 40, 4, mode="local")
     compare_search(got, exp, len(Q), len(T), label="wavefront ovf")
     assert exp["score"].max() > 32767
+
+
+@pytest.mark.parametrize("mode,ends", CASES[:3])
+def test_search_rounds_of_one_query(mode, ends, blosum, monkeypatch):
+    """A tiny boundary-memory budget makes the persistent form run one query
+    per round (one query slot)."""
+    monkeypatch.setenv("DSA_BND_BUDGET", "1")
+    T = _targets(7, 300, 1200, extra=[1, 1300])
+    Q = _queries(8, [5, 40, 700, 1500])
+    got, _ = gpu_search(Q, T, blosum, 11, 1, mode, ends)
+    exp = oracle.search(Q, T, blosum, 11, 1, mode=mode, ends=ends)
+    compare_search(got, exp, len(Q), len(T), label=f"rounds {mode}")
