@@ -36,14 +36,16 @@ def log(msg):
 
 
 def source_hash():
-    p = os.path.join(ROOT, "paper_1701_01575_amd", "csrc", "search.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in ["search.hip", "intra.hip", "pk16.h", "internal.h", "runtime.hip"]:
+        h.update(open(os.path.join(ROOT, "paper_1701_01575_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(cells):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
-    or None when the kernel changed since it was taken."""
-    p = os.path.join(ROOT, "profiles", "search16_cfg2_pmc.json")
+    or None when the kernels changed since it was taken."""
+    p = os.path.join(ROOT, "profiles", "search_cfg2_pmc.json")
     if not os.path.exists(p):
         return None
     try:
@@ -199,11 +201,13 @@ def main():
         f"inter {tm['inter'][0] / max(tm['inter'][1], 1):.2f} ms x {tm['inter'][1]}, "
         f"wavefront {tm['intra'][0] / max(tm['intra'][1], 1):.2f} ms x {tm['intra'][1]}")
 
-    log(f"plain: 1 warmup + {args.plain_steps} timed steps")
-    pdt, _, _ = run(True, 1, args.plain_steps)
-    plain_ms = pdt / args.plain_steps * 1e3
-    plain_gcups = cells / (pdt / args.plain_steps) / 1e9
-    log(f"plain: {plain_ms:.2f} ms/step, {plain_gcups:.1f} GCUPS")
+    plain_ms = plain_gcups = None
+    if args.plain_steps > 0:
+        log(f"plain: 1 warmup + {args.plain_steps} timed steps")
+        pdt, _, _ = run(True, 1, args.plain_steps)
+        plain_ms = pdt / args.plain_steps * 1e3
+        plain_gcups = cells / (pdt / args.plain_steps) / 1e9
+        log(f"plain: {plain_ms:.2f} ms/step, {plain_gcups:.1f} GCUPS")
 
     achieved = cells * OPS_PER_CELL / (span_ms * 1e-3) / 1e12
     traffic = load_traffic(cells)
@@ -268,9 +272,10 @@ def main():
                                f"vs {nt} log-normal targets, BLOSUM62 11/1, local, score + end",
                    "cells": cells, "queries": nq, "targets": nt,
                    "residues": int(T.lengths.sum()), "form": "batched (persistent, LPT units)"},
-        "plain": {"value": round(plain_gcups, 2), "unit": "GCUPS", "ms_per_step": round(plain_ms, 3),
-                  "form": "one launch per query"},
-        "batched_over_plain": round(gcups / plain_gcups, 3),
+        "plain": None if plain_gcups is None else {
+            "value": round(plain_gcups, 2), "unit": "GCUPS", "ms_per_step": round(plain_ms, 3),
+            "form": "one launch per query"},
+        "batched_over_plain": None if plain_gcups is None else round(gcups / plain_gcups, 3),
         "db_pack_s": round(pack_s, 3),
         "int32_reruns": int((status & 1).sum()),
         "roofline": roofline,

@@ -1,0 +1,34 @@
+"""Measured ceilings on the current GPU (dsa_probe): VALU issue rate of the
+instructions the alignment kernels use, and an HBM copy of known size (also
+the reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE).
+
+    python paper_1701_01575_amd/probe.py            # all probes
+    python paper_1701_01575_amd/probe.py copy BYTES # one copy of BYTES
+"""
+import os
+import sys
+
+if __package__ in (None, ""):
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+from paper_1701_01575_amd import binding as B  # noqa: E402
+
+NAMES = ["v_pk_add_i16 (clamp)", "v_pk_max_i16", "v_pk_sub_u16 (clamp)", "v_add_u32", "v_max_i32"]
+
+
+def main(argv):
+    import torch
+    torch.cuda.init()
+    if len(argv) >= 2 and argv[0] == "copy":
+        r = B.dsa_probe(5, int(argv[1]))
+        print(f"copy of {int(argv[1])} bytes x 6 launches: {r / 1e9:.0f} GB/s (read + write)")
+        return
+    for w, n in enumerate(NAMES):
+        r = B.dsa_probe(w, 20000)
+        per16 = r * 2 if w < 3 else r
+        print(f"{n:22s} {r / 1e12:7.2f} T lane-instructions/s  ({per16 / 1e12:.2f} T 16-bit ops/s)")
+    r = B.dsa_probe(5, 4 << 30)
+    print(f"HBM copy of 4 GiB: {r / 1e9:.0f} GB/s (read + write)")
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
