@@ -109,6 +109,63 @@ def run_serving(args, dsa, B, torch, gen, dev):
     return out
 
 
+def run_other_workloads(args, dsa, B, torch, gen, dev):
+    """Batched vs plain on the other workloads, each timed after one warm-up
+    call: the single 64-residue query vs 1,000 targets (local, score + end),
+    100,000 DNA read / window pairs (local with CIGAR) and 50,000 protein
+    pairs of log-uniform length in [100, 3000] (global and semi-global with
+    CIGAR).  The plain pairwise form launches once per pair, so it is timed
+    on the first `plain_pairs` pairs of the same list."""
+    out = {}
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    c = gen.cfg1()
+    Q, T, S = c["queries"], c["targets"], c["matrix"]
+    db = dsa.Database.from_seqset(T, S.shape[0])
+    cells = int(Q.lengths.sum()) * int(T.lengths.sum())
+    r = {}
+    for form, plain in (("batched", False), ("plain", True)):
+        dt = timed(lambda: dsa.align(Q, db=db, matrix=S, gap_open=11, gap_extend=1, plain=plain,
+                                     force_int32=True), 20)
+        r[form] = {"gcups": round(cells / dt / 1e9, 3), "ms": round(dt * 1e3, 3)}
+    db.close()
+    out["single_query_64_vs_1000"] = dict(cells=cells, **r, note="int32 scores; host-side call "
+                                          "overhead included (Python marshalling + launch)")
+    log(f"64 x 1000 local: {r}")
+
+    def pair_leg(name, Q, T, S, o, e, mode, reps=2):
+        cells = int((Q.lengths * T.lengths).sum())
+        dt = timed(lambda: dsa.align(Q, targets=T, matrix=S, gap_open=o, gap_extend=e, mode=mode,
+                                     traceback=True), reps)
+        n = min(args.plain_pairs, len(Q))
+        Qs, Ts = Q.subset(list(range(n))), T.subset(list(range(n)))
+        pcells = int((Qs.lengths * Ts.lengths).sum())
+        pdt = timed(lambda: dsa.align(Qs, targets=Ts, matrix=S, gap_open=o, gap_extend=e, mode=mode,
+                                      traceback=True, plain=True), 1)
+        bg, pg = cells / dt / 1e9, pcells / pdt / 1e9
+        res = {"pairs": len(Q), "cells": cells, "batched": {"gcups": round(bg, 2), "ms": round(dt * 1e3, 2)},
+               "plain": {"gcups": round(pg, 3), "ms": round(pdt * 1e3, 2), "pairs": n, "cells": pcells},
+               "batched_over_plain": round(bg / pg, 1), "traceback": "CIGAR"}
+        log(f"{name}: {res}")
+        out[name] = res
+
+    c = gen.cfg3()
+    pair_leg("dna_read_mapping_100k_local", c["queries"], c["targets"], c["matrix"], 5, 2, "local")
+    del c
+    c = gen.cfg4()
+    for mode in ("global", "semiglobal"):
+        pair_leg(f"protein_pairs_50k_{mode}", c["queries"], c["targets"], c["matrix"], 10, 1, mode)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +178,9 @@ def main():
     ap.add_argument("--serving", type=int, default=8,
                     help="requests in the serving window (0 = skip the serving leg)")
     ap.add_argument("--serving-targets", type=int, default=500_000)
+    ap.add_argument("--other", type=int, default=1, help="1 = also time the other workloads")
+    ap.add_argument("--plain-pairs", type=int, default=500,
+                    help="pairs timed in the one-launch-per-pair form")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -251,6 +311,10 @@ def main():
                "agrees_with_gpu": agree}
         log(f"cpu oracle: {cpu['value']} GCUPS on {threads} threads, agrees={agree}")
 
+    other = None
+    if args.other:
+        other = run_other_workloads(args, dsa, B, torch, gen, dev)
+
     serving = None
     if args.serving > 0:
         serving = run_serving(args, dsa, B, torch, gen, dev)
@@ -281,6 +345,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "serving": serving,
+        "other_workloads": other,
     }
     print(json.dumps(line), flush=True)
 

@@ -81,6 +81,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pair32(PairArgs P) {
     if (act) I = P.pairs[slot];
     const int o = P.o, e = P.e, ends = P.ends;
     const int m = I.m, n = I.n, S = G.strips;
+    const int Sl = (m + T - 1) / T;  // this lane's own strip count (<= S)
     const uint8_t *qc = P.q_codes + I.q_off;
     const uint32_t *tw = P.tpk + G.tpk + lane;
     uint2 *bnd = P.bnd + G.bnd + lane;
@@ -90,7 +91,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pair32(PairArgs P) {
     int Gs = (MODE == LOCAL) ? 0 : PAD32, Gj = 0, Gi = 0;
     for (int s = 0; s < S; s++) {
         const int i0 = s * T;
-        const bool first = (s == 0), last = (s == S - 1);
+        const bool first = (s == 0), wave_last = (s == S - 1), last = (s == Sl - 1);
         int rowb[T], H[T], E[T];
 #pragma unroll
         for (int r = 0; r < T; r++) {
@@ -167,7 +168,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pair32(PairArgs P) {
                         Ls = vl; Lj = j;
                     }
                 }
-                if (!last) bnd[(int64_t)(j - 1) * kWave] = make_uint2((uint32_t)H[T - 1], (uint32_t)F);
+                if (!wave_last) bnd[(int64_t)(j - 1) * kWave] = make_uint2((uint32_t)H[T - 1], (uint32_t)F);
             }
         }
         if (MODE == LOCAL) {
@@ -180,7 +181,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pair32(PairArgs P) {
         }
     }
     if (!act) return;
-    if (S == 0) {  // empty query: the last row is the top boundary row
+    if (Sl == 0) {  // empty query: the last row is the top boundary row
         if (MODE == LOCAL) { Gs = 0; }
         else if (MODE == SEMIGLOBAL && (ends & TE)) { Gs = 0; Gj = 0; }
         else { Gs = top_value(MODE, ends, o, e, n); Gj = n; }

@@ -398,6 +398,7 @@ struct PairPlan {
     std::vector<int64_t> chunk_first;  // first group of each chunk (+ end)
     int64_t tb_max = 0;             // uint32 codes of the largest chunk
     int64_t tb_total = 0, tb_group_max = 0;
+    bool plain = false;  // one pair per group, input order; groups run one by one and share buffers
     int64_t bnd_total = 0, tpk_total = 0;
     bool capacity_short = false;
     size_t off_slots = 0, off_groups = 0, off_subst = 0, table_bytes = 0;
@@ -418,18 +419,22 @@ int64_t tb_budget_bytes() {
 // Group and lay out a list of pairs.  n_results sizes the CIGAR regions (one
 // per result index, in result order); tb_cap caps the codes of one chunk.
 void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mode, int ends,
-                     bool traceback, int64_t cigar_capacity, int A, int64_t tb_cap, PairPlan &P) {
+                     bool traceback, int64_t cigar_capacity, int A, int64_t tb_cap, PairPlan &P,
+                     bool plain = false) {
     const int64_t n = (int64_t)sp.size();
     P.mode = mode;
     P.ends = ends;
     P.traceback = traceback;
+    P.plain = plain;
     std::vector<int64_t> order(n);
     std::iota(order.begin(), order.end(), 0);
     auto strips = [&](int64_t k) { return (sp[k].m + kTP - 1) / kTP; };
-    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
-        if (strips(x) != strips(y)) return strips(x) > strips(y);
-        return sp[x].n > sp[y].n;
-    });
+    // batched: length-binned, longest first; plain: input order, one pair per group
+    if (!plain)
+        std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+            if (strips(x) != strips(y)) return strips(x) > strips(y);
+            return sp[x].n > sp[y].n;
+        });
     // CIGAR regions in result order: m + n + 1 runs each while capacity lasts
     std::vector<int64_t> need(std::max<int64_t>(n_results, 1), 0), roff(need.size(), 0), rcap(need.size(), 0);
     for (const auto &x : sp) need[x.res] = x.m + x.n + 1;
@@ -444,19 +449,60 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     }
     int64_t chunk_tb = 0;
     for (int64_t k = 0; k < n;) {
-        const int64_t S = strips(order[k]);
+        int64_t S = strips(order[k]);
         int64_t e = k;
-        while (e < n && e - k < kWave && strips(order[e]) == S) e++;
+        if (plain) {
+            e = k + 1;
+        } else {
+            while (e < n && e - k < kWave && strips(order[e]) == S) e++;
+        }
+        int64_t ncol = 0;
+        for (int64_t x = k; x < e; x++) {
+            S = std::max(S, strips(order[x]));
+            ncol = std::max(ncol, sp[order[x]].n);
+        }
         PairGroup G;
-        G.ncols = (int32_t)align_up((size_t)sp[order[k]].n, kPadLen);
+        G.ncols = (int32_t)align_up((size_t)ncol, kPadLen);
         G.strips = (int32_t)S;
         G.p0 = (int32_t)(P.groups.size() * kWave);
         G.np = (int32_t)(e - k);
+        const int64_t tb_words = traceback ? (int64_t)S * G.ncols * 2 * kWave : 0;
+        if (plain) {
+            // launched one at a time on one stream: every group reuses the same
+            // boundary, packed-target and code regions
+            G.bnd = 0;
+            G.tpk = 0;
+            G.tb = 0;
+            P.bnd_total = std::max(P.bnd_total, (int64_t)G.ncols * kWave);
+            P.tpk_total = std::max(P.tpk_total, (int64_t)(G.ncols / 4) * kWave);
+            if (P.groups.empty()) P.chunk_first.push_back(0);
+            P.tb_max = std::max(P.tb_max, tb_words);
+            P.tb_total += tb_words;
+            P.tb_group_max = std::max(P.tb_group_max, tb_words);
+            P.groups.push_back(G);
+            P.slots.push_back(PairInfo{});
+            PairInfo &I = P.slots.back();
+            const PairSpec &x = sp[order[k]];
+            memset(&I, 0, sizeof(I));
+            I.q_off = x.q_off;
+            I.t_off = x.t_off;
+            I.m = (int32_t)x.m;
+            I.n = (int32_t)x.n;
+            I.res = x.res;
+            I.cig_off = roff[x.res];
+            I.cig_cap = (int32_t)rcap[x.res];
+            for (int lane = 1; lane < kWave; lane++) {
+                P.slots.push_back(PairInfo{});
+                memset(&P.slots.back(), 0, sizeof(PairInfo));
+                P.slots.back().res = -1;
+            }
+            k = e;
+            continue;
+        }
         G.bnd = P.bnd_total;
         G.tpk = P.tpk_total;
         P.bnd_total += (int64_t)G.ncols * kWave;
         P.tpk_total += (int64_t)(G.ncols / 4) * kWave;
-        const int64_t tb_words = traceback ? (int64_t)S * G.ncols * 2 * kWave : 0;
         if (P.groups.empty() || (chunk_tb > 0 && (chunk_tb + tb_words) * 4 > tb_cap)) {
             P.chunk_first.push_back((int64_t)P.groups.size());
             chunk_tb = 0;
@@ -529,7 +575,7 @@ int make_pair_plan(const dsa_args *a, const dsa_out *out, PairPlan &P) {
     }
     const bool tb = (a->flags & DSA_TRACEBACK) != 0;
     build_pair_plan(sp, n, a->mode, ends, tb, (tb && out) ? out->cigar_capacity : 0, a->alphabet_size,
-                    tb_budget_bytes(), P);
+                    tb_budget_bytes(), P, (a->flags & DSA_PLAIN) != 0);
     return DSA_OK;
 }
 
@@ -805,6 +851,21 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
     K.cig_off_out = out->cigar_off;
     K.cig_len_out = out->cigar_len;
     K.cigar = out->cigar_ops;
+    if (P.plain) {  // one pair at a time: pack, fill, walk
+        const PairGroup *dg = (const PairGroup *)(ws + P.off_groups);
+        for (size_t g = 0; g < P.groups.size(); g++) {
+            PairArgs k1 = K;
+            k1.groups = dg + g;
+            k1.n_groups = 1;
+            k1.pairs = K.pairs + g * kWave;
+            k1.end_i = K.end_i + g * kWave;
+            k1.end_j = K.end_j + g * kWave;
+            HIPCHK(launch_pack_targets(k1, (int64_t)(P.groups[g].ncols / 4) * kWave, st));
+            HIPCHK(launch_pair32(k1, P.mode, st));
+            if (P.traceback) HIPCHK(launch_walk(k1, P.mode, 0, kWave, st));
+        }
+        return P.capacity_short ? fail(DSA_E_CAPACITY, "CIGAR capacity too small; see status bit 1") : DSA_OK;
+    }
     // pack every group's targets once
     {
         PairArgs k = K;

@@ -88,6 +88,20 @@ def test_pairs_strip_edges(mode, ends, dna):
     compare_pairs(got, exp, True, f"edges {mode}")
 
 
+@pytest.mark.parametrize("mode,ends", CASES[:3] + [("semiglobal", 1 | 8)])
+def test_pairs_plain(mode, ends, blosum):
+    """The plain form (one launch per pair, input order) gives the batched results."""
+    Q, T = _pairs(15, 90, 0, 140, 20)
+    Q2, T2 = _pairs(16, 40, 30, 260, 20, related=True)
+    Q = SeqSet.from_list([Q[k] for k in range(len(Q))] + [Q2[k] for k in range(len(Q2))])
+    T = SeqSet.from_list([T[k] for k in range(len(T))] + [T2[k] for k in range(len(T2))])
+    got = gpu_pairs(Q, T, blosum, 10, 1, mode, ends, plain=True)
+    exp = oracle.align_pairs(Q, T, blosum, 10, 1, mode=mode, ends=ends, traceback=True)
+    compare_pairs(got, exp, True, f"plain {mode}/{ends}")
+    got = gpu_pairs(Q, T, blosum, 10, 1, mode, ends, traceback=False, plain=True)
+    compare_pairs(got, exp, False, f"plain score-only {mode}/{ends}")
+
+
 def test_pairs_chunked_codes(blosum, monkeypatch):
     monkeypatch.setenv("DSA_TB_BUDGET", str(1 << 20))  # many chunks of direction codes
     Q, T = _pairs(13, 400, 20, 300, 20, related=True)
