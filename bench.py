@@ -143,15 +143,29 @@ def run_other_workloads(args, dsa, B, torch, gen, dev):
 
     def pair_leg(name, Q, T, S, o, e, mode, reps=2):
         cells = int((Q.lengths * T.lengths).sum())
-        dt = timed(lambda: dsa.align(Q, targets=T, matrix=S, gap_open=o, gap_extend=e, mode=mode,
-                                     traceback=True), reps)
+        call = lambda: dsa.align(Q, targets=T, matrix=S, gap_open=o, gap_extend=e, mode=mode,  # noqa: E731
+                                 traceback=True)
+        call()
+        torch.cuda.synchronize()
+        B.dsa_timing_reset()
+        B.dsa_timing_enable(True)
+        dt = timed(call, reps)
+        dev_ms = {}
+        for nm, kind in (("span", B.TIMING_SPAN), ("lane", B.TIMING_PAIR_LANE), ("wavefront", B.TIMING_PAIR_WF)):
+            tot, cnt = B.dsa_timing_read(kind)
+            dev_ms[nm] = round(tot / max(cnt, 1), 3)
+        B.dsa_timing_enable(False)
+        B.dsa_timing_reset()
         n = min(args.plain_pairs, len(Q))
         Qs, Ts = Q.subset(list(range(n))), T.subset(list(range(n)))
         pcells = int((Qs.lengths * Ts.lengths).sum())
         pdt = timed(lambda: dsa.align(Qs, targets=Ts, matrix=S, gap_open=o, gap_extend=e, mode=mode,
                                       traceback=True, plain=True), 1)
         bg, pg = cells / dt / 1e9, pcells / pdt / 1e9
-        res = {"pairs": len(Q), "cells": cells, "batched": {"gcups": round(bg, 2), "ms": round(dt * 1e3, 2)},
+        dg = cells / (dev_ms["span"] * 1e-3) / 1e9
+        res = {"pairs": len(Q), "cells": cells,
+               "batched": {"gcups": round(bg, 2), "ms": round(dt * 1e3, 2), "device_gcups": round(dg, 2),
+                           "device_ms": dev_ms},
                "plain": {"gcups": round(pg, 3), "ms": round(pdt * 1e3, 2), "pairs": n, "cells": pcells},
                "batched_over_plain": round(bg / pg, 1), "traceback": "CIGAR"}
         log(f"{name}: {res}")

@@ -183,8 +183,11 @@ int dsa_align_batch(const dsa_args *args, const dsa_out *out);
  * Measurement hooks.  dsa_timing_enable(1) makes dsa_align_batch record HIP
  * event pairs on the stream each kernel is launched on: kind 0 = the whole
  * search phase on args->stream (both search kernels, from the fork to the
- * join), 1 = each launch of the inter-sequence kernel, 2 = each launch of
- * the wavefront kernel (on the library's auxiliary stream).
+ * join), or the whole pairwise phase (fill and walk of both pair kinds),
+ * 1 = each launch of the inter-sequence kernel, 2 = each launch of the
+ * wavefront search kernel (on the library's auxiliary stream), 3 = all
+ * lane-per-pair fill + walk launches of one call, 4 = all wavefront-pair
+ * fill + walk launches of one call (auxiliary stream when both kinds run).
  * dsa_timing_read(kind, ...) waits for that kind's events and returns the
  * summed milliseconds and the launch count; dsa_timing_reset clears the
  * record.  Used by the benchmark to time the dominant kernels; off by default.

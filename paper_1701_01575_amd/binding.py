@@ -149,7 +149,7 @@ def dsa_timing_enable(on: bool):
     check(lib().dsa_timing_enable(1 if on else 0), "dsa_timing_enable")
 
 
-TIMING_SPAN, TIMING_INTER, TIMING_INTRA = 0, 1, 2
+TIMING_SPAN, TIMING_INTER, TIMING_INTRA, TIMING_PAIR_LANE, TIMING_PAIR_WF = 0, 1, 2, 3, 4
 
 
 def dsa_timing_read(kind: int = TIMING_SPAN):

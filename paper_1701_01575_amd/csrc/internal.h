@@ -131,10 +131,20 @@ struct PairGroup {
     int32_t np;       // pairs (<= 64)
 };
 
+// A pair filled by the wavefront kernel (one wave per pair).
+struct WfPair {
+    int64_t tb;       // first uint2 of its direction codes (chunk-relative)
+    int64_t bnd;      // first uint2 of its boundary row between passes (n entries)
+    int32_t slot;     // its PairInfo and end-cell slot
+    int32_t pad;
+};
+
 struct PairArgs {
     const PairInfo *pairs;
     const PairGroup *groups;
     int32_t n_groups;
+    const WfPair *wf;             // wavefront pairs of this launch
+    int32_t n_wf;
     const uint8_t *q_codes, *t_codes;
     const int8_t *subst;
     int32_t A, o, e, ends;
@@ -152,6 +162,8 @@ struct PairArgs {
 hipError_t launch_pack_targets(const PairArgs &a, int64_t n_words, hipStream_t s);
 hipError_t launch_pair32(const PairArgs &a, int mode, hipStream_t s);
 hipError_t launch_walk(const PairArgs &a, int mode, int64_t slot0, int64_t n_slots, hipStream_t s);
+hipError_t launch_pairwf(const PairArgs &a, int mode, hipStream_t s);
+hipError_t launch_walk_wf(const PairArgs &a, int mode, hipStream_t s);
 size_t pair32_lds_bytes(int A);
 
 struct TopkArgs {

@@ -217,6 +217,191 @@ hipError_t launch_pair32(const PairArgs &a, int mode, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Wavefront fill for large pairs: one wave per pair.  Lane l owns rows
+// [16 s, 16 s + 16) of strip s = 64 * pass + l and at step t computes
+// column t - l + 1, so the row above (lane l - 1's last row one step
+// earlier) and the F leaving it arrive by a lane shuffle; between passes
+// lane 63's last row goes through the pair's boundary row in HBM.  Exact
+// int32, the same recurrence, direction codes and end-cell rule as
+// k_pair32.  A lane's 16 codes of one step are 64 bits, stored at
+// (pass, step, lane) so that each step's store is 512 contiguous bytes.
+template <int MODE, bool TB>
+__global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
+    constexpr int T = kTP;
+    extern __shared__ int32_t sm[];
+    const int A = P.A, SS = P.A + 1;
+    for (int k = threadIdx.x; k < SS * SS; k += blockDim.x) {
+        const int r = k / SS, c = k - r * SS;
+        sm[k] = (r < A && c < A) ? (int)P.subst[r * A + c] : PAD32;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int w = blockIdx.x * kPairWaves + wave;
+    if (w >= P.n_wf) return;  // no block barrier below this point
+    const WfPair W = P.wf[w];
+    const PairInfo I = P.pairs[W.slot];
+    const int o = P.o, e = P.e, ends = P.ends;
+    const int m = I.m, n = I.n;
+    const int S = (m + T - 1) / T, passes = (S + kWave - 1) / kWave;
+    const int nsteps = n + kWave - 1;
+    const uint8_t *qc = P.q_codes + I.q_off, *tc = P.t_codes + I.t_off;
+    uint2 *bnd = P.bnd + W.bnd;
+    uint2 *tb = reinterpret_cast<uint2 *>(P.tb) + W.tb + lane;
+
+    uint64_t gk = end_key(0, 0, 0);  // local: this lane's best over its strips
+    int gs = 0, gj = 0;              // global / semi: held by the lane of the last strip
+    for (int pass = 0; pass < passes; pass++) {
+        const int s = pass * kWave + lane;
+        const bool act = s < S, last = (s == S - 1);
+        const int i0 = s * T;
+        int rowb[T], H[T], E[T];
+#pragma unroll
+        for (int r = 0; r < T; r++) {
+            const int i = i0 + r;
+            rowb[r] = (i < m ? min((int)qc[i], A - 1) : A) * SS;
+            H[r] = left_value(MODE, ends, o, e, i + 1);
+            E[r] = H[r] - o;
+        }
+        int Hd_top = left_value(MODE, ends, o, e, i0);
+        int B = 0, Bj = 0, Bi = 0;
+        const int rlast = m - 1 - i0;
+        int res = 0, Ls = 0, Lj = 0;
+        if (MODE != LOCAL && last) { res = left_value(MODE, ends, o, e, m); Ls = res; }
+        int outH = 0, outF = 0;
+        // the next step's target code, and lane 0's next boundary word
+        int cnext = (lane == 0 && act && n > 0) ? (int)tc[0] : 0;
+        uint2 bnext = make_uint2(0u, 0u);
+        if (lane == 0 && pass > 0 && n > 0) bnext = bnd[0];
+        for (int t = 0; t < nsteps; t++) {
+            int rH = __shfl_up(outH, 1, kWave);
+            int rF = __shfl_up(outF, 1, kWave);
+            const int j = t - lane + 1;
+            const int cc = cnext;
+            const uint2 bc = bnext;
+            if (act && j >= 0 && j < n) cnext = (int)tc[j];
+            if (lane == 0 && pass > 0 && j < n) bnext = bnd[j];
+            if (act && j >= 1 && j <= n) {
+                if (lane == 0) {
+                    if (pass == 0) {
+                        rH = top_value(MODE, ends, o, e, j);
+                        rF = rH - o;
+                    } else {
+                        rH = (int)bc.x;
+                        rF = (int)bc.y;
+                    }
+                }
+                const int b = min(cc, A - 1);
+                int Hd = Hd_top;
+                Hd_top = rH;
+                int F = rF;
+                int ho_up = rH - o;
+                int cm = 0;
+                uint32_t acc[2] = {0u, 0u};
+#pragma unroll
+                for (int r = 0; r < T; r++) {
+                    const int tv = Hd + sm[rowb[r] + b];
+                    const int Hold = H[r];
+                    Hd = Hold;
+                    const int Ein = E[r], Fin = F;
+                    int h = max(max(tv, Ein), Fin);
+                    if (MODE == LOCAL) { h = max(h, 0); cm = max(cm, h); }
+                    const int ho = h - o;
+                    E[r] = max(Ein - e, ho);
+                    F = max(Fin - e, ho);
+                    H[r] = h;
+                    if (TB) {
+                        uint32_t src = (h == tv) ? 1u : ((h == Ein) ? 2u : 3u);
+                        if (MODE == LOCAL && h == 0) src = 0u;
+                        const uint32_t eext = (Ein != Hold - o) ? 4u : 0u;
+                        const uint32_t fext = (Fin != ho_up) ? 8u : 0u;
+                        acc[r >> 3] |= (src | eext | fext) << (4 * (r & 7));
+                    }
+                    ho_up = ho;
+                }
+                if (TB) tb[((int64_t)pass * nsteps + t) * kWave] = make_uint2(acc[0], acc[1]);
+                if (MODE == LOCAL) {
+                    if (cm > B) {
+                        int rr = 0;
+#pragma unroll
+                        for (int r = T - 1; r >= 0; r--) rr = (H[r] == cm) ? r : rr;
+                        B = cm; Bj = j; Bi = i0 + rr + 1;
+                    }
+                } else if (last) {
+                    int vl = H[0];
+#pragma unroll
+                    for (int k = 1; k < T; k++) vl = (k == rlast) ? H[k] : vl;
+                    if (!(ends & TE)) {
+                        if (j == n) res = vl;
+                    } else if (vl > Ls) {
+                        Ls = vl; Lj = j;
+                    }
+                }
+                outH = H[T - 1];
+                outF = F;
+                if (lane == kWave - 1 && pass + 1 < passes)
+                    bnd[j - 1] = make_uint2((uint32_t)outH, (uint32_t)outF);
+            }
+        }
+        if (act) {
+            if (MODE == LOCAL) {
+                if (B > 0) gk = umax64(gk, end_key(B, Bj, Bi));
+            } else if (last) {
+                if (ends & TE) { gs = Ls; gj = Lj; }
+                else { gs = res; gj = n; }
+            }
+        }
+    }
+    int Gs, Gj, Gi;
+    if (MODE == LOCAL) {
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)gk, d, kWave);
+            const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(gk >> 32), d, kWave);
+            gk = umax64(gk, ((uint64_t)hi << 32) | lo);
+        }
+        Gs = key_score(gk); Gj = key_j(gk); Gi = key_i(gk);
+    } else {
+        const int src = S > 0 ? (S - 1) % kWave : 0;
+        Gs = __shfl(gs, src, kWave);
+        Gj = __shfl(gj, src, kWave);
+        Gi = m;
+    }
+    if (lane != 0) return;
+    if (S == 0) {  // empty query: the last row is the top boundary row
+        if (MODE == LOCAL) { Gs = 0; }
+        else if (MODE == SEMIGLOBAL && (ends & TE)) { Gs = 0; Gj = 0; }
+        else { Gs = top_value(MODE, ends, o, e, n); Gj = n; }
+        Gi = 0;
+    }
+    int qe, te;
+    if (MODE == LOCAL) { qe = Gs > 0 ? Gi - 1 : -1; te = Gs > 0 ? Gj - 1 : -1; }
+    else { qe = m - 1; te = Gj - 1; }
+    P.out_score[I.res] = Gs;
+    if (P.out_qend) P.out_qend[I.res] = qe;
+    if (P.out_tend) P.out_tend[I.res] = te;
+    if (P.out_status) P.out_status[I.res] = 1;  // DSA_ST_INT32: exact int32 fill
+    if (TB) {
+        P.end_i[W.slot] = (MODE == LOCAL && Gs == 0) ? -1 : Gi;
+        P.end_j[W.slot] = Gj;
+    } else {
+        if (P.out_qbeg) P.out_qbeg[I.res] = -1;
+        if (P.out_tbeg) P.out_tbeg[I.res] = -1;
+    }
+}
+
+hipError_t launch_pairwf(const PairArgs &a, int mode, hipStream_t s) {
+    if (a.n_wf <= 0) return hipSuccess;
+    const int nb = (a.n_wf + kPairWaves - 1) / kPairWaves;
+    const size_t lds = pair32_lds_bytes(a.A);
+#define LP(MODE, TBV) hipLaunchKernelGGL((k_pairwf<MODE, TBV>), dim3(nb), dim3(kPairWaves * kWave), lds, s, a)
+    if (a.traceback) {
+        if (mode == LOCAL) LP(LOCAL, true); else if (mode == GLOBAL) LP(GLOBAL, true); else LP(SEMIGLOBAL, true);
+    } else {
+        if (mode == LOCAL) LP(LOCAL, false); else if (mode == GLOBAL) LP(GLOBAL, false); else LP(SEMIGLOBAL, false);
+    }
+#undef LP
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Traceback walk: one thread per pair slot.
 
@@ -240,17 +425,11 @@ struct RunWriter {
 
 constexpr uint32_t OP_I = 1, OP_D = 2, OP_EQ = 7, OP_X = 8;
 
-template <int MODE>
-__global__ void k_walk(PairArgs P, int64_t slot0, int64_t n_slots) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_slots) return;
-    const int64_t slot = slot0 + k;
-    const int g = (int)(slot / kWave), lane = (int)(slot % kWave);
-    const PairGroup G = P.groups[g];
-    if (lane >= G.np) return;
-    const PairInfo I = P.pairs[slot];
+// Walk one pair back from its end cell (1-based i, j; i < 0 = nothing to
+// trace) through the direction codes that code(i, j) returns.
+template <int MODE, class Code>
+__device__ void walk_pair(const PairArgs &P, const PairInfo &I, int i, int j, Code code) {
     const int ends = P.ends;
-    int i = P.end_i[slot], j = P.end_j[slot];
     RunWriter W{P.cigar, I.cig_off, I.cig_off + I.cig_cap};
     if (i < 0) {  // local alignment of score 0: nothing to trace
         if (P.out_qbeg) P.out_qbeg[I.res] = -1;
@@ -260,13 +439,6 @@ __global__ void k_walk(PairArgs P, int64_t slot0, int64_t n_slots) {
         return;
     }
     const uint8_t *qc = P.q_codes + I.q_off, *tc = P.t_codes + I.t_off;
-    const uint32_t *tb = P.tb + G.tb + lane;
-    const int ncols = G.ncols;
-    auto code = [&](int ii, int jj) -> uint32_t {
-        const int s = (ii - 1) / kTP, r = (ii - 1) % kTP;
-        const uint32_t w = tb[(((int64_t)s * ncols + (jj - 1)) * 2 + (r >> 3)) * kWave];
-        return (w >> (4 * (r & 7))) & 15u;
-    };
     int state = 0;  // 0 = H, 1 = E, 2 = F
     const int max_steps = I.m + I.n + 2;
     for (int step = 0; step < max_steps; step++) {
@@ -305,6 +477,52 @@ __global__ void k_walk(PairArgs P, int64_t slot0, int64_t n_slots) {
     P.cig_off_out[I.res] = W.pos;
     P.cig_len_out[I.res] = (int32_t)(I.cig_off + I.cig_cap - W.pos);
     if (W.truncated && P.out_status) P.out_status[I.res] |= 2;  // DSA_ST_TRUNCATED
+}
+
+// Walk of the lane-per-pair kernel's pairs: one thread per pair slot.
+template <int MODE>
+__global__ void k_walk(PairArgs P, int64_t slot0, int64_t n_slots) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_slots) return;
+    const int64_t slot = slot0 + k;
+    const int g = (int)(slot / kWave), lane = (int)(slot % kWave);
+    const PairGroup G = P.groups[g];
+    if (lane >= G.np) return;
+    const PairInfo I = P.pairs[slot];
+    const uint32_t *tb = P.tb + G.tb + lane;
+    const int ncols = G.ncols;
+    walk_pair<MODE>(P, I, P.end_i[slot], P.end_j[slot], [&](int ii, int jj) -> uint32_t {
+        const int s = (ii - 1) / kTP, r = (ii - 1) % kTP;
+        const uint32_t w = tb[(((int64_t)s * ncols + (jj - 1)) * 2 + (r >> 3)) * kWave];
+        return (w >> (4 * (r & 7))) & 15u;
+    });
+}
+
+// Walk of the wavefront kernel's pairs: one thread per pair.
+template <int MODE>
+__global__ void k_walk_wf(PairArgs P) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P.n_wf) return;
+    const WfPair W = P.wf[k];
+    const PairInfo I = P.pairs[W.slot];
+    const uint32_t *tb = P.tb + 2 * W.tb;
+    const int64_t nsteps = I.n + kWave - 1;
+    walk_pair<MODE>(P, I, P.end_i[W.slot], P.end_j[W.slot], [&](int ii, int jj) -> uint32_t {
+        const int s = (ii - 1) / kTP, r = (ii - 1) % kTP;
+        const int pass = s / kWave, lane = s % kWave;
+        const uint32_t w = tb[(((int64_t)pass * nsteps + (jj - 1 + lane)) * kWave + lane) * 2 + (r >> 3)];
+        return (w >> (4 * (r & 7))) & 15u;
+    });
+}
+
+hipError_t launch_walk_wf(const PairArgs &a, int mode, hipStream_t s) {
+    if (a.n_wf <= 0) return hipSuccess;
+    const int bs = 64;
+    const unsigned nb = (unsigned)((a.n_wf + bs - 1) / bs);
+    if (mode == LOCAL) hipLaunchKernelGGL(k_walk_wf<LOCAL>, dim3(nb), dim3(bs), 0, s, a);
+    else if (mode == GLOBAL) hipLaunchKernelGGL(k_walk_wf<GLOBAL>, dim3(nb), dim3(bs), 0, s, a);
+    else hipLaunchKernelGGL(k_walk_wf<SEMIGLOBAL>, dim3(nb), dim3(bs), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_walk(const PairArgs &a, int mode, int64_t slot0, int64_t n_slots, hipStream_t s) {

@@ -45,7 +45,7 @@ Staging g_staging[64];
 
 // Optional kernel timing (dsa_timing_enable / dsa_timing_read): event pairs
 // recorded on the stream a kernel is launched on, grouped by kind.
-enum TimingKind { TK_SPAN = 0, TK_INTER = 1, TK_INTRA = 2, TK_KINDS = 3 };
+enum TimingKind { TK_SPAN = 0, TK_INTER = 1, TK_INTRA = 2, TK_PAIR_LANE = 3, TK_PAIR_WF = 4, TK_KINDS = 5 };
 struct Timing {
     std::mutex mu;
     bool on = false;
@@ -332,6 +332,25 @@ struct Round {
     int64_t ifirst = 0, icount = 0;           // wavefront units
 };
 
+// Pairwise routing and region sizes (used by the pairwise plan below).
+struct PairRoute {
+    int64_t rows = 384;      // wavefront iff m >= rows ...
+    int64_t cells = 262144;  // ... and m * n >= cells
+};
+
+PairRoute pair_route() {
+    PairRoute r;
+    if (const char *v = getenv("DSA_PAIR_WF_ROWS")) r.rows = std::max<int64_t>(atoll(v), 1);
+    if (const char *v = getenv("DSA_PAIR_WF_CELLS")) r.cells = std::max<int64_t>(atoll(v), 0);
+    return r;
+}
+
+// Sizes of a plan's device regions; a plan may be laid out with larger ones
+// (the hit traceback lays out its plan in a workspace sized for the worst case).
+struct PairCaps {
+    int64_t slots = 0, groups = 0, wf = 0, bnd = 0, tpk = 0, tb = 0, bndw = 0, tbw = 0;
+};
+
 struct Plan {
     // DB search
     int T = 32;
@@ -356,7 +375,7 @@ struct Plan {
     int K = 0;
     bool traceback = false;
     size_t off_full = 0, off_hits = 0, off_pairws = 0, pairws_bytes = 0;
-    int64_t pair_tb_cap = 0;
+    PairCaps pair_caps;
     int64_t prof_dwords = 0;
     int32_t min_s = 0, max_abs_s = 0;
 };
@@ -387,9 +406,11 @@ int check_common(const dsa_args *a) {
     return DSA_OK;
 }
 
-// Pairwise plan: pairs sorted by (strips, target length), longest first,
-// into groups of 64 lanes sharing a strip count; direction codes chunked to a
-// byte budget (fill then walk per chunk).
+// Pairwise plan.  Large pairs (query rows and cells above the routing
+// thresholds) go to the wavefront kernel, one wave each, longest first; the
+// rest are sorted by (strips, target length), longest first, into groups of
+// 64 lanes sharing a strip count.  Each kind's direction codes are chunked to
+// a byte budget (fill then walk per chunk); the two kinds run concurrently.
 struct PairPlan {
     int mode = 0, ends = 0;
     bool traceback = false;
@@ -401,9 +422,43 @@ struct PairPlan {
     bool plain = false;  // one pair per group, input order; groups run one by one and share buffers
     int64_t bnd_total = 0, tpk_total = 0;
     bool capacity_short = false;
-    size_t off_slots = 0, off_groups = 0, off_subst = 0, table_bytes = 0;
-    size_t off_end = 0, off_bnd = 0, off_tpk = 0, off_tb = 0, total = 0;
+    std::vector<WfPair> wf;             // wavefront pairs; their slots follow the groups'
+    std::vector<int64_t> wf_chunk_first;
+    int64_t wf_tb_max = 0, wf_tb_total = 0, wf_bnd_total = 0;  // uint32 / uint32 / uint2
+    std::vector<std::pair<int, int64_t>> plain_seq;  // plain: (0 group | 1 wavefront, index) in input order
+    size_t off_slots = 0, off_groups = 0, off_wf = 0, off_subst = 0, table_bytes = 0;
+    size_t off_end = 0, off_bnd = 0, off_tpk = 0, off_tb = 0, off_bndw = 0, off_tbw = 0, total = 0;
 };
+
+PairCaps caps_of(const PairPlan &P) {
+    PairCaps c;
+    c.slots = (int64_t)P.slots.size();
+    c.groups = (int64_t)P.groups.size();
+    c.wf = (int64_t)P.wf.size();
+    c.bnd = P.bnd_total;
+    c.tpk = P.tpk_total;
+    c.tb = P.tb_max;
+    c.bndw = P.wf_bnd_total;
+    c.tbw = P.wf_tb_max;
+    return c;
+}
+
+void layout_pair_plan(PairPlan &P, const PairCaps &c, int A) {
+    auto cnt = [](int64_t v) { return (size_t)std::max<int64_t>(v, 1); };
+    size_t o = 0;
+    P.off_slots = o; o = align_up(o + cnt(c.slots) * sizeof(PairInfo), 256);
+    P.off_groups = o; o = align_up(o + cnt(c.groups) * sizeof(PairGroup), 256);
+    P.off_wf = o; o = align_up(o + cnt(c.wf) * sizeof(WfPair), 256);
+    P.off_subst = o; o = align_up(o + (size_t)A * A, 256);
+    P.table_bytes = o;
+    P.off_end = o; o = align_up(o + cnt(c.slots) * 8, 256);
+    P.off_bnd = o; o = align_up(o + cnt(c.bnd) * 8, 256);
+    P.off_tpk = o; o = align_up(o + cnt(c.tpk) * 4, 256);
+    P.off_tb = o; o = align_up(o + cnt(c.tb) * 4, 256);
+    P.off_bndw = o; o = align_up(o + cnt(c.bndw) * 8, 256);
+    P.off_tbw = o; o = align_up(o + cnt(c.tbw) * 4, 256);
+    P.total = o;
+}
 
 struct PairSpec {
     int64_t q_off, t_off, m, n;
@@ -420,14 +475,19 @@ int64_t tb_budget_bytes() {
 // per result index, in result order); tb_cap caps the codes of one chunk.
 void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mode, int ends,
                      bool traceback, int64_t cigar_capacity, int A, int64_t tb_cap, PairPlan &P,
-                     bool plain = false) {
-    const int64_t n = (int64_t)sp.size();
+                     bool plain, const PairRoute &route) {
     P.mode = mode;
     P.ends = ends;
     P.traceback = traceback;
     P.plain = plain;
-    std::vector<int64_t> order(n);
-    std::iota(order.begin(), order.end(), 0);
+    auto is_wf = [&](const PairSpec &x) { return x.m >= route.rows && x.m * x.n >= route.cells; };
+    std::vector<int64_t> order, worder;
+    for (int64_t k = 0; k < (int64_t)sp.size(); k++) {
+        if (is_wf(sp[k])) worder.push_back(k); else order.push_back(k);
+        if (plain) P.plain_seq.push_back({is_wf(sp[k]) ? 1 : 0,
+                                          is_wf(sp[k]) ? (int64_t)worder.size() - 1 : (int64_t)order.size() - 1});
+    }
+    const int64_t n = (int64_t)order.size();
     auto strips = [&](int64_t k) { return (sp[k].m + kTP - 1) / kTP; };
     // batched: length-binned, longest first; plain: input order, one pair per group
     if (!plain)
@@ -532,16 +592,52 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
         k = e;
     }
     P.chunk_first.push_back((int64_t)P.groups.size());
-    size_t o = 0;
-    P.off_slots = o; o = align_up(o + std::max<size_t>(P.slots.size(), 1) * sizeof(PairInfo), 256);
-    P.off_groups = o; o = align_up(o + std::max<size_t>(P.groups.size(), 1) * sizeof(PairGroup), 256);
-    P.off_subst = o; o = align_up(o + (size_t)A * A, 256);
-    P.table_bytes = o;
-    P.off_end = o; o = align_up(o + std::max<size_t>(P.slots.size(), 1) * 8, 256);
-    P.off_bnd = o; o = align_up(o + (size_t)std::max<int64_t>(P.bnd_total, 1) * 8, 256);
-    P.off_tpk = o; o = align_up(o + (size_t)std::max<int64_t>(P.tpk_total, 1) * 4, 256);
-    P.off_tb = o; o = align_up(o + (size_t)std::max<int64_t>(P.tb_max, 1) * 4, 256);
-    P.total = o;
+
+    // wavefront pairs: largest first (plain: input order), slots after the groups'
+    if (!plain)
+        std::stable_sort(worder.begin(), worder.end(), [&](int64_t x, int64_t y) {
+            return sp[x].m * sp[x].n > sp[y].m * sp[y].n;
+        });
+    int64_t wchunk = 0;
+    for (size_t k = 0; k < worder.size(); k++) {
+        const PairSpec &x = sp[worder[k]];
+        const int64_t strips_w = (x.m + kTP - 1) / kTP, passes = (strips_w + kWave - 1) / kWave;
+        const int64_t words = traceback ? passes * (x.n + kWave - 1) * kWave * 2 : 0;
+        WfPair W;
+        memset(&W, 0, sizeof(W));
+        W.slot = (int32_t)P.slots.size();
+        if (plain) {
+            W.tb = 0;
+            W.bnd = 0;
+            P.wf_bnd_total = std::max(P.wf_bnd_total, x.n);
+            P.wf_tb_max = std::max(P.wf_tb_max, words);
+            if (k == 0) P.wf_chunk_first.push_back(0);
+        } else {
+            if (k == 0 || (wchunk > 0 && (wchunk + words) * 4 > tb_cap)) {
+                P.wf_chunk_first.push_back((int64_t)k);
+                wchunk = 0;
+            }
+            W.tb = wchunk / 2;
+            wchunk += words;
+            P.wf_tb_max = std::max(P.wf_tb_max, wchunk);
+            W.bnd = P.wf_bnd_total;
+            P.wf_bnd_total += std::max<int64_t>(x.n, 1);
+        }
+        P.wf_tb_total += words;
+        P.wf.push_back(W);
+        PairInfo I;
+        memset(&I, 0, sizeof(I));
+        I.q_off = x.q_off;
+        I.t_off = x.t_off;
+        I.m = (int32_t)x.m;
+        I.n = (int32_t)x.n;
+        I.res = x.res;
+        I.cig_off = roff[x.res];
+        I.cig_cap = (int32_t)rcap[x.res];
+        P.slots.push_back(I);
+    }
+    P.wf_chunk_first.push_back((int64_t)P.wf.size());
+    layout_pair_plan(P, caps_of(P), A);
 }
 
 int check_pair_range(const dsa_args *a, int64_t m, int64_t n) {
@@ -575,7 +671,7 @@ int make_pair_plan(const dsa_args *a, const dsa_out *out, PairPlan &P) {
     }
     const bool tb = (a->flags & DSA_TRACEBACK) != 0;
     build_pair_plan(sp, n, a->mode, ends, tb, (tb && out) ? out->cigar_capacity : 0, a->alphabet_size,
-                    tb_budget_bytes(), P, (a->flags & DSA_PLAIN) != 0);
+                    tb_budget_bytes(), P, (a->flags & DSA_PLAIN) != 0, pair_route());
     return DSA_OK;
 }
 
@@ -753,11 +849,25 @@ int make_search_plan(const dsa_args *a, Plan &P) {
                 const int rc = check_pair_range(a, x.m, x.n);
                 if (rc) return rc;
             }
-        PairPlan B;
-        build_pair_plan(sp, nq * P.K, P.mode, P.ends, true, 0, A, tb_budget_bytes(), B);
-        const int64_t words = std::max(B.tb_max, std::min(tb_budget_bytes() / 4, B.tb_total));
-        P.pair_tb_cap = words * 4;
-        P.pairws_bytes = align_up(B.off_tb + (size_t)std::max<int64_t>(words, 1) * 4, 256);
+        // bound each region by the plan with every pair in that kind; a hit
+        // plan takes a subset of these pairs, each no longer than its bound
+        PairRoute all_lane, all_wf;
+        all_lane.rows = INT64_MAX;
+        all_wf.rows = 0;
+        all_wf.cells = 0;
+        PairPlan B1, B2;
+        build_pair_plan(sp, nq * P.K, P.mode, P.ends, true, 0, A, tb_budget_bytes(), B1, false, all_lane);
+        build_pair_plan(sp, nq * P.K, P.mode, P.ends, true, 0, A, tb_budget_bytes(), B2, false, all_wf);
+        PairCaps c = caps_of(B1);
+        c.slots = (int64_t)B1.slots.size() + (int64_t)B2.wf.size();
+        c.wf = (int64_t)B2.wf.size();
+        c.tb = std::max(B1.tb_max, std::min(tb_budget_bytes() / 4, B1.tb_total));
+        c.bndw = B2.wf_bnd_total;
+        c.tbw = std::max(B2.wf_tb_max, std::min(tb_budget_bytes() / 4, B2.wf_tb_total));
+        P.pair_caps = c;
+        PairPlan L;
+        layout_pair_plan(L, c, A);
+        P.pairws_bytes = L.total;
         P.off_pairws = o; o = align_up(o + P.pairws_bytes, 256);
     }
     P.total = o;
@@ -823,6 +933,7 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
     int rc = upload_tables(st, ws, P.table_bytes, [&](uint8_t *h) {
         memcpy(h + P.off_slots, P.slots.data(), P.slots.size() * sizeof(PairInfo));
         memcpy(h + P.off_groups, P.groups.data(), P.groups.size() * sizeof(PairGroup));
+        memcpy(h + P.off_wf, P.wf.data(), P.wf.size() * sizeof(WfPair));
         memcpy(h + P.off_subst, a->subst, (size_t)A * A);
     });
     if (rc) return rc;
@@ -851,40 +962,81 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
     K.cig_off_out = out->cigar_off;
     K.cig_len_out = out->cigar_len;
     K.cigar = out->cigar_ops;
-    if (P.plain) {  // one pair at a time: pack, fill, walk
-        const PairGroup *dg = (const PairGroup *)(ws + P.off_groups);
-        for (size_t g = 0; g < P.groups.size(); g++) {
-            PairArgs k1 = K;
-            k1.groups = dg + g;
-            k1.n_groups = 1;
-            k1.pairs = K.pairs + g * kWave;
-            k1.end_i = K.end_i + g * kWave;
-            k1.end_j = K.end_j + g * kWave;
-            HIPCHK(launch_pack_targets(k1, (int64_t)(P.groups[g].ncols / 4) * kWave, st));
-            HIPCHK(launch_pair32(k1, P.mode, st));
-            if (P.traceback) HIPCHK(launch_walk(k1, P.mode, 0, kWave, st));
-        }
-        return P.capacity_short ? fail(DSA_E_CAPACITY, "CIGAR capacity too small; see status bit 1") : DSA_OK;
-    }
-    // pack every group's targets once
-    {
+    const PairGroup *dg = (const PairGroup *)(ws + P.off_groups);
+    const WfPair *dw = (const WfPair *)(ws + P.off_wf);
+    PairArgs KW = K;  // the wavefront kind: its own boundary and code regions
+    KW.tb = (uint32_t *)(ws + P.off_tbw);
+    KW.bnd = (uint2 *)(ws + P.off_bndw);
+    auto wf_launch = [&](int64_t w0, int64_t w1, hipStream_t s) -> int {
+        PairArgs k = KW;
+        k.wf = dw + w0;
+        k.n_wf = (int32_t)(w1 - w0);
+        HIPCHK(launch_pairwf(k, P.mode, s));
+        if (P.traceback) HIPCHK(launch_walk_wf(k, P.mode, s));
+        return DSA_OK;
+    };
+    auto lane_launch = [&](int64_t g0, int64_t g1, hipStream_t s) -> int {
         PairArgs k = K;
-        k.groups = (const PairGroup *)(ws + P.off_groups);
-        k.n_groups = (int32_t)P.groups.size();
-        HIPCHK(launch_pack_targets(k, P.tpk_total, st));
-    }
-    for (size_t c = 0; c + 1 < P.chunk_first.size(); c++) {
-        const int64_t g0 = P.chunk_first[c], g1 = P.chunk_first[c + 1];
-        PairArgs k = K;
-        k.groups = (const PairGroup *)(ws + P.off_groups) + g0;
+        k.groups = dg + g0;
         k.n_groups = (int32_t)(g1 - g0);
         k.pairs = K.pairs + g0 * kWave;
         k.end_i = K.end_i + g0 * kWave;
         k.end_j = K.end_j + g0 * kWave;
-        HIPCHK(launch_pair32(k, P.mode, st));
-        if (P.traceback) HIPCHK(launch_walk(k, P.mode, 0, (g1 - g0) * kWave, st));
+        if (P.plain) HIPCHK(launch_pack_targets(k, (int64_t)(P.groups[g0].ncols / 4) * kWave, s));
+        HIPCHK(launch_pair32(k, P.mode, s));
+        if (P.traceback) HIPCHK(launch_walk(k, P.mode, 0, (g1 - g0) * kWave, s));
+        return DSA_OK;
+    };
+    const char *cap_msg = "CIGAR capacity too small; see status bit 1";
+    size_t span_slot;
+    if ((rc = timing_begin(st, TK_SPAN, &span_slot))) return rc;
+    if (P.plain) {  // one pair at a time, in input order: (pack,) fill, walk
+        for (const auto &x : P.plain_seq) {
+            if ((rc = x.first ? wf_launch(x.second, x.second + 1, st) : lane_launch(x.second, x.second + 1, st)))
+                return rc;
+        }
+        if ((rc = timing_end(st, span_slot))) return rc;
+        return P.capacity_short ? fail(DSA_E_CAPACITY, cap_msg) : DSA_OK;
     }
-    return P.capacity_short ? fail(DSA_E_CAPACITY, "CIGAR capacity too small; see status bit 1") : DSA_OK;
+    // pack every group's targets once
+    {
+        PairArgs k = K;
+        k.groups = dg;
+        k.n_groups = (int32_t)P.groups.size();
+        HIPCHK(launch_pack_targets(k, P.tpk_total, st));
+    }
+    // wavefront pairs on the auxiliary stream, concurrently with the lane groups
+    Aux *aux = nullptr;
+    const bool fork = !P.wf.empty() && !P.groups.empty();
+    hipStream_t ws_st = st;
+    if (fork) {
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        if ((rc = aux_get(dev, &aux))) return rc;
+        HIPCHK(hipEventRecord(aux->fork, st));
+        HIPCHK(hipStreamWaitEvent(aux->s, aux->fork, 0));
+        ws_st = aux->s;
+    }
+    if (!P.wf.empty()) {
+        size_t slot;
+        if ((rc = timing_begin(ws_st, TK_PAIR_WF, &slot))) return rc;
+        for (size_t c = 0; c + 1 < P.wf_chunk_first.size(); c++)
+            if ((rc = wf_launch(P.wf_chunk_first[c], P.wf_chunk_first[c + 1], ws_st))) return rc;
+        if ((rc = timing_end(ws_st, slot))) return rc;
+    }
+    if (!P.groups.empty()) {
+        size_t slot;
+        if ((rc = timing_begin(st, TK_PAIR_LANE, &slot))) return rc;
+        for (size_t c = 0; c + 1 < P.chunk_first.size(); c++)
+            if ((rc = lane_launch(P.chunk_first[c], P.chunk_first[c + 1], st))) return rc;
+        if ((rc = timing_end(st, slot))) return rc;
+    }
+    if (fork) {
+        HIPCHK(hipEventRecord(aux->join, aux->s));
+        HIPCHK(hipStreamWaitEvent(st, aux->join, 0));
+    }
+    if ((rc = timing_end(st, span_slot))) return rc;
+    return P.capacity_short ? fail(DSA_E_CAPACITY, cap_msg) : DSA_OK;
 }
 
 extern "C" int dsa_cigar_capacity(const dsa_args *args, int64_t *entries) {
@@ -1205,7 +1357,14 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
         if (out->cigar_len) HIPCHK(launch_fill_i32(out->cigar_len, 0, nq * P.K, st));
         if (sp.empty()) return DSA_OK;
         PairPlan PP;
-        build_pair_plan(sp, nq * P.K, P.mode, P.ends, true, out->cigar_capacity, A, P.pair_tb_cap, PP);
+        build_pair_plan(sp, nq * P.K, P.mode, P.ends, true, out->cigar_capacity, A,
+                        std::min(P.pair_caps.tb, P.pair_caps.tbw) * 4, PP, false, pair_route());
+        const PairCaps need = caps_of(PP);
+        const PairCaps &cap = P.pair_caps;
+        if (need.slots > cap.slots || need.groups > cap.groups || need.wf > cap.wf || need.bnd > cap.bnd ||
+            need.tpk > cap.tpk || need.tb > cap.tb || need.bndw > cap.bndw || need.tbw > cap.tbw)
+            return fail(DSA_E_WORKSPACE, "hit traceback plan exceeds its workspace bound");
+        layout_pair_plan(PP, cap, A);
         if (PP.total > P.pairws_bytes) return fail(DSA_E_WORKSPACE, "hit traceback plan exceeds its workspace bound");
         return run_pairs(a, out, PP, ws + P.off_pairws, db->d_codes);
     }

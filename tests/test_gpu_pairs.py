@@ -3,7 +3,10 @@ traceback against the CPU oracle: score, both begins, both ends and the CIGAR
 must be identical.  Covers every mode, lengths around the 16-row strip
 boundaries, empty sequences, code storage split into several chunks, a CIGAR
 buffer that is too small, the hand-worked golden cases and reduced versions
-of the read-mapping and global / semi-global workloads."""
+of the read-mapping and global / semi-global workloads.  Large pairs go to
+the wavefront kernel (one wave per pair); the routing thresholds are set
+through DSA_PAIR_WF_ROWS / DSA_PAIR_WF_CELLS to send every pair down either
+path."""
 import numpy as np
 import pytest
 
@@ -100,6 +103,60 @@ def test_pairs_plain(mode, ends, blosum):
     compare_pairs(got, exp, True, f"plain {mode}/{ends}")
     got = gpu_pairs(Q, T, blosum, 10, 1, mode, ends, traceback=False, plain=True)
     compare_pairs(got, exp, False, f"plain score-only {mode}/{ends}")
+
+
+def all_wavefront(monkeypatch):
+    monkeypatch.setenv("DSA_PAIR_WF_ROWS", "1")
+    monkeypatch.setenv("DSA_PAIR_WF_CELLS", "0")
+
+
+def _edge_pairs(seed, alphabet, m_lens, n_lens):
+    rng = np.random.default_rng([170101575, seed])
+    qs, ts = [], []
+    for a in m_lens:
+        for b in n_lens:
+            q = rng.integers(0, alphabet, size=a).astype(np.uint8)
+            # half the targets share a stretch of the query so that scores are large
+            t = rng.integers(0, alphabet, size=b).astype(np.uint8)
+            if a and b and rng.random() < 0.5:
+                k = min(a, b) // 2
+                t[:k] = q[a - k:]
+            qs.append(q)
+            ts.append(t)
+    return qs, ts
+
+
+@pytest.mark.parametrize("mode,ends", CASES)
+@pytest.mark.parametrize("traceback", [True, False], ids=["tb", "score"])
+def test_pairs_wavefront(mode, ends, traceback, blosum, monkeypatch):
+    """Every pair through the wavefront kernel: one-pass pairs with idle
+    lanes, multi-pass pairs (over 1024 rows) and lengths at the 16-row strip
+    and 1024-row pass edges."""
+    all_wavefront(monkeypatch)
+    Q, T = _pairs(17, 60, 0, 120, 20)
+    Q2, T2 = _pairs(18, 16, 900, 2600, 20, related=True)
+    eq, et = _edge_pairs(61, 20, [1, 15, 16, 17, 1023, 1024, 1025, 2049], [0, 1, 5, 300])
+    Q = SeqSet.from_list([Q[k] for k in range(len(Q))] + [Q2[k] for k in range(len(Q2))] + eq)
+    T = SeqSet.from_list([T[k] for k in range(len(T))] + [T2[k] for k in range(len(T2))] + et)
+    log(f"pairs wavefront mode={mode} ends={ends} tb={traceback} n={len(Q)}")
+    got = gpu_pairs(Q, T, blosum, 10, 1, mode, ends, traceback)
+    exp = oracle.align_pairs(Q, T, blosum, 10, 1, mode=mode, ends=ends, traceback=traceback)
+    compare_pairs(got, exp, traceback, f"wavefront {mode}/{ends}")
+
+
+@pytest.mark.parametrize("mode", ["local", "global", "semiglobal"])
+def test_pairs_wavefront_chunked_plain(mode, blosum, monkeypatch):
+    """Wavefront pairs with their codes split over many chunks, mixed with
+    lane-group pairs (both kinds run concurrently), then the plain form."""
+    monkeypatch.setenv("DSA_TB_BUDGET", str(1 << 20))
+    monkeypatch.setenv("DSA_PAIR_WF_ROWS", "200")
+    monkeypatch.setenv("DSA_PAIR_WF_CELLS", "40000")
+    Q, T = _pairs(19, 120, 20, 700, 20, related=True)
+    exp = oracle.align_pairs(Q, T, blosum, 10, 1, mode=mode, traceback=True)
+    got = gpu_pairs(Q, T, blosum, 10, 1, mode)
+    compare_pairs(got, exp, True, f"wavefront chunked {mode}")
+    got = gpu_pairs(Q, T, blosum, 10, 1, mode, plain=True)
+    compare_pairs(got, exp, True, f"wavefront plain {mode}")
 
 
 def test_pairs_chunked_codes(blosum, monkeypatch):
