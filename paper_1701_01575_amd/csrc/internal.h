@@ -136,7 +136,7 @@ struct WfPair {
     int64_t tb;       // first uint2 of its direction codes (chunk-relative)
     int64_t bnd;      // first uint2 of its boundary row between passes (n entries)
     int32_t slot;     // its PairInfo and end-cell slot
-    int32_t pad;
+    int32_t seg;      // lanes per pair: 16, 32 or 64
 };
 
 struct PairArgs {
@@ -162,7 +162,7 @@ struct PairArgs {
 hipError_t launch_pack_targets(const PairArgs &a, int64_t n_words, hipStream_t s);
 hipError_t launch_pair32(const PairArgs &a, int mode, hipStream_t s);
 hipError_t launch_walk(const PairArgs &a, int mode, int64_t slot0, int64_t n_slots, hipStream_t s);
-hipError_t launch_pairwf(const PairArgs &a, int mode, hipStream_t s);
+hipError_t launch_pairwf(const PairArgs &a, int mode, int seg, hipStream_t s);
 hipError_t launch_walk_wf(const PairArgs &a, int mode, hipStream_t s);
 size_t pair32_lds_bytes(int A);
 

@@ -217,15 +217,17 @@ hipError_t launch_pair32(const PairArgs &a, int mode, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Wavefront fill for large pairs: one wave per pair.  Lane l owns rows
-// [16 s, 16 s + 16) of strip s = 64 * pass + l and at step t computes
+// Wavefront fill for large pairs: one segment of SEG lanes (16, 32 or 64)
+// per pair, 64 / SEG pairs per wave.  Segment lane l owns rows
+// [16 s, 16 s + 16) of strip s = SEG * pass + l and at step t computes
 // column t - l + 1, so the row above (lane l - 1's last row one step
-// earlier) and the F leaving it arrive by a lane shuffle; between passes
-// lane 63's last row goes through the pair's boundary row in HBM.  Exact
-// int32, the same recurrence, direction codes and end-cell rule as
-// k_pair32.  A lane's 16 codes of one step are 64 bits, stored at
-// (pass, step, lane) so that each step's store is 512 contiguous bytes.
-template <int MODE, bool TB>
+// earlier) and the F leaving it arrive by a lane shuffle inside the
+// segment; between passes the segment's last lane hands its last row over
+// through the pair's boundary row in HBM.  Exact int32, the same
+// recurrence, direction codes and end-cell rule as k_pair32.  A lane's 16
+// codes of one step are 64 bits, stored at (pass, step, lane) so that a
+// segment's store of one step is SEG * 8 contiguous bytes.
+template <int MODE, bool TB, int SEG>
 __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
     constexpr int T = kTP;
     extern __shared__ int32_t sm[];
@@ -235,15 +237,15 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
         sm[k] = (r < A && c < A) ? (int)P.subst[r * A + c] : PAD32;
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int w = blockIdx.x * kPairWaves + wave;
-    if (w >= P.n_wf) return;  // no block barrier below this point
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & (SEG - 1);
+    const int w = (blockIdx.x * kPairWaves + wave) * (kWave / SEG) + ((threadIdx.x & 63) / SEG);
+    if (w >= P.n_wf) return;  // no block barrier below; segments never read another segment's lanes
     const WfPair W = P.wf[w];
     const PairInfo I = P.pairs[W.slot];
     const int o = P.o, e = P.e, ends = P.ends;
     const int m = I.m, n = I.n;
-    const int S = (m + T - 1) / T, passes = (S + kWave - 1) / kWave;
-    const int nsteps = n + kWave - 1;
+    const int S = (m + T - 1) / T, passes = (S + SEG - 1) / SEG;
+    const int nsteps = n + SEG - 1;
     const uint8_t *qc = P.q_codes + I.q_off, *tc = P.t_codes + I.t_off;
     uint2 *bnd = P.bnd + W.bnd;
     uint2 *tb = reinterpret_cast<uint2 *>(P.tb) + W.tb + lane;
@@ -251,7 +253,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
     uint64_t gk = end_key(0, 0, 0);  // local: this lane's best over its strips
     int gs = 0, gj = 0;              // global / semi: held by the lane of the last strip
     for (int pass = 0; pass < passes; pass++) {
-        const int s = pass * kWave + lane;
+        const int s = pass * SEG + lane;
         const bool act = s < S, last = (s == S - 1);
         const int i0 = s * T;
         int rowb[T], H[T], E[T];
@@ -273,8 +275,8 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
         uint2 bnext = make_uint2(0u, 0u);
         if (lane == 0 && pass > 0 && n > 0) bnext = bnd[0];
         for (int t = 0; t < nsteps; t++) {
-            int rH = __shfl_up(outH, 1, kWave);
-            int rF = __shfl_up(outF, 1, kWave);
+            int rH = __shfl_up(outH, 1, SEG);
+            int rF = __shfl_up(outF, 1, SEG);
             const int j = t - lane + 1;
             const int cc = cnext;
             const uint2 bc = bnext;
@@ -318,7 +320,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
                     }
                     ho_up = ho;
                 }
-                if (TB) tb[((int64_t)pass * nsteps + t) * kWave] = make_uint2(acc[0], acc[1]);
+                if (TB) tb[((int64_t)pass * nsteps + t) * SEG] = make_uint2(acc[0], acc[1]);
                 if (MODE == LOCAL) {
                     if (cm > B) {
                         int rr = 0;
@@ -338,7 +340,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
                 }
                 outH = H[T - 1];
                 outF = F;
-                if (lane == kWave - 1 && pass + 1 < passes)
+                if (lane == SEG - 1 && pass + 1 < passes)
                     bnd[j - 1] = make_uint2((uint32_t)outH, (uint32_t)outF);
             }
         }
@@ -353,16 +355,16 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
     }
     int Gs, Gj, Gi;
     if (MODE == LOCAL) {
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)gk, d, kWave);
-            const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(gk >> 32), d, kWave);
+        for (int d = 1; d < SEG; d <<= 1) {
+            const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)gk, d, SEG);
+            const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(gk >> 32), d, SEG);
             gk = umax64(gk, ((uint64_t)hi << 32) | lo);
         }
         Gs = key_score(gk); Gj = key_j(gk); Gi = key_i(gk);
     } else {
-        const int src = S > 0 ? (S - 1) % kWave : 0;
-        Gs = __shfl(gs, src, kWave);
-        Gj = __shfl(gj, src, kWave);
+        const int src = S > 0 ? (S - 1) % SEG : 0;
+        Gs = __shfl(gs, src, SEG);
+        Gj = __shfl(gj, src, SEG);
         Gi = m;
     }
     if (lane != 0) return;
@@ -388,17 +390,27 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
     }
 }
 
-hipError_t launch_pairwf(const PairArgs &a, int mode, hipStream_t s) {
-    if (a.n_wf <= 0) return hipSuccess;
-    const int nb = (a.n_wf + kPairWaves - 1) / kPairWaves;
+template <int SEG>
+static void launch_pairwf_seg(const PairArgs &a, int mode, hipStream_t s) {
+    const int per_block = kPairWaves * (kWave / SEG);
+    const int nb = (a.n_wf + per_block - 1) / per_block;
     const size_t lds = pair32_lds_bytes(a.A);
-#define LP(MODE, TBV) hipLaunchKernelGGL((k_pairwf<MODE, TBV>), dim3(nb), dim3(kPairWaves * kWave), lds, s, a)
+#define LP(MODE, TBV) \
+    hipLaunchKernelGGL((k_pairwf<MODE, TBV, SEG>), dim3(nb), dim3(kPairWaves * kWave), lds, s, a)
     if (a.traceback) {
         if (mode == LOCAL) LP(LOCAL, true); else if (mode == GLOBAL) LP(GLOBAL, true); else LP(SEMIGLOBAL, true);
     } else {
         if (mode == LOCAL) LP(LOCAL, false); else if (mode == GLOBAL) LP(GLOBAL, false); else LP(SEMIGLOBAL, false);
     }
 #undef LP
+}
+
+hipError_t launch_pairwf(const PairArgs &a, int mode, int seg, hipStream_t s) {
+    if (a.n_wf <= 0) return hipSuccess;
+    if (seg == 16) launch_pairwf_seg<16>(a, mode, s);
+    else if (seg == 32) launch_pairwf_seg<32>(a, mode, s);
+    else if (seg == 64) launch_pairwf_seg<64>(a, mode, s);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -506,11 +518,12 @@ __global__ void k_walk_wf(PairArgs P) {
     const WfPair W = P.wf[k];
     const PairInfo I = P.pairs[W.slot];
     const uint32_t *tb = P.tb + 2 * W.tb;
-    const int64_t nsteps = I.n + kWave - 1;
+    const int seg = W.seg;
+    const int64_t nsteps = I.n + seg - 1;
     walk_pair<MODE>(P, I, P.end_i[W.slot], P.end_j[W.slot], [&](int ii, int jj) -> uint32_t {
         const int s = (ii - 1) / kTP, r = (ii - 1) % kTP;
-        const int pass = s / kWave, lane = s % kWave;
-        const uint32_t w = tb[(((int64_t)pass * nsteps + (jj - 1 + lane)) * kWave + lane) * 2 + (r >> 3)];
+        const int pass = s / seg, lane = s % seg;
+        const uint32_t w = tb[(((int64_t)pass * nsteps + (jj - 1 + lane)) * seg + lane) * 2 + (r >> 3)];
         return (w >> (4 * (r & 7))) & 15u;
     });
 }

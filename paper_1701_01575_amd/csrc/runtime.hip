@@ -334,9 +334,13 @@ struct Round {
 
 // Pairwise routing and region sizes (used by the pairwise plan below).
 struct PairRoute {
-    int64_t rows = 384;      // wavefront iff m >= rows ...
-    int64_t cells = 262144;  // ... and m * n >= cells
+    int64_t rows = 96;       // wavefront iff m >= rows ...
+    int64_t cells = 32768;   // ... and m * n >= cells
 };
+
+// Lanes per wavefront pair: the narrowest segment that covers the query in
+// one pass of 16-row strips (64 lanes and several passes beyond 1024 rows).
+int wf_seg(int64_t m) { return m <= 16 * 16 ? 16 : (m <= 16 * 32 ? 32 : 64); }
 
 PairRoute pair_route() {
     PairRoute r;
@@ -593,19 +597,24 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     }
     P.chunk_first.push_back((int64_t)P.groups.size());
 
-    // wavefront pairs: largest first (plain: input order), slots after the groups'
+    // wavefront pairs: by segment width, then largest first (plain: input
+    // order); their slots follow the groups'
     if (!plain)
         std::stable_sort(worder.begin(), worder.end(), [&](int64_t x, int64_t y) {
+            const int sx = wf_seg(sp[x].m), sy = wf_seg(sp[y].m);
+            if (sx != sy) return sx > sy;
             return sp[x].m * sp[x].n > sp[y].m * sp[y].n;
         });
     int64_t wchunk = 0;
     for (size_t k = 0; k < worder.size(); k++) {
         const PairSpec &x = sp[worder[k]];
-        const int64_t strips_w = (x.m + kTP - 1) / kTP, passes = (strips_w + kWave - 1) / kWave;
-        const int64_t words = traceback ? passes * (x.n + kWave - 1) * kWave * 2 : 0;
+        const int seg = wf_seg(x.m);
+        const int64_t strips_w = (x.m + kTP - 1) / kTP, passes = (strips_w + seg - 1) / seg;
+        const int64_t words = traceback ? passes * (x.n + seg - 1) * seg * 2 : 0;
         WfPair W;
         memset(&W, 0, sizeof(W));
         W.slot = (int32_t)P.slots.size();
+        W.seg = seg;
         if (plain) {
             W.tb = 0;
             W.bnd = 0;
@@ -613,7 +622,7 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
             P.wf_tb_max = std::max(P.wf_tb_max, words);
             if (k == 0) P.wf_chunk_first.push_back(0);
         } else {
-            if (k == 0 || (wchunk > 0 && (wchunk + words) * 4 > tb_cap)) {
+            if (k == 0 || (wchunk > 0 && (wchunk + words) * 4 > tb_cap) || seg != P.wf[k - 1].seg) {
                 P.wf_chunk_first.push_back((int64_t)k);
                 wchunk = 0;
             }
@@ -971,7 +980,7 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
         PairArgs k = KW;
         k.wf = dw + w0;
         k.n_wf = (int32_t)(w1 - w0);
-        HIPCHK(launch_pairwf(k, P.mode, s));
+        HIPCHK(launch_pairwf(k, P.mode, P.wf[w0].seg, s));
         if (P.traceback) HIPCHK(launch_walk_wf(k, P.mode, s));
         return DSA_OK;
     };
