@@ -6,10 +6,12 @@ log-normal lengths (median 300, ~70.8 M residues); BLOSUM62, gap open 11 /
 extend 1; local alignment, score + end coordinates; exact (int16 pass with
 an int32 rerun of anything that saturated).
 
-One step = one dsa_align_batch call over all 5 queries (the batched form:
-one persistent launch with length-binned, longest-first work units).  The
-plain form (one launch per query) is timed too.  GCUPS counts the full
-m x n rectangle of every (query, target) pair.
+One step = one replay of the batched call over all 5 queries, recorded once
+into a HIP graph (persistent launches with length-binned, longest-first work
+units).  An eager dsa_align_batch call with the library's kernel timing
+gives the roofline figures, and the plain form (one launch per query) is
+timed too.  GCUPS counts the full m x n rectangle of every (query, target)
+pair.
 
 Prints one JSON line (rank 0).  `--gpus N` with N > 1 exits with a message:
 this build runs on one GPU.
@@ -110,62 +112,93 @@ def run_serving(args, dsa, B, torch, gen, dev):
 
 
 def run_other_workloads(args, dsa, B, torch, gen, dev):
-    """Batched vs plain on the other workloads, each timed after one warm-up
-    call: the single 64-residue query vs 1,000 targets (local, score + end),
-    100,000 DNA read / window pairs (local with CIGAR) and 50,000 protein
-    pairs of log-uniform length in [100, 3000] (global and semi-global with
-    CIGAR).  The plain pairwise form launches once per pair, so it is timed
-    on the first `plain_pairs` pairs of the same list."""
+    """Batched vs plain on the other workloads: the single 64-residue query
+    vs 1,000 targets (local, score + end), 100,000 DNA read / window pairs
+    (local with CIGAR) and 50,000 protein pairs of log-uniform length in
+    [100, 3000] (global and semi-global with CIGAR).  Batched = the call
+    recorded once into a HIP graph and replayed (inputs resident on the
+    device); plain = one launch per query, or per pair, through
+    dsa_align_batch on prepared buffers.  The plain pairwise form is timed on
+    the first `plain_pairs` pairs of the same list."""
     out = {}
 
-    def timed(fn, reps):
+    def timed(fn, reps, sync=None):
         fn()
-        torch.cuda.synchronize()
+        (sync or torch.cuda.synchronize)()
         t = time.perf_counter()
         for _ in range(reps):
             fn()
-        torch.cuda.synchronize()
+        (sync or torch.cuda.synchronize)()
         return (time.perf_counter() - t) / reps
+
+    def prepared_call(Q, S, o, e, mode, plain, db=None, targets=None, traceback=False, force_int32=False):
+        """Buffers and arguments made once; returns a function that only calls the library."""
+        qc, qo = dsa.device_queries(Q, dev)
+        tc = to = None
+        if targets is not None:
+            tc, to = dsa.device_queries(targets, dev)
+        a = dsa.make_args(qc, qo, S, o, e, mode, db, tc, to, None, traceback, 0, plain, force_int32,
+                          torch.cuda.current_stream())
+        n = len(Q) if targets is not None else len(Q) * db.n_targets
+        need = B.dsa_workspace_size(a)
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+        a.workspace = (ws.data_ptr() + 255) // 256 * 256
+        a.workspace_bytes = need
+        o_, res = dsa._outputs(a, dev, n)
+        keep = (qc, tc, ws, res)
+
+        def call():
+            B.dsa_align_batch(a, o_)
+        call.keep = keep
+        return call
+
+    def graph_rate(rec, reps):
+        return timed(rec.run, reps, rec.stream.synchronize)
 
     c = gen.cfg1()
     Q, T, S = c["queries"], c["targets"], c["matrix"]
     db = dsa.Database.from_seqset(T, S.shape[0])
     cells = int(Q.lengths.sum()) * int(T.lengths.sum())
-    r = {}
-    for form, plain in (("batched", False), ("plain", True)):
-        dt = timed(lambda: dsa.align(Q, db=db, matrix=S, gap_open=11, gap_extend=1, plain=plain,
-                                     force_int32=True), 20)
-        r[form] = {"gcups": round(cells / dt / 1e9, 3), "ms": round(dt * 1e3, 3)}
+    rec = dsa.Recorded(Q, db=db, matrix=S, gap_open=11, gap_extend=1, force_int32=True)
+    dt = graph_rate(rec, 200)
+    pdt = timed(prepared_call(Q, S, 11, 1, "local", True, db=db, force_int32=True), 200)
+    r = {"batched": {"gcups": round(cells / dt / 1e9, 3), "us": round(dt * 1e6, 2)},
+         "plain": {"gcups": round(cells / pdt / 1e9, 3), "us": round(pdt * 1e6, 2)},
+         "batched_over_plain": round(pdt / dt, 2)}
+    rec.close()
     db.close()
-    out["single_query_64_vs_1000"] = dict(cells=cells, **r, note="int32 scores; host-side call "
-                                          "overhead included (Python marshalling + launch)")
+    out["single_query_64_vs_1000"] = dict(cells=cells, **r, note="int32 scores; per call, host "
+                                          "planning and launch included")
     log(f"64 x 1000 local: {r}")
 
-    def pair_leg(name, Q, T, S, o, e, mode, reps=2):
+    def pair_leg(name, Q, T, S, o, e, mode, reps=3):
         cells = int((Q.lengths * T.lengths).sum())
-        call = lambda: dsa.align(Q, targets=T, matrix=S, gap_open=o, gap_extend=e, mode=mode,  # noqa: E731
-                                 traceback=True)
+        # device-time breakdown from one timed eager call
+        call = prepared_call(Q, S, o, e, mode, False, targets=T, traceback=True)
         call()
         torch.cuda.synchronize()
         B.dsa_timing_reset()
         B.dsa_timing_enable(True)
-        dt = timed(call, reps)
+        edt = timed(call, 1)
         dev_ms = {}
         for nm, kind in (("span", B.TIMING_SPAN), ("lane", B.TIMING_PAIR_LANE), ("wavefront", B.TIMING_PAIR_WF)):
             tot, cnt = B.dsa_timing_read(kind)
             dev_ms[nm] = round(tot / max(cnt, 1), 3)
         B.dsa_timing_enable(False)
         B.dsa_timing_reset()
+        del call
+        rec = dsa.Recorded(Q, targets=T, matrix=S, gap_open=o, gap_extend=e, mode=mode, traceback=True)
+        dt = graph_rate(rec, reps)
+        rec.close()
+        del rec
         n = min(args.plain_pairs, len(Q))
         Qs, Ts = Q.subset(list(range(n))), T.subset(list(range(n)))
         pcells = int((Qs.lengths * Ts.lengths).sum())
-        pdt = timed(lambda: dsa.align(Qs, targets=Ts, matrix=S, gap_open=o, gap_extend=e, mode=mode,
-                                      traceback=True, plain=True), 1)
+        pdt = timed(prepared_call(Qs, S, o, e, mode, True, targets=Ts, traceback=True), 1)
         bg, pg = cells / dt / 1e9, pcells / pdt / 1e9
-        dg = cells / (dev_ms["span"] * 1e-3) / 1e9
         res = {"pairs": len(Q), "cells": cells,
-               "batched": {"gcups": round(bg, 2), "ms": round(dt * 1e3, 2), "device_gcups": round(dg, 2),
-                           "device_ms": dev_ms},
+               "batched": {"gcups": round(bg, 2), "ms": round(dt * 1e3, 2),
+                           "eager_call_ms": round(edt * 1e3, 2), "device_ms": dev_ms},
                "plain": {"gcups": round(pg, 3), "ms": round(pdt * 1e3, 2), "pairs": n, "cells": pcells},
                "batched_over_plain": round(bg / pg, 1), "traceback": "CIGAR"}
         log(f"{name}: {res}")
@@ -266,14 +299,33 @@ def main():
             B.dsa_timing_reset()
         return dt, tm, outs
 
-    log(f"batched: {args.warmup} warmup + {args.steps} timed steps")
-    dt, tm, outs = run(False, args.warmup, args.steps, timing=True)
-    ms_step = dt / args.steps * 1e3
-    gcups = cells / (dt / args.steps) / 1e9
+    log(f"eager batched call with kernel timing: {args.warmup} warmup + {args.steps} steps")
+    edt, tm, outs = run(False, args.warmup, args.steps, timing=True)
+    eager_ms = edt / args.steps * 1e3
     span_ms = tm["span"][0] / max(tm["span"][1], 1)
-    log(f"batched: {ms_step:.2f} ms/step, {gcups:.1f} GCUPS; search span {span_ms:.2f} ms, "
+    log(f"eager: {eager_ms:.2f} ms/call; search span {span_ms:.2f} ms, "
         f"inter {tm['inter'][0] / max(tm['inter'][1], 1):.2f} ms x {tm['inter'][1]}, "
         f"wavefront {tm['intra'][0] / max(tm['intra'][1], 1):.2f} ms x {tm['intra'][1]}")
+
+    # the batched form: the call recorded once into a HIP graph, replayed
+    rec = dsa.Recorded(Q, db=db, matrix=S, gap_open=11, gap_extend=1, mode="local")
+    log(f"batched (graph replay): {args.warmup} warmup + {args.steps} timed steps")
+    for _ in range(args.warmup):
+        rec.run()
+    rec.stream.synchronize()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        rec.run()
+    rec.stream.synchronize()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    ms_step = dt / args.steps * 1e3
+    gcups = cells / (dt / args.steps) / 1e9
+    gr = rec.results()
+    graph_agrees = bool(all((gr[k] == outs[k]).all().item() for k in ("score", "q_end", "t_end")))
+    rec.close()
+    log(f"batched: {ms_step:.2f} ms/step, {gcups:.1f} GCUPS, replay == eager: {graph_agrees}")
 
     plain_ms = plain_gcups = None
     if args.plain_steps > 0:
@@ -349,7 +401,10 @@ def main():
         "config": {"workload": "protein database search: 5 queries (144, 464, 1000, 2000, 5000) "
                                f"vs {nt} log-normal targets, BLOSUM62 11/1, local, score + end",
                    "cells": cells, "queries": nq, "targets": nt,
-                   "residues": int(T.lengths.sum()), "form": "batched (persistent, LPT units)"},
+                   "residues": int(T.lengths.sum()),
+                   "form": "batched (persistent, LPT units, replayed from a HIP graph)"},
+        "eager_call_ms": round(eager_ms, 3),
+        "graph_replay_equals_eager": graph_agrees,
         "plain": None if plain_gcups is None else {
             "value": round(plain_gcups, 2), "unit": "GCUPS", "ms_per_step": round(plain_ms, 3),
             "form": "one launch per query"},

@@ -180,6 +180,31 @@ int dsa_cigar_capacity(const dsa_args *args, int64_t *entries);
 int dsa_align_batch(const dsa_args *args, const dsa_out *out);
 
 /*
+ * Recorded batches: the batched form replayed from a HIP graph, for callers
+ * that run the same batch shape again and again (Section II.B's map phase
+ * over a fixed query set and reference).
+ *
+ * dsa_graph_create plans the call (args, out) as dsa_align_batch would,
+ * writes its tables into args->workspace (it waits for args->stream once),
+ * then records every kernel of the call into a graph by capturing
+ * args->stream (which must not be the null stream).  Nothing runs yet.
+ * dsa_graph_launch(graph, stream) replays the whole call on `stream`: it reads
+ * the query codes, database, workspace and writes the outputs at the device
+ * addresses given at creation, with whatever they hold at replay time, so
+ * the caller keeps all of them alive and unmoved, may change the query
+ * residues (not the lengths) between replays, and must not run two replays
+ * of one graph, or a replay and another call on the same workspace, at the
+ * same time.  *graph is set when the return is DSA_OK or DSA_E_CAPACITY.
+ * dsa_graph_destroy frees the graph (not the buffers).
+ * Errors: as dsa_align_batch; DSA_E_NOTSUP for top_k with traceback (the hit
+ * traceback reads the hit list back on the host).
+ */
+typedef struct dsa_graph dsa_graph;
+int dsa_graph_create(const dsa_args *args, const dsa_out *out, dsa_graph **graph);
+int dsa_graph_launch(dsa_graph *graph, void *stream);
+int dsa_graph_destroy(dsa_graph *graph);
+
+/*
  * Measurement hooks.  dsa_timing_enable(1) makes dsa_align_batch record HIP
  * event pairs on the stream each kernel is launched on: kind 0 = the whole
  * search phase on args->stream (both search kernels, from the fork to the

@@ -171,6 +171,78 @@ def align_args(a, device, n_results, want_coords=True, want_begin=True, cigar_ca
     return res
 
 
+def _outputs(a, device, n_results, cigar_capacity=None):
+    torch = _torch()
+    out = B.dsa_out()
+    i32 = dict(dtype=torch.int32, device=device)
+    nr = max(n_results, 1)
+    res = {k: torch.empty(nr, **i32) for k in ("score", "q_end", "t_end", "q_begin", "t_begin")}
+    res["status"] = torch.empty(nr, dtype=torch.uint8, device=device)
+    if a.top_k:
+        res["t_index"] = torch.empty(nr, dtype=torch.int64, device=device)
+    if a.flags & DSA_TRACEBACK:
+        cap = B.dsa_cigar_capacity(a) if cigar_capacity is None else int(cigar_capacity)
+        res["cigar_off"] = torch.empty(nr, dtype=torch.int64, device=device)
+        res["cigar_len"] = torch.empty(nr, **i32)
+        res["cigar_ops"] = torch.empty(max(cap, 1), dtype=torch.int32, device=device)
+        out.cigar_capacity = cap
+    for k, v in res.items():
+        setattr(out, k, v.data_ptr())
+    return out, res
+
+
+class Recorded:
+    """One batch recorded into a HIP graph (dsa_graph_create): `run()`
+    replays every kernel of the call on the stream given at creation, with
+    the same buffers, which this object keeps alive.  `results()` returns the
+    output tensors (valid once the stream has finished the replay)."""
+
+    def __init__(self, queries, db: Database = None, targets=None, matrix=None, gap_open=11,
+                 gap_extend=1, mode="local", free_ends=None, traceback=False, top_k=0,
+                 force_int32=False, stream=None):
+        torch = _torch()
+        self.device = db.device if db is not None else torch.device("cuda", torch.cuda.current_device())
+        if stream is None:
+            stream = torch.cuda.Stream(device=self.device)
+        self.stream = stream
+        with torch.cuda.stream(stream):
+            qc, qo = device_queries(queries, self.device)
+            tc = to = None
+            if targets is not None:
+                tc, to = device_queries(targets, self.device)
+            a = make_args(qc, qo, matrix, gap_open, gap_extend, mode, db, tc, to, free_ends, traceback,
+                          top_k, False, force_int32, stream)
+            nq = len(qo) - 1
+            n = nq if targets is not None else (nq * top_k if top_k else nq * db.n_targets)
+            need = B.dsa_workspace_size(a)
+            self._ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+            a.workspace = (self._ws.data_ptr() + 255) // 256 * 256
+            a.workspace_bytes = need
+            out, res = _outputs(a, self.device, n)
+        stream.synchronize()
+        self._keep = (qc, tc, a, out, db)
+        self._res = {k: (v[:n] if k != "cigar_ops" else v) for k, v in res.items()}
+        self.handle, st = B.dsa_graph_create(a, out)
+        self.capacity_ok = st == B.DSA_OK
+
+    def run(self):
+        B.dsa_graph_launch(self.handle, self.stream.cuda_stream)
+
+    def results(self) -> dict:
+        return self._res
+
+    def close(self):
+        if getattr(self, "handle", None):
+            B.dsa_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def cigars(res) -> list:
     """Per-result CIGAR runs (uint32 numpy arrays, (len << 4) | op) on the host."""
     ops = res["cigar_ops"].cpu().numpy().view(np.uint32)

@@ -18,7 +18,8 @@ DSA_TRACEBACK, DSA_PLAIN, DSA_FORCE_INT32 = 1, 2, 4
 DSA_ST_INT32, DSA_ST_TRUNCATED = 1, 2
 
 EXPORTS = ["dsa_db_create", "dsa_db_destroy", "dsa_db_info", "dsa_workspace_size",
-           "dsa_cigar_capacity", "dsa_align_batch", "dsa_timing_enable", "dsa_timing_read",
+           "dsa_cigar_capacity", "dsa_align_batch", "dsa_graph_create", "dsa_graph_launch",
+           "dsa_graph_destroy", "dsa_timing_enable", "dsa_timing_read",
            "dsa_timing_reset",
            "dsa_probe",
            "dsa_strerror", "dsa_last_error", "dsa_abi_version"]
@@ -143,6 +144,23 @@ def dsa_align_batch(args: dsa_args, out: dsa_out) -> int:
     if st not in (DSA_OK, DSA_E_CAPACITY):
         check(st, "dsa_align_batch")
     return st
+
+
+def dsa_graph_create(args: dsa_args, out: dsa_out):
+    """Record the call (args, out) into a graph; returns (handle, status)."""
+    g = ctypes.c_void_p()
+    st = lib().dsa_graph_create(ctypes.byref(args), ctypes.byref(out), ctypes.byref(g))
+    if st not in (DSA_OK, DSA_E_CAPACITY):
+        check(st, "dsa_graph_create")
+    return g, st
+
+
+def dsa_graph_launch(graph, stream) -> None:
+    check(lib().dsa_graph_launch(graph, ctypes.c_void_p(stream)), "dsa_graph_launch")
+
+
+def dsa_graph_destroy(graph) -> None:
+    check(lib().dsa_graph_destroy(graph), "dsa_graph_destroy")
 
 
 def dsa_timing_enable(on: bool):

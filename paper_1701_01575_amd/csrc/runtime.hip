@@ -55,8 +55,12 @@ struct Timing {
 };
 Timing g_timing;
 
+// Set while this thread records a graph: no timing events go into it.
+thread_local bool t_capturing = false;
+
 int timing_begin(hipStream_t st, int kind, size_t *slot) {
     *slot = SIZE_MAX;
+    if (t_capturing) return DSA_OK;
     std::lock_guard<std::mutex> lk(g_timing.mu);
     if (!g_timing.on) return DSA_OK;
     if (g_timing.used == g_timing.pool.size()) {
@@ -933,19 +937,27 @@ static int upload_tables(hipStream_t st, void *dst, size_t bytes,
     return DSA_OK;
 }
 
+// Parts of a call: tables to the workspace, then the kernels.  A graph
+// records only the kernels, after the tables are in place.
+enum RunPhase { RUN_ALL = 0, RUN_UPLOAD = 1, RUN_KERNELS = 2 };
+
 static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t *ws,
-                     const uint8_t *t_codes) {
+                     const uint8_t *t_codes, int phase = RUN_ALL) {
     hipStream_t st = (hipStream_t)a->stream;
     const int A = a->alphabet_size;
     if (P.traceback && (!out->cigar_ops || !out->cigar_off || !out->cigar_len))
         return fail(DSA_E_INVAL, "traceback needs cigar_ops, cigar_off and cigar_len");
-    int rc = upload_tables(st, ws, P.table_bytes, [&](uint8_t *h) {
-        memcpy(h + P.off_slots, P.slots.data(), P.slots.size() * sizeof(PairInfo));
-        memcpy(h + P.off_groups, P.groups.data(), P.groups.size() * sizeof(PairGroup));
-        memcpy(h + P.off_wf, P.wf.data(), P.wf.size() * sizeof(WfPair));
-        memcpy(h + P.off_subst, a->subst, (size_t)A * A);
-    });
-    if (rc) return rc;
+    int rc = DSA_OK;
+    if (phase != RUN_KERNELS) {
+        rc = upload_tables(st, ws, P.table_bytes, [&](uint8_t *h) {
+            memcpy(h + P.off_slots, P.slots.data(), P.slots.size() * sizeof(PairInfo));
+            memcpy(h + P.off_groups, P.groups.data(), P.groups.size() * sizeof(PairGroup));
+            memcpy(h + P.off_wf, P.wf.data(), P.wf.size() * sizeof(WfPair));
+            memcpy(h + P.off_subst, a->subst, (size_t)A * A);
+        });
+        if (rc) return rc;
+        if (phase == RUN_UPLOAD) return DSA_OK;
+    }
     PairArgs K;
     memset(&K, 0, sizeof(K));
     K.pairs = (const PairInfo *)(ws + P.off_slots);
@@ -1070,7 +1082,7 @@ extern "C" int dsa_cigar_capacity(const dsa_args *args, int64_t *entries) {
     return DSA_OK;
 }
 
-static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
+static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase = RUN_ALL) {
     const dsa_db *db = a->db;
     hipStream_t st = (hipStream_t)a->stream;
     uint8_t *ws = (uint8_t *)a->workspace;
@@ -1095,7 +1107,7 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
     int dev = 0;
     hipGetDevice(&dev);
     Staging &S = g_staging[dev & 63];
-    {
+    if (phase != RUN_KERNELS) {
         std::lock_guard<std::mutex> lk(S.mu);
         if (S.pending) {
             HIPCHK(hipEventSynchronize(S.ev));
@@ -1123,6 +1135,7 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
         HIPCHK(hipEventRecord(S.ev, st));
         S.pending = true;
     }
+    if (phase == RUN_UPLOAD) return DSA_OK;
 
     SearchArgs K;
     memset(&K, 0, sizeof(K));
@@ -1380,31 +1393,112 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P) {
     return DSA_OK;
 }
 
-extern "C" int dsa_align_batch(const dsa_args *args, const dsa_out *out) {
+static int check_workspace(const dsa_args *args, size_t total) {
+    if (!args->workspace && total) return fail(DSA_E_INVAL, "workspace is NULL");
+    if (args->workspace_bytes < total)
+        return fail(DSA_E_WORKSPACE, "workspace too small: need " + std::to_string(total) + " bytes");
+    if (((uintptr_t)args->workspace) & 255) return fail(DSA_E_INVAL, "workspace must be 256-byte aligned");
+    return DSA_OK;
+}
+
+// Plan and run one call, or one phase of it.
+static int align_phase(const dsa_args *args, const dsa_out *out, int phase) {
     if (!out || !out->score) return fail(DSA_E_INVAL, "out->score is required");
     int rc = check_common(args);
     if (rc) return rc;
     if (!args->db) {
         PairPlan PP;
         if ((rc = make_pair_plan(args, out, PP))) return rc;
-        if (!args->workspace && PP.total) return fail(DSA_E_INVAL, "workspace is NULL");
-        if (args->workspace_bytes < PP.total)
-            return fail(DSA_E_WORKSPACE, "workspace too small: need " + std::to_string(PP.total) + " bytes");
-        if (((uintptr_t)args->workspace) & 255) return fail(DSA_E_INVAL, "workspace must be 256-byte aligned");
-        return run_pairs(args, out, PP, (uint8_t *)args->workspace, args->t_codes);
+        if ((rc = check_workspace(args, PP.total))) return rc;
+        return run_pairs(args, out, PP, (uint8_t *)args->workspace, args->t_codes, phase);
     }
     Plan P;
     rc = make_plan(args, P);
     if (rc) return rc;
-    if (!args->workspace && P.total) return fail(DSA_E_INVAL, "workspace is NULL");
-    if (args->workspace_bytes < P.total)
-        return fail(DSA_E_WORKSPACE, "workspace too small: need " + std::to_string(P.total) + " bytes");
-    if (((uintptr_t)args->workspace) & 255) return fail(DSA_E_INVAL, "workspace must be 256-byte aligned");
+    if ((rc = check_workspace(args, P.total))) return rc;
     int dev = 0;
     hipGetDevice(&dev);
     if (args->db && args->db->device != dev)
         return fail(DSA_E_INVAL, "database lives on another device");
-    return run_search(args, out, P);
+    if (phase != RUN_ALL && P.K > 0 && P.traceback)
+        return fail(DSA_E_NOTSUP, "top-K with traceback waits for the hit list on the host and cannot be recorded");
+    return run_search(args, out, P, phase);
+}
+
+extern "C" int dsa_align_batch(const dsa_args *args, const dsa_out *out) {
+    return align_phase(args, out, RUN_ALL);
+}
+
+struct dsa_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
+};
+
+static void graph_free(dsa_graph *g) {
+    if (!g) return;
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    delete g;
+}
+
+extern "C" int dsa_graph_create(const dsa_args *args, const dsa_out *out, dsa_graph **graph) {
+    if (!graph) return fail(DSA_E_INVAL, "graph is NULL");
+    *graph = nullptr;
+    if (!args) return fail(DSA_E_INVAL, "args is NULL");
+    hipStream_t st = (hipStream_t)args->stream;
+    if (!st) return fail(DSA_E_INVAL, "recording a graph needs a stream other than the null stream");
+    dsa_graph *g = new dsa_graph();
+    hipGetDevice(&g->device);
+    {
+        Aux *aux = nullptr;  // created outside the recording
+        int arc = aux_get(g->device, &aux);
+        if (arc) { graph_free(g); return arc; }
+    }
+    // the tables go to the workspace now, once; the graph holds the kernels
+    int rc = align_phase(args, out, RUN_UPLOAD);
+    if (rc) { graph_free(g); return rc; }
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) { graph_free(g); return fail(DSA_E_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e)); }
+    e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { graph_free(g); return fail(DSA_E_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e)); }
+    t_capturing = true;
+    rc = align_phase(args, out, RUN_KERNELS);
+    t_capturing = false;
+    hipGraph_t gr = nullptr;
+    e = hipStreamEndCapture(st, &gr);
+    if (rc != DSA_OK && rc != DSA_E_CAPACITY) {
+        if (gr) hipGraphDestroy(gr);
+        graph_free(g);
+        return rc;
+    }
+    if (e != hipSuccess || !gr) {
+        if (gr) hipGraphDestroy(gr);
+        graph_free(g);
+        return fail(DSA_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
+    g->graph = gr;
+    e = hipGraphInstantiate(&g->exec, gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        graph_free(g);
+        return fail(DSA_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    *graph = g;
+    return rc;
+}
+
+extern "C" int dsa_graph_launch(dsa_graph *g, void *stream) {
+    if (!g || !g->exec) return fail(DSA_E_INVAL, "graph is NULL");
+    int dev = 0;
+    hipGetDevice(&dev);
+    if (dev != g->device) return fail(DSA_E_INVAL, "graph was recorded on another device");
+    HIPCHK(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return DSA_OK;
+}
+
+extern "C" int dsa_graph_destroy(dsa_graph *g) {
+    graph_free(g);
+    return DSA_OK;
 }
 
 extern "C" int dsa_timing_enable(int on) {
