@@ -205,6 +205,43 @@ int dsa_graph_launch(dsa_graph *graph, void *stream);
 int dsa_graph_destroy(dsa_graph *graph);
 
 /*
+ * Autotuning of launch choices that never change results: the strip height
+ * (16 or 32 rows) and waves per block of the inter-sequence kernel and the
+ * cell budget above which a target group goes to the wavefront kernel
+ * (database search), or the query rows and cells above which a pair goes
+ * to the wavefront pairwise kernel (pairwise).  Choices are kept per shape
+ * class: kind, mode, form (plain or batched), traceback, top-K, alphabet and
+ * power-of-two buckets of the query residues and database residues (search)
+ * or of the cells and longest query (pairwise); dsa_tuning_key writes that
+ * class's name.
+ *
+ * dsa_autotune(args, cache_path, chosen) times candidates on these very
+ * arguments (blocking; it allocates its own workspace and outputs, so
+ * args->workspace is not used), keeps the fastest for the class in the
+ * process, merges it into the JSON file cache_path when that is not NULL,
+ * and returns it in *chosen (NULL allowed).  Later calls of the class,
+ * dsa_workspace_size included, use it: the caller sizes the workspace after
+ * tuning.  A file named by the environment variable DSA_AUTOTUNE_CACHE is
+ * read once, at the first call that plans.  Environment variables DSA_STRIP,
+ * DSA_WAVES, DSA_INTRA_BUDGET, DSA_PAIR_WF_ROWS and DSA_PAIR_WF_CELLS
+ * override the table.
+ * dsa_tuning_get returns the values a call with these arguments would use
+ * now (search: strip, waves, intra_budget; pairwise: pair_rows, pair_cells;
+ * the others -1), with ms = the tuned time (0 if untuned).
+ */
+typedef struct {
+    int32_t strip;           /* rows per strip of the inter-sequence kernel */
+    int32_t waves;           /* waves per block of the inter-sequence kernel */
+    int64_t intra_budget;    /* strips x columns above which a group goes to the wavefront kernel */
+    int64_t pair_rows;       /* pairwise: wavefront iff query rows >= pair_rows ... */
+    int64_t pair_cells;      /* ... and rows x columns >= pair_cells */
+    double ms;               /* time of the chosen candidate when tuned */
+} dsa_tuning;
+int dsa_autotune(const dsa_args *args, const char *cache_path, dsa_tuning *chosen);
+int dsa_tuning_get(const dsa_args *args, dsa_tuning *out);
+int dsa_tuning_key(const dsa_args *args, char *buf, size_t size);
+
+/*
  * Measurement hooks.  dsa_timing_enable(1) makes dsa_align_batch record HIP
  * event pairs on the stream each kernel is launched on: kind 0 = the whole
  * search phase on args->stream (both search kernels, from the fork to the

@@ -243,6 +243,37 @@ class Recorded:
             pass
 
 
+def autotune(queries, db: Database = None, targets=None, matrix=None, gap_open=11, gap_extend=1,
+             mode="local", free_ends=None, traceback=False, top_k=0, plain=False, cache_path=None) -> dict:
+    """Time the launch candidates on these inputs (dsa_autotune) and keep the
+    fastest for their shape class; returns the choice."""
+    torch = _torch()
+    device = db.device if db is not None else torch.device("cuda", torch.cuda.current_device())
+    qc, qo = device_queries(queries, device)
+    tc = to = None
+    if targets is not None:
+        tc, to = device_queries(targets, device)
+    a = make_args(qc, qo, matrix, gap_open, gap_extend, mode, db, tc, to, free_ends, traceback, top_k,
+                  plain, False, None)
+    return B.dsa_autotune(a, cache_path)
+
+
+def tuning(queries, db: Database = None, targets=None, matrix=None, gap_open=11, gap_extend=1,
+           mode="local", free_ends=None, traceback=False, top_k=0, plain=False) -> dict:
+    """The launch choices a call with these inputs would use now, and its class key."""
+    torch = _torch()
+    device = db.device if db is not None else torch.device("cuda", torch.cuda.current_device())
+    qc, qo = device_queries(queries, device)
+    tc = to = None
+    if targets is not None:
+        tc, to = device_queries(targets, device)
+    a = make_args(qc, qo, matrix, gap_open, gap_extend, mode, db, tc, to, free_ends, traceback, top_k,
+                  plain, False, None)
+    out = B.dsa_tuning_get(a)
+    out["key"] = B.dsa_tuning_key(a)
+    return out
+
+
 def cigars(res) -> list:
     """Per-result CIGAR runs (uint32 numpy arrays, (len << 4) | op) on the host."""
     ops = res["cigar_ops"].cpu().numpy().view(np.uint32)

@@ -19,7 +19,8 @@ DSA_ST_INT32, DSA_ST_TRUNCATED = 1, 2
 
 EXPORTS = ["dsa_db_create", "dsa_db_destroy", "dsa_db_info", "dsa_workspace_size",
            "dsa_cigar_capacity", "dsa_align_batch", "dsa_graph_create", "dsa_graph_launch",
-           "dsa_graph_destroy", "dsa_timing_enable", "dsa_timing_read",
+           "dsa_graph_destroy", "dsa_autotune", "dsa_tuning_get", "dsa_tuning_key",
+           "dsa_timing_enable", "dsa_timing_read",
            "dsa_timing_reset",
            "dsa_probe",
            "dsa_strerror", "dsa_last_error", "dsa_abi_version"]
@@ -161,6 +162,40 @@ def dsa_graph_launch(graph, stream) -> None:
 
 def dsa_graph_destroy(graph) -> None:
     check(lib().dsa_graph_destroy(graph), "dsa_graph_destroy")
+
+
+class dsa_tuning(ctypes.Structure):
+    _fields_ = [
+        ("strip", ctypes.c_int32),
+        ("waves", ctypes.c_int32),
+        ("intra_budget", ctypes.c_int64),
+        ("pair_rows", ctypes.c_int64),
+        ("pair_cells", ctypes.c_int64),
+        ("ms", ctypes.c_double),
+    ]
+
+
+def _tuning_dict(t: dsa_tuning) -> dict:
+    return {f: getattr(t, f) for f, _ in dsa_tuning._fields_}
+
+
+def dsa_autotune(args: dsa_args, cache_path: str | None = None) -> dict:
+    t = dsa_tuning()
+    path = cache_path.encode() if cache_path else None
+    check(lib().dsa_autotune(ctypes.byref(args), path, ctypes.byref(t)), "dsa_autotune")
+    return _tuning_dict(t)
+
+
+def dsa_tuning_get(args: dsa_args) -> dict:
+    t = dsa_tuning()
+    check(lib().dsa_tuning_get(ctypes.byref(args), ctypes.byref(t)), "dsa_tuning_get")
+    return _tuning_dict(t)
+
+
+def dsa_tuning_key(args: dsa_args) -> str:
+    buf = ctypes.create_string_buffer(256)
+    check(lib().dsa_tuning_key(ctypes.byref(args), buf, ctypes.c_size_t(256)), "dsa_tuning_key")
+    return buf.value.decode()
 
 
 def dsa_timing_enable(on: bool):

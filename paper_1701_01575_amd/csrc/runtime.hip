@@ -1,10 +1,13 @@
 // Host runtime of libdsa: argument checks, database packing, work planning
 // and the C ABI declared in include/dsa.h.
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -336,6 +339,147 @@ struct Round {
     int64_t ifirst = 0, icount = 0;           // wavefront units
 };
 
+// ---------------------------------------------------------------------------
+// Tuning: launch choices that do not change results.  Each call looks up
+// its shape class (kind, mode, form, traceback, size buckets) in a table
+// that dsa_autotune fills by timing candidates, and that a JSON cache file
+// (DSA_AUTOTUNE_CACHE, read once) preloads.  A value of -1 (or 0 for strip
+// and waves) keeps the built-in default; environment variables override
+// the table, and the candidate being timed overrides everything.
+struct Tuning {
+    int32_t strip = 0;           // 16 or 32 rows per strip of the inter-sequence kernel
+    int32_t waves = 0;           // waves per block of the inter-sequence kernel (1..8)
+    int64_t intra_budget = -1;   // strips x columns above which a group goes to the wavefront kernel
+    int64_t pair_rows = -1;      // pairwise: wavefront iff m >= pair_rows ...
+    int64_t pair_cells = -1;     // ... and m * n >= pair_cells
+    double ms = 0.0;             // time of the chosen candidate when it was tuned
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, Tuning> g_tuned;
+thread_local const Tuning *t_force = nullptr;
+
+int bucket(int64_t v) { return v <= 0 ? 0 : (int)std::floor(std::log2((double)v)); }
+
+std::string search_key(const dsa_args *a, int64_t db_residues) {
+    int64_t sum_m = 0;
+    for (int64_t q = 0; q < a->n_q; q++) sum_m += a->q_offsets[q + 1] - a->q_offsets[q];
+    char buf[160];
+    snprintf(buf, sizeof(buf), "search/m%d/f%d/tb%d/k%d/A%d/q%d/t%d", a->mode, (a->flags & DSA_PLAIN) ? 1 : 0,
+             (a->flags & DSA_TRACEBACK) ? 1 : 0, a->top_k > 0 ? 1 : 0, a->alphabet_size, bucket(sum_m),
+             bucket(db_residues));
+    return buf;
+}
+
+std::string pair_key(const dsa_args *a) {
+    int64_t cells = 0, mmax = 0;
+    for (int64_t k = 0; k < a->n_q; k++) {
+        const int64_t m = a->q_offsets[k + 1] - a->q_offsets[k], n = a->t_offsets[k + 1] - a->t_offsets[k];
+        cells += m * n;
+        mmax = std::max(mmax, m);
+    }
+    char buf[160];
+    snprintf(buf, sizeof(buf), "pairs/m%d/f%d/tb%d/A%d/c%d/r%d", a->mode, (a->flags & DSA_PLAIN) ? 1 : 0,
+             (a->flags & DSA_TRACEBACK) ? 1 : 0, a->alphabet_size, bucket(cells), bucket(mmax));
+    return buf;
+}
+
+// Minimal reader for the cache this library writes: an array of flat objects
+// with one string field "key" and numeric fields.
+bool json_num(const std::string &obj, const char *name, double *v) {
+    const std::string pat = std::string("\"") + name + "\"";
+    size_t p = obj.find(pat);
+    if (p == std::string::npos) return false;
+    p = obj.find(':', p + pat.size());
+    if (p == std::string::npos) return false;
+    char *end = nullptr;
+    *v = strtod(obj.c_str() + p + 1, &end);
+    return end != obj.c_str() + p + 1;
+}
+
+bool json_str(const std::string &obj, const char *name, std::string *v) {
+    const std::string pat = std::string("\"") + name + "\"";
+    size_t p = obj.find(pat);
+    if (p == std::string::npos) return false;
+    p = obj.find('"', obj.find(':', p + pat.size()));
+    if (p == std::string::npos) return false;
+    const size_t q = obj.find('"', p + 1);
+    if (q == std::string::npos) return false;
+    *v = obj.substr(p + 1, q - p - 1);
+    return true;
+}
+
+void load_cache_file(const char *path, std::map<std::string, Tuning> *into) {
+    FILE *f = fopen(path, "rb");
+    if (!f) return;
+    std::string text;
+    char buf[4096];
+    size_t r;
+    while ((r = fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, r);
+    fclose(f);
+    size_t p = 0;
+    while ((p = text.find('{', p)) != std::string::npos) {
+        const size_t q = text.find('}', p);
+        if (q == std::string::npos) break;
+        const std::string obj = text.substr(p, q - p + 1);
+        p = q + 1;
+        std::string key;
+        if (!json_str(obj, "key", &key)) continue;
+        Tuning t;
+        double v;
+        if (json_num(obj, "strip", &v)) t.strip = (int32_t)v;
+        if (json_num(obj, "waves", &v)) t.waves = (int32_t)v;
+        if (json_num(obj, "intra_budget", &v)) t.intra_budget = (int64_t)v;
+        if (json_num(obj, "pair_rows", &v)) t.pair_rows = (int64_t)v;
+        if (json_num(obj, "pair_cells", &v)) t.pair_cells = (int64_t)v;
+        if (json_num(obj, "ms", &v)) t.ms = v;
+        (*into)[key] = t;
+    }
+}
+
+bool save_cache_file(const char *path, const std::map<std::string, Tuning> &entries) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "wb");
+    if (!f) return false;
+    fprintf(f, "[\n");
+    size_t k = 0;
+    for (const auto &e : entries) {
+        const Tuning &t = e.second;
+        fprintf(f,
+                "  {\"key\": \"%s\", \"strip\": %d, \"waves\": %d, \"intra_budget\": %lld, "
+                "\"pair_rows\": %lld, \"pair_cells\": %lld, \"ms\": %.4f}%s\n",
+                e.first.c_str(), t.strip, t.waves, (long long)t.intra_budget, (long long)t.pair_rows,
+                (long long)t.pair_cells, t.ms, (++k < entries.size()) ? "," : "");
+    }
+    fprintf(f, "]\n");
+    const bool ok = fclose(f) == 0;
+    return ok && rename(tmp.c_str(), path) == 0;
+}
+
+std::once_flag g_cache_once;
+
+Tuning tuning_for(const std::string &key) {
+    std::call_once(g_cache_once, [] {
+        if (const char *path = getenv("DSA_AUTOTUNE_CACHE")) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            load_cache_file(path, &g_tuned);
+        }
+    });
+    if (t_force) return *t_force;
+    Tuning t;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) t = it->second;
+    }
+    if (const char *v = getenv("DSA_STRIP")) t.strip = atoi(v);
+    if (const char *v = getenv("DSA_WAVES")) t.waves = atoi(v);
+    if (const char *v = getenv("DSA_INTRA_BUDGET")) t.intra_budget = atoll(v);
+    if (const char *v = getenv("DSA_PAIR_WF_ROWS")) t.pair_rows = atoll(v);
+    if (const char *v = getenv("DSA_PAIR_WF_CELLS")) t.pair_cells = atoll(v);
+    return t;
+}
+
 // Pairwise routing and region sizes (used by the pairwise plan below).
 struct PairRoute {
     int64_t rows = 96;       // wavefront iff m >= rows ...
@@ -346,10 +490,10 @@ struct PairRoute {
 // one pass of 16-row strips (64 lanes and several passes beyond 1024 rows).
 int wf_seg(int64_t m) { return m <= 16 * 16 ? 16 : (m <= 16 * 32 ? 32 : 64); }
 
-PairRoute pair_route() {
+PairRoute pair_route(const Tuning &t) {
     PairRoute r;
-    if (const char *v = getenv("DSA_PAIR_WF_ROWS")) r.rows = std::max<int64_t>(atoll(v), 1);
-    if (const char *v = getenv("DSA_PAIR_WF_CELLS")) r.cells = std::max<int64_t>(atoll(v), 0);
+    if (t.pair_rows >= 0) r.rows = std::max<int64_t>(t.pair_rows, 1);
+    if (t.pair_cells >= 0) r.cells = t.pair_cells;
     return r;
 }
 
@@ -684,7 +828,7 @@ int make_pair_plan(const dsa_args *a, const dsa_out *out, PairPlan &P) {
     }
     const bool tb = (a->flags & DSA_TRACEBACK) != 0;
     build_pair_plan(sp, n, a->mode, ends, tb, (tb && out) ? out->cigar_capacity : 0, a->alphabet_size,
-                    tb_budget_bytes(), P, (a->flags & DSA_PLAIN) != 0, pair_route());
+                    tb_budget_bytes(), P, (a->flags & DSA_PLAIN) != 0, pair_route(tuning_for(pair_key(a))));
     return DSA_OK;
 }
 
@@ -713,19 +857,13 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     // pick the strip height from the LDS the pair profile needs
     P.T = 32;
     if (search16_lds_bytes(32, db->AP) > 80 * 1024) P.T = 16;
-    // tuning overrides (used by the autotuning sweeps)
-    if (const char *v = getenv("DSA_STRIP")) {
-        const int t = atoi(v);
-        if (t == 16 || t == 32) P.T = t;
-    }
-    if (const char *v = getenv("DSA_WAVES")) {
-        const int w = atoi(v);
-        if (w >= 1 && w <= 8) P.wpb16 = w;
-    }
     // the plain form runs one query at a time, so the wavefront kernel has to
     // take more of each query's work to keep the GPU busy
     P.budget = P.persistent ? 64000 : 16000;
-    if (const char *v = getenv("DSA_INTRA_BUDGET")) P.budget = atoll(v);
+    const Tuning tu = tuning_for(search_key(a, db->n_residues));
+    if (tu.strip == 16 || (tu.strip == 32 && search16_lds_bytes(32, db->AP) <= 160 * 1024)) P.T = tu.strip;
+    if (tu.waves >= 1 && tu.waves <= 8) P.wpb16 = tu.waves;
+    if (tu.intra_budget >= 0) P.budget = tu.intra_budget;
     P.lds16 = search16_lds_bytes(P.T, db->AP);
     P.lds32 = search32_lds_bytes(db->AP);
     if (P.lds16 > 160 * 1024) return fail(DSA_E_NOTSUP, "alphabet too large for the LDS profile");
@@ -1380,7 +1518,7 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
         if (sp.empty()) return DSA_OK;
         PairPlan PP;
         build_pair_plan(sp, nq * P.K, P.mode, P.ends, true, out->cigar_capacity, A,
-                        std::min(P.pair_caps.tb, P.pair_caps.tbw) * 4, PP, false, pair_route());
+                        std::min(P.pair_caps.tb, P.pair_caps.tbw) * 4, PP, false, pair_route(Tuning()));
         const PairCaps need = caps_of(PP);
         const PairCaps &cap = P.pair_caps;
         if (need.slots > cap.slots || need.groups > cap.groups || need.wf > cap.wf || need.bnd > cap.bnd ||
@@ -1498,6 +1636,204 @@ extern "C" int dsa_graph_launch(dsa_graph *g, void *stream) {
 
 extern "C" int dsa_graph_destroy(dsa_graph *g) {
     graph_free(g);
+    return DSA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuning
+
+static void to_public(const Tuning &t, dsa_tuning *o) {
+    o->strip = t.strip;
+    o->waves = t.waves;
+    o->intra_budget = t.intra_budget;
+    o->pair_rows = t.pair_rows;
+    o->pair_cells = t.pair_cells;
+    o->ms = t.ms;
+}
+
+extern "C" int dsa_tuning_key(const dsa_args *args, char *buf, size_t size) {
+    int rc = check_common(args);
+    if (rc) return rc;
+    if (!buf || size == 0) return fail(DSA_E_INVAL, "buf is NULL");
+    if (!args->db && (!args->t_codes || !args->t_offsets))
+        return fail(DSA_E_INVAL, "pairwise needs t_codes and t_offsets");
+    const std::string k = args->db ? search_key(args, args->db->n_residues) : pair_key(args);
+    snprintf(buf, size, "%s", k.c_str());
+    return k.size() < size ? DSA_OK : fail(DSA_E_INVAL, "buf too small");
+}
+
+extern "C" int dsa_tuning_get(const dsa_args *args, dsa_tuning *out) {
+    if (!out) return fail(DSA_E_INVAL, "out is NULL");
+    int rc = check_common(args);
+    if (rc) return rc;
+    Tuning t;
+    if (args->db) {
+        Plan P;
+        if ((rc = make_plan(args, P))) return rc;
+        t.strip = P.T;
+        t.waves = P.wpb16;
+        t.intra_budget = P.budget;
+        t.ms = tuning_for(search_key(args, args->db->n_residues)).ms;
+    } else {
+        if (!args->t_codes || !args->t_offsets) return fail(DSA_E_INVAL, "pairwise needs t_codes and t_offsets");
+        const Tuning tu = tuning_for(pair_key(args));
+        const PairRoute r = pair_route(tu);
+        t.pair_rows = r.rows;
+        t.pair_cells = r.cells;
+        t.ms = tu.ms;
+    }
+    to_public(t, out);
+    return DSA_OK;
+}
+
+namespace {
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() { if (p) hipFree(p); }
+};
+}  // namespace
+
+extern "C" int dsa_autotune(const dsa_args *args, const char *cache_path, dsa_tuning *chosen) {
+    int rc = check_common(args);
+    if (rc) return rc;
+    const bool search = args->db != nullptr;
+    if (!search && (!args->t_codes || !args->t_offsets))
+        return fail(DSA_E_INVAL, "pairwise needs t_codes and t_offsets");
+    const bool plain = (args->flags & DSA_PLAIN) != 0;
+    const std::string key = search ? search_key(args, args->db->n_residues) : pair_key(args);
+    hipStream_t st = (hipStream_t)args->stream;
+
+    // first sweep: strip height x wavefront cutover (search) or pair routing rows
+    std::vector<Tuning> first;
+    if (search) {
+        const int64_t none = (int64_t)1 << 60;  // no wavefront kernel
+        const std::vector<int64_t> budgets = plain ? std::vector<int64_t>{4000, 8000, 16000, 32000, 64000, none}
+                                                   : std::vector<int64_t>{16000, 32000, 64000, 128000, 256000, none};
+        for (int strip : {32, 16})
+            for (int64_t b : budgets) {
+                Tuning t;
+                t.strip = strip;
+                t.waves = 8;
+                t.intra_budget = b;
+                first.push_back(t);
+            }
+    } else {
+        for (int64_t rows : {(int64_t)48, (int64_t)64, (int64_t)96, (int64_t)128, (int64_t)192, (int64_t)256,
+                             (int64_t)512, (int64_t)1 << 30}) {
+            Tuning t;
+            t.pair_rows = rows;
+            t.pair_cells = 32768;
+            first.push_back(t);
+        }
+    }
+    // scratch sized for every candidate of both sweeps
+    auto second_of = [&](const Tuning &b) {
+        std::vector<Tuning> v;
+        if (search) {
+            for (int w : {2, 4}) { Tuning t = b; t.waves = w; v.push_back(t); }
+        } else {
+            for (int64_t c : {(int64_t)0, (int64_t)8192, (int64_t)131072, (int64_t)524288}) {
+                Tuning t = b; t.pair_cells = c; v.push_back(t);
+            }
+        }
+        return v;
+    };
+    size_t ws_max = 0;
+    {
+        std::vector<Tuning> all = first;
+        for (const Tuning &b : first) for (const Tuning &t : second_of(b)) all.push_back(t);
+        for (const Tuning &t : all) {
+            t_force = &t;
+            size_t b = 0;
+            const int r = dsa_workspace_size(args, &b);
+            t_force = nullptr;
+            if (r == DSA_OK) ws_max = std::max(ws_max, b);
+        }
+    }
+    int64_t n_res = search ? (args->top_k ? args->n_q * args->top_k : args->n_q * args->db->n_targets) : args->n_q;
+    n_res = std::max<int64_t>(n_res, 1);
+    int64_t cig = 0;
+    if (args->flags & DSA_TRACEBACK) {
+        if ((rc = dsa_cigar_capacity(args, &cig))) return rc;
+    }
+    DevBuf ws, res, cigb;
+    HIPCHK(hipMalloc(&ws.p, std::max<size_t>(ws_max, 256)));
+    const size_t res_bytes = (size_t)n_res * (5 * 4 + 8 + 8 + 4 + 1) + 1024;
+    HIPCHK(hipMalloc(&res.p, res_bytes));
+    HIPCHK(hipMalloc(&cigb.p, std::max<int64_t>(cig, 1) * 4));
+    dsa_out o;
+    memset(&o, 0, sizeof(o));
+    uint8_t *rb = (uint8_t *)res.p;
+    auto take = [&](size_t bytes) { uint8_t *p = rb; rb += align_up(bytes, 256); return p; };
+    o.score = (int32_t *)take(n_res * 4);
+    o.q_begin = (int32_t *)take(n_res * 4);
+    o.q_end = (int32_t *)take(n_res * 4);
+    o.t_begin = (int32_t *)take(n_res * 4);
+    o.t_end = (int32_t *)take(n_res * 4);
+    o.t_index = args->top_k ? (int64_t *)take(n_res * 8) : nullptr;
+    o.status = take(n_res);
+    if (args->flags & DSA_TRACEBACK) {
+        o.cigar_off = (int64_t *)take(n_res * 8);
+        o.cigar_len = (int32_t *)take(n_res * 4);
+        o.cigar_ops = (uint32_t *)cigb.p;
+        o.cigar_capacity = cig;
+    }
+    dsa_args a = *args;
+    a.workspace = ws.p;
+    a.workspace_bytes = ws_max;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto time_one = [&](const Tuning &t, double *ms) -> int {
+        t_force = &t;
+        int r = DSA_OK;
+        double best = 1e300;
+        for (int rep = 0; rep < 3 && r == DSA_OK; rep++) {  // the first run warms up
+            if (hipEventRecord(e0, st) != hipSuccess) { r = DSA_E_DEVICE; break; }
+            r = dsa_align_batch(&a, &o);
+            if (r != DSA_OK) break;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { r = DSA_E_DEVICE; break; }
+            float f = 0.f;
+            hipEventElapsedTime(&f, e0, e1);
+            if (rep > 0) best = std::min(best, (double)f);
+        }
+        t_force = nullptr;
+        *ms = best;
+        return r;
+    };
+    Tuning best;
+    double best_ms = 1e300;
+    int tried = 0;
+    auto sweep = [&](const std::vector<Tuning> &cands) -> int {
+        for (const Tuning &t : cands) {
+            double ms = 0;
+            const int r = time_one(t, &ms);
+            if (r == DSA_E_DEVICE) return r;
+            if (r != DSA_OK) continue;  // a candidate this input cannot use (e.g. LDS)
+            tried++;
+            if (ms < best_ms) { best_ms = ms; best = t; }
+        }
+        return DSA_OK;
+    };
+    rc = sweep(first);
+    if (rc == DSA_OK && tried) rc = sweep(second_of(best));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return fail(rc, std::string("autotune: ") + dsa_last_error());
+    if (!tried) return fail(DSA_E_NOTSUP, "autotune: no candidate ran for these arguments");
+    best.ms = best_ms;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[key] = best;
+        if (cache_path && *cache_path) {
+            std::map<std::string, Tuning> merged;
+            load_cache_file(cache_path, &merged);
+            merged[key] = best;
+            if (!save_cache_file(cache_path, merged))
+                return fail(DSA_E_INVAL, std::string("autotune: cannot write ") + cache_path);
+        }
+    }
+    if (chosen) to_public(best, chosen);
     return DSA_OK;
 }
 
