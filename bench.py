@@ -115,9 +115,10 @@ def run_other_workloads(args, dsa, B, torch, gen, dev):
     """Batched vs plain on the other workloads: the single 64-residue query
     vs 1,000 targets (local, score + end), 100,000 DNA read / window pairs
     (local with CIGAR) and 50,000 protein pairs of log-uniform length in
-    [100, 3000] (global and semi-global with CIGAR).  Batched = the call
-    recorded once into a HIP graph and replayed (inputs resident on the
-    device); plain = one launch per query, or per pair, through
+    [100, 3000] (global and semi-global with CIGAR).  Batched = for the
+    single query, the call recorded once into a HIP graph and replayed; for
+    pairs, dsa_align_batch on prepared device buffers (graph replay reported
+    beside it); plain = one launch per query, or per pair, through
     dsa_align_batch on prepared buffers.  The plain pairwise form is timed on
     the first `plain_pairs` pairs of the same list."""
     out = {}
@@ -173,13 +174,19 @@ def run_other_workloads(args, dsa, B, torch, gen, dev):
 
     def pair_leg(name, Q, T, S, o, e, mode, reps=3):
         cells = int((Q.lengths * T.lengths).sum())
-        # device-time breakdown from one timed eager call
+        tuned = None
+        if args.autotune:
+            t0 = time.perf_counter()
+            tuned = dsa.autotune(Q, targets=T, matrix=S, gap_open=o, gap_extend=e, mode=mode, traceback=True)
+            tuned["tuning_s"] = round(time.perf_counter() - t0, 2)
+            log(f"{name} autotune: {tuned}")
+        # the batched call on prepared buffers (host planning included), then
+        # its device-time breakdown from the library's event timing
         call = prepared_call(Q, S, o, e, mode, False, targets=T, traceback=True)
-        call()
-        torch.cuda.synchronize()
+        dt = timed(call, reps)
         B.dsa_timing_reset()
         B.dsa_timing_enable(True)
-        edt = timed(call, 1)
+        timed(call, 1)
         dev_ms = {}
         for nm, kind in (("span", B.TIMING_SPAN), ("lane", B.TIMING_PAIR_LANE), ("wavefront", B.TIMING_PAIR_WF)):
             tot, cnt = B.dsa_timing_read(kind)
@@ -187,8 +194,9 @@ def run_other_workloads(args, dsa, B, torch, gen, dev):
         B.dsa_timing_enable(False)
         B.dsa_timing_reset()
         del call
+        # the same call recorded into a HIP graph and replayed (code chunks in order)
         rec = dsa.Recorded(Q, targets=T, matrix=S, gap_open=o, gap_extend=e, mode=mode, traceback=True)
-        dt = graph_rate(rec, reps)
+        gdt = graph_rate(rec, reps)
         rec.close()
         del rec
         n = min(args.plain_pairs, len(Q))
@@ -197,10 +205,11 @@ def run_other_workloads(args, dsa, B, torch, gen, dev):
         pdt = timed(prepared_call(Qs, S, o, e, mode, True, targets=Ts, traceback=True), 1)
         bg, pg = cells / dt / 1e9, pcells / pdt / 1e9
         res = {"pairs": len(Q), "cells": cells,
-               "batched": {"gcups": round(bg, 2), "ms": round(dt * 1e3, 2),
-                           "eager_call_ms": round(edt * 1e3, 2), "device_ms": dev_ms},
+               "batched": {"gcups": round(bg, 2), "ms": round(dt * 1e3, 2), "device_ms": dev_ms,
+                           "device_gcups": round(cells / (dev_ms["span"] * 1e-3) / 1e9, 2),
+                           "graph_replay_ms": round(gdt * 1e3, 2)},
                "plain": {"gcups": round(pg, 3), "ms": round(pdt * 1e3, 2), "pairs": n, "cells": pcells},
-               "batched_over_plain": round(bg / pg, 1), "traceback": "CIGAR"}
+               "batched_over_plain": round(bg / pg, 1), "traceback": "CIGAR", "autotuned": tuned}
         log(f"{name}: {res}")
         out[name] = res
 
@@ -226,6 +235,8 @@ def main():
                     help="requests in the serving window (0 = skip the serving leg)")
     ap.add_argument("--serving-targets", type=int, default=500_000)
     ap.add_argument("--other", type=int, default=1, help="1 = also time the other workloads")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1 = run dsa_autotune on each workload before timing it")
     ap.add_argument("--plain-pairs", type=int, default=500,
                     help="pairs timed in the one-launch-per-pair form")
     args = ap.parse_args()
@@ -299,6 +310,16 @@ def main():
             B.dsa_timing_reset()
         return dt, tm, outs
 
+    tuned = {}
+    if args.autotune:
+        for form, plain in (("batched", False), ("plain", True)):
+            if plain and args.plain_steps <= 0:
+                continue
+            t0 = time.perf_counter()
+            ch = dsa.autotune(Q, db=db, matrix=S, gap_open=11, gap_extend=1, plain=plain)
+            ch["tuning_s"] = round(time.perf_counter() - t0, 2)
+            tuned[form] = ch
+            log(f"autotune {form}: {ch}")
     log(f"eager batched call with kernel timing: {args.warmup} warmup + {args.steps} steps")
     edt, tm, outs = run(False, args.warmup, args.steps, timing=True)
     eager_ms = edt / args.steps * 1e3
@@ -404,6 +425,7 @@ def main():
                    "residues": int(T.lengths.sum()),
                    "form": "batched (persistent, LPT units, replayed from a HIP graph)"},
         "eager_call_ms": round(eager_ms, 3),
+        "autotuned": tuned or None,
         "graph_replay_equals_eager": graph_agrees,
         "plain": None if plain_gcups is None else {
             "value": round(plain_gcups, 2), "unit": "GCUPS", "ms_per_step": round(plain_ms, 3),

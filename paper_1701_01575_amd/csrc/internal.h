@@ -112,6 +112,7 @@ size_t intra16_lds_bytes(int AP, int A);
 // the strip count.
 constexpr int kTP = 16;           // rows per strip in the pairwise kernel
 constexpr int kPairWaves = 4;     // waves (groups) per block
+constexpr int kWfBlock = 16;      // steps per lane per block of wavefront direction codes
 
 struct PairInfo {
     int64_t q_off, t_off;         // into the query / target code buffers

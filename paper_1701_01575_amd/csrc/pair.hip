@@ -225,8 +225,37 @@ hipError_t launch_pair32(const PairArgs &a, int mode, hipStream_t s) {
 // segment; between passes the segment's last lane hands its last row over
 // through the pair's boundary row in HBM.  Exact int32, the same
 // recurrence, direction codes and end-cell rule as k_pair32.  A lane's 16
-// codes of one step are 64 bits, stored at (pass, step, lane) so that a
-// segment's store of one step is SEG * 8 contiguous bytes.
+// codes of one step are 64 bits, stored in blocks of kWfBlock steps per lane
+// ([pass][step / 16][lane][step % 16]): a diagonal or horizontal move of the
+// traceback walk then stays inside one 128-byte line 15 times out of 16.
+// H[r] for a per-lane row r: lanes that share r (one per segment at most)
+// take it by a uniform index, one distinct r at a time.
+template <int T>
+__device__ __forceinline__ int row_of(const int (&H)[T], int r) {
+    static_assert(T == 16, "row_of is written for 16-row strips");
+    int v = 0;
+    for (;;) {
+        int u = __builtin_amdgcn_readfirstlane(r);
+        asm volatile("" : "+s"(u));  // keep the index uniform: branch on it, do not select per lane
+        // a branch per row on the uniform index; the empty asm keeps the
+        // compiler from folding the cases into an indexed load of H, which
+        // would move H out of registers
+        int c;
+#define DSA_ROW(k) case k: c = H[k]; asm volatile("" : "+v"(c)); break;
+        switch (u) {
+            DSA_ROW(0) DSA_ROW(1) DSA_ROW(2) DSA_ROW(3) DSA_ROW(4) DSA_ROW(5) DSA_ROW(6) DSA_ROW(7)
+            DSA_ROW(8) DSA_ROW(9) DSA_ROW(10) DSA_ROW(11) DSA_ROW(12) DSA_ROW(13) DSA_ROW(14)
+            default: c = H[15]; asm volatile("" : "+v"(c)); break;
+        }
+#undef DSA_ROW
+        if (r == u) {
+            v = c;
+            break;
+        }
+    }
+    return v;
+}
+
 template <int MODE, bool TB, int SEG>
 __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
     constexpr int T = kTP;
@@ -248,7 +277,8 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
     const int nsteps = n + SEG - 1;
     const uint8_t *qc = P.q_codes + I.q_off, *tc = P.t_codes + I.t_off;
     uint2 *bnd = P.bnd + W.bnd;
-    uint2 *tb = reinterpret_cast<uint2 *>(P.tb) + W.tb + lane;
+    uint2 *tb = reinterpret_cast<uint2 *>(P.tb) + W.tb + lane * kWfBlock;
+    const int nblk = (nsteps + kWfBlock - 1) / kWfBlock;
 
     uint64_t gk = end_key(0, 0, 0);  // local: this lane's best over its strips
     int gs = 0, gj = 0;              // global / semi: held by the lane of the last strip
@@ -270,6 +300,8 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
         int res = 0, Ls = 0, Lj = 0;
         if (MODE != LOCAL && last) { res = left_value(MODE, ends, o, e, m); Ls = res; }
         int outH = 0, outF = 0;
+        // E-extend bits of the lane's next column, known one column early
+        uint32_t eN[2] = {0u, 0u};
         // the next step's target code, and lane 0's next boundary word
         int cnext = (lane == 0 && act && n > 0) ? (int)tc[0] : 0;
         uint2 bnext = make_uint2(0u, 0u);
@@ -298,29 +330,35 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
                 int F = rF;
                 int ho_up = rH - o;
                 int cm = 0;
-                uint32_t acc[2] = {0u, 0u};
+                uint32_t acc[2] = {eN[0], eN[1]};
+                eN[0] = 0u;
+                eN[1] = 0u;
 #pragma unroll
                 for (int r = 0; r < T; r++) {
                     const int tv = Hd + sm[rowb[r] + b];
-                    const int Hold = H[r];
-                    Hd = Hold;
+                    Hd = H[r];
                     const int Ein = E[r], Fin = F;
                     int h = max(max(tv, Ein), Fin);
                     if (MODE == LOCAL) { h = max(h, 0); cm = max(cm, h); }
                     const int ho = h - o;
-                    E[r] = max(Ein - e, ho);
+                    const int Ee = Ein - e;
+                    E[r] = max(Ee, ho);
                     F = max(Fin - e, ho);
                     H[r] = h;
                     if (TB) {
-                        uint32_t src = (h == tv) ? 1u : ((h == Ein) ? 2u : 3u);
-                        if (MODE == LOCAL && h == 0) src = 0u;
-                        const uint32_t eext = (Ein != Hold - o) ? 4u : 0u;
-                        const uint32_t fext = (Fin != ho_up) ? 8u : 0u;
-                        acc[r >> 3] |= (src | eext | fext) << (4 * (r & 7));
+                        const int sh = 4 * (r & 7);
+                        uint32_t src = (h == tv) ? (1u << sh) : ((h == Ein) ? (2u << sh) : (3u << sh));
+                        if (MODE == LOCAL && h == 0) src = 0u;  // extend bits of a zero cell are never read
+                        const uint32_t fext = (Fin != ho_up) ? (8u << sh) : 0u;
+                        acc[r >> 3] |= src | fext;
+                        // E of (i, j + 1) extends iff E - e beats H - o here (open wins ties)
+                        eN[r >> 3] |= (Ee > ho) ? (4u << sh) : 0u;
                     }
                     ho_up = ho;
                 }
-                if (TB) tb[((int64_t)pass * nsteps + t) * SEG] = make_uint2(acc[0], acc[1]);
+                if (TB)
+                    tb[((int64_t)pass * nblk + t / kWfBlock) * (SEG * kWfBlock) + (t % kWfBlock)] =
+                        make_uint2(acc[0], acc[1]);
                 if (MODE == LOCAL) {
                     if (cm > B) {
                         int rr = 0;
@@ -328,12 +366,10 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
                         for (int r = T - 1; r >= 0; r--) rr = (H[r] == cm) ? r : rr;
                         B = cm; Bj = j; Bi = i0 + rr + 1;
                     }
-                } else if (last) {
-                    int vl = H[0];
-#pragma unroll
-                    for (int k = 1; k < T; k++) vl = (k == rlast) ? H[k] : vl;
+                } else if (last && ((ends & TE) || j == n)) {
+                    const int vl = row_of<T>(H, rlast);
                     if (!(ends & TE)) {
-                        if (j == n) res = vl;
+                        res = vl;
                     } else if (vl > Ls) {
                         Ls = vl; Lj = j;
                     }
@@ -439,8 +475,11 @@ constexpr uint32_t OP_I = 1, OP_D = 2, OP_EQ = 7, OP_X = 8;
 
 // Walk one pair back from its end cell (1-based i, j; i < 0 = nothing to
 // trace) through the direction codes that code(i, j) returns.
-template <int MODE, class Code>
-__device__ void walk_pair(const PairArgs &P, const PairInfo &I, int i, int j, Code code) {
+// eq(i, j) tells whether query residue i and target residue j (1-based) are
+// equal.  refill(i, j) runs before every 16th step from a cell with i, j >= 1:
+// the next 16 steps read only rows (i - 16, i] and columns (j - 16, j].
+template <int MODE, class Code, class Eq, class Refill>
+__device__ void walk_pair(const PairArgs &P, const PairInfo &I, int i, int j, Code code, Eq eq, Refill refill) {
     const int ends = P.ends;
     RunWriter W{P.cigar, I.cig_off, I.cig_off + I.cig_cap};
     if (i < 0) {  // local alignment of score 0: nothing to trace
@@ -450,10 +489,10 @@ __device__ void walk_pair(const PairArgs &P, const PairInfo &I, int i, int j, Co
         P.cig_len_out[I.res] = 0;
         return;
     }
-    const uint8_t *qc = P.q_codes + I.q_off, *tc = P.t_codes + I.t_off;
     int state = 0;  // 0 = H, 1 = E, 2 = F
     const int max_steps = I.m + I.n + 2;
     for (int step = 0; step < max_steps; step++) {
+        if ((step & 15) == 0 && i > 0 && j > 0) refill(i, j);
         if (state == 0) {
             if (i == 0 || j == 0) {
                 if (MODE == LOCAL) break;
@@ -464,7 +503,7 @@ __device__ void walk_pair(const PairArgs &P, const PairInfo &I, int i, int j, Co
             const uint32_t src = code(i, j) & 3u;
             if (src == 0u) break;
             if (src == 1u) {
-                W.emit(qc[i - 1] == tc[j - 1] ? OP_EQ : OP_X, 1);
+                W.emit(eq(i, j) ? OP_EQ : OP_X, 1);
                 i--; j--;
             } else {
                 state = (src == 2u) ? 1 : 2;
@@ -503,34 +542,104 @@ __global__ void k_walk(PairArgs P, int64_t slot0, int64_t n_slots) {
     const PairInfo I = P.pairs[slot];
     const uint32_t *tb = P.tb + G.tb + lane;
     const int ncols = G.ncols;
-    walk_pair<MODE>(P, I, P.end_i[slot], P.end_j[slot], [&](int ii, int jj) -> uint32_t {
-        const int s = (ii - 1) / kTP, r = (ii - 1) % kTP;
-        const uint32_t w = tb[(((int64_t)s * ncols + (jj - 1)) * 2 + (r >> 3)) * kWave];
-        return (w >> (4 * (r & 7))) & 15u;
-    });
+    const uint8_t *qc = P.q_codes + I.q_off, *tc = P.t_codes + I.t_off;
+    walk_pair<MODE>(
+        P, I, P.end_i[slot], P.end_j[slot],
+        [&](int ii, int jj) -> uint32_t {
+            const int s = (ii - 1) / kTP, r = (ii - 1) % kTP;
+            const uint32_t w = tb[(((int64_t)s * ncols + (jj - 1)) * 2 + (r >> 3)) * kWave];
+            return (w >> (4 * (r & 7))) & 15u;
+        },
+        [&](int ii, int jj) { return qc[ii - 1] == tc[jj - 1]; }, [](int, int) {});
 }
 
-// Walk of the wavefront kernel's pairs: one thread per pair.
+// Walk of the wavefront kernel's pairs: one thread per pair.  The walk is a
+// chain of dependent steps, so every 16 steps each thread fetches all it
+// can need next in one batch of independent loads: the up to four 128-byte
+// code blocks (16 steps of one lane) covering rows (i - 16, i] and columns
+// (j - 16, j] into LDS, and the 16 query and target residues before i and j
+// into registers.  The 16 steps then read only LDS and registers.
+constexpr int kWalkThreads = 64;
+
+__device__ __forceinline__ int byte_of(const uint32_t (&w)[4], int k) {
+    const uint32_t x = (k < 8) ? ((k < 4) ? w[0] : w[1]) : ((k < 12) ? w[2] : w[3]);
+    return (int)((x >> (8 * (k & 3))) & 0xffu);
+}
+
+__device__ __forceinline__ void load_window(const uint8_t *seq, int len, int base, uint32_t (&w)[4]) {
+    uint32_t v[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int k = 0; k < 16; k++)
+        if (base + k < len) v[k >> 2] |= (uint32_t)seq[base + k] << (8 * (k & 3));
+#pragma unroll
+    for (int k = 0; k < 4; k++) w[k] = v[k];
+}
+
 template <int MODE>
-__global__ void k_walk_wf(PairArgs P) {
+__global__ void __launch_bounds__(kWalkThreads) k_walk_wf(PairArgs P) {
+    __shared__ uint4 cache[kWalkThreads * 4 * 8];  // per thread: 4 blocks x 128 bytes
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= P.n_wf) return;
     const WfPair W = P.wf[k];
     const PairInfo I = P.pairs[W.slot];
-    const uint32_t *tb = P.tb + 2 * W.tb;
+    const uint2 *tb = reinterpret_cast<const uint2 *>(P.tb) + W.tb;
     const int seg = W.seg;
-    const int64_t nsteps = I.n + seg - 1;
-    walk_pair<MODE>(P, I, P.end_i[W.slot], P.end_j[W.slot], [&](int ii, int jj) -> uint32_t {
-        const int s = (ii - 1) / kTP, r = (ii - 1) % kTP;
-        const int pass = s / seg, lane = s % seg;
-        const uint32_t w = tb[(((int64_t)pass * nsteps + (jj - 1 + lane)) * seg + lane) * 2 + (r >> 3)];
-        return (w >> (4 * (r & 7))) & 15u;
-    });
+    const int nblk = (I.n + seg - 1 + kWfBlock - 1) / kWfBlock;
+    uint4 *mine = cache + threadIdx.x * 32;
+    const uint2 *mine2 = reinterpret_cast<const uint2 *>(mine);
+    const uint8_t *qc = P.q_codes + I.q_off, *tc = P.t_codes + I.t_off;
+    int s_lo = 0, blo0 = 0, blo1 = 0, qbase = 0, tbase = 0;
+    uint32_t qw[4] = {0u, 0u, 0u, 0u}, tw[4] = {0u, 0u, 0u, 0u};
+    auto refill = [&](int i, int j) {
+        const int s_hi = (i - 1) / kTP;
+        s_lo = s_hi - 1;
+        uint4 v[4][8];
+        int bl[2] = {0, 0};
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            const int s = s_lo + c;
+            const int pass = s / seg, lane = s % seg;
+            bl[c] = (max(j - 16, 0) + lane) / kWfBlock;
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                const int b = bl[c] + q;
+                if (s >= 0 && b < nblk) {
+                    const uint4 *src = reinterpret_cast<const uint4 *>(
+                        tb + (((int64_t)pass * nblk + b) * seg + lane) * kWfBlock);
+#pragma unroll
+                    for (int x = 0; x < 8; x++) v[2 * c + q][x] = src[x];
+                }
+            }
+        }
+        blo0 = bl[0];
+        blo1 = bl[1];
+        qbase = max(i - 16, 0);
+        tbase = max(j - 16, 0);
+        load_window(qc, I.m, qbase, qw);
+        load_window(tc, I.n, tbase, tw);
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+#pragma unroll
+            for (int x = 0; x < 8; x++) mine[c * 8 + x] = v[c][x];
+    };
+    walk_pair<MODE>(
+        P, I, P.end_i[W.slot], P.end_j[W.slot],
+        [&](int ii, int jj) -> uint32_t {
+            const int s = (ii - 1) / kTP, r = (ii - 1) % kTP;
+            const int c = s - s_lo;  // 0 or 1
+            const int t = jj - 1 + s % seg;
+            const int slot = 2 * c + (t / kWfBlock - (c ? blo1 : blo0));
+            const uint2 v = mine2[slot * kWfBlock + t % kWfBlock];
+            const uint32_t w = (r < 8) ? v.x : v.y;
+            return (w >> (4 * (r & 7))) & 15u;
+        },
+        [&](int ii, int jj) { return byte_of(qw, ii - 1 - qbase) == byte_of(tw, jj - 1 - tbase); },
+        refill);
 }
 
 hipError_t launch_walk_wf(const PairArgs &a, int mode, hipStream_t s) {
     if (a.n_wf <= 0) return hipSuccess;
-    const int bs = 64;
+    const int bs = kWalkThreads;
     const unsigned nb = (unsigned)((a.n_wf + bs - 1) / bs);
     if (mode == LOCAL) hipLaunchKernelGGL(k_walk_wf<LOCAL>, dim3(nb), dim3(bs), 0, s, a);
     else if (mode == GLOBAL) hipLaunchKernelGGL(k_walk_wf<GLOBAL>, dim3(nb), dim3(bs), 0, s, a);

@@ -91,8 +91,9 @@ int timing_end(hipStream_t st, size_t slot) {
 // default priority).  One per calling thread and device, so concurrent
 // calls from different threads never share fork / join events.
 struct Aux {
-    hipStream_t s = nullptr;
+    hipStream_t s = nullptr, s2 = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    std::vector<hipEvent_t> ev;  // ordering events of pipelined chunks
 };
 thread_local Aux t_aux[64];
 
@@ -100,6 +101,7 @@ int aux_get(int dev, Aux **out) {
     Aux &A = t_aux[dev & 63];
     if (!A.s) {
         HIPCHK(hipStreamCreateWithFlags(&A.s, hipStreamNonBlocking));
+        HIPCHK(hipStreamCreateWithFlags(&A.s2, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&A.fork, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&A.join, hipEventDisableTiming));
     }
@@ -577,6 +579,7 @@ struct PairPlan {
     std::vector<WfPair> wf;             // wavefront pairs; their slots follow the groups'
     std::vector<int64_t> wf_chunk_first;
     int64_t wf_tb_max = 0, wf_tb_total = 0, wf_bnd_total = 0;  // uint32 / uint32 / uint2
+    int wf_buffers = 1;                 // code buffers of wf_tb_max words each
     std::vector<std::pair<int, int64_t>> plain_seq;  // plain: (0 group | 1 wavefront, index) in input order
     size_t off_slots = 0, off_groups = 0, off_wf = 0, off_subst = 0, table_bytes = 0;
     size_t off_end = 0, off_bnd = 0, off_tpk = 0, off_tb = 0, off_bndw = 0, off_tbw = 0, total = 0;
@@ -591,7 +594,7 @@ PairCaps caps_of(const PairPlan &P) {
     c.tpk = P.tpk_total;
     c.tb = P.tb_max;
     c.bndw = P.wf_bnd_total;
-    c.tbw = P.wf_tb_max;
+    c.tbw = P.wf_tb_max * P.wf_buffers;
     return c;
 }
 
@@ -618,7 +621,7 @@ struct PairSpec {
 };
 
 int64_t tb_budget_bytes() {
-    int64_t b = (int64_t)4 << 30;  // bytes of direction codes per chunk
+    int64_t b = (int64_t)8 << 30;  // bytes of direction codes per chunk
     if (const char *v = getenv("DSA_TB_BUDGET")) b = std::max<int64_t>(atoll(v), 1 << 20);
     return b;
 }
@@ -758,7 +761,8 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
         const PairSpec &x = sp[worder[k]];
         const int seg = wf_seg(x.m);
         const int64_t strips_w = (x.m + kTP - 1) / kTP, passes = (strips_w + seg - 1) / seg;
-        const int64_t words = traceback ? passes * (x.n + seg - 1) * seg * 2 : 0;
+        const int64_t nblk = (x.n + seg - 1 + kWfBlock - 1) / kWfBlock;
+        const int64_t words = traceback ? passes * nblk * kWfBlock * seg * 2 : 0;
         WfPair W;
         memset(&W, 0, sizeof(W));
         W.slot = (int32_t)P.slots.size();
@@ -794,6 +798,9 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
         P.slots.push_back(I);
     }
     P.wf_chunk_first.push_back((int64_t)P.wf.size());
+    // with several chunks, fills and walks alternate between two code buffers
+    // so that a chunk's walk overlaps the next chunk's fill
+    if (traceback && !plain && P.wf_chunk_first.size() > 2) P.wf_buffers = 2;
     layout_pair_plan(P, caps_of(P), A);
 }
 
@@ -1014,7 +1021,7 @@ int make_search_plan(const dsa_args *a, Plan &P) {
         c.wf = (int64_t)B2.wf.size();
         c.tb = std::max(B1.tb_max, std::min(tb_budget_bytes() / 4, B1.tb_total));
         c.bndw = B2.wf_bnd_total;
-        c.tbw = std::max(B2.wf_tb_max, std::min(tb_budget_bytes() / 4, B2.wf_tb_total));
+        c.tbw = 2 * std::max(B2.wf_tb_max, std::min(tb_budget_bytes() / 4, B2.wf_tb_total));
         P.pair_caps = c;
         PairPlan L;
         layout_pair_plan(L, c, A);
@@ -1134,6 +1141,34 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
         if (P.traceback) HIPCHK(launch_walk_wf(k, P.mode, s));
         return DSA_OK;
     };
+    // chunks of wavefront pairs with two code buffers: fills on `sf`, walks on
+    // `sw`; a fill waits for the walk that last used its buffer
+    auto wf_pipelined = [&](Aux *ax, hipStream_t sf) -> int {
+        hipStream_t sw = ax->s2;
+        const size_t nch = P.wf_chunk_first.size() - 1;
+        if (ax->ev.size() < 2 * nch + 1) {
+            const size_t old = ax->ev.size();
+            ax->ev.resize(2 * nch + 1);
+            for (size_t k = old; k < ax->ev.size(); k++)
+                HIPCHK(hipEventCreateWithFlags(&ax->ev[k], hipEventDisableTiming));
+        }
+        for (size_t c = 0; c < nch; c++) {
+            const int64_t w0 = P.wf_chunk_first[c], w1 = P.wf_chunk_first[c + 1];
+            PairArgs k = KW;
+            k.wf = dw + w0;
+            k.n_wf = (int32_t)(w1 - w0);
+            k.tb = KW.tb + (c & 1) * P.wf_tb_max;
+            if (c >= 2) HIPCHK(hipStreamWaitEvent(sf, ax->ev[2 * (c - 2) + 1], 0));
+            HIPCHK(launch_pairwf(k, P.mode, P.wf[w0].seg, sf));
+            HIPCHK(hipEventRecord(ax->ev[2 * c], sf));
+            HIPCHK(hipStreamWaitEvent(sw, ax->ev[2 * c], 0));
+            HIPCHK(launch_walk_wf(k, P.mode, sw));
+            HIPCHK(hipEventRecord(ax->ev[2 * c + 1], sw));
+        }
+        HIPCHK(hipEventRecord(ax->ev[2 * nch], sw));
+        HIPCHK(hipStreamWaitEvent(sf, ax->ev[2 * nch], 0));
+        return DSA_OK;
+    };
     auto lane_launch = [&](int64_t g0, int64_t g1, hipStream_t s) -> int {
         PairArgs k = K;
         k.groups = dg + g0;
@@ -1179,8 +1214,20 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
     if (!P.wf.empty()) {
         size_t slot;
         if ((rc = timing_begin(ws_st, TK_PAIR_WF, &slot))) return rc;
-        for (size_t c = 0; c + 1 < P.wf_chunk_first.size(); c++)
-            if ((rc = wf_launch(P.wf_chunk_first[c], P.wf_chunk_first[c + 1], ws_st))) return rc;
+        // pipelined chunks are not recorded into graphs: recording them (a
+        // second auxiliary stream joined through the first) crashed inside
+        // dsa_graph_create; a graph replays the chunks in order instead
+        if (P.wf_buffers == 2 && !t_capturing) {
+            if (!aux) {
+                int dev = 0;
+                HIPCHK(hipGetDevice(&dev));
+                if ((rc = aux_get(dev, &aux))) return rc;
+            }
+            if ((rc = wf_pipelined(aux, ws_st))) return rc;
+        } else {
+            for (size_t c = 0; c + 1 < P.wf_chunk_first.size(); c++)
+                if ((rc = wf_launch(P.wf_chunk_first[c], P.wf_chunk_first[c + 1], ws_st))) return rc;
+        }
         if ((rc = timing_end(ws_st, slot))) return rc;
     }
     if (!P.groups.empty()) {
@@ -1518,7 +1565,7 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
         if (sp.empty()) return DSA_OK;
         PairPlan PP;
         build_pair_plan(sp, nq * P.K, P.mode, P.ends, true, out->cigar_capacity, A,
-                        std::min(P.pair_caps.tb, P.pair_caps.tbw) * 4, PP, false, pair_route(Tuning()));
+                        std::min(P.pair_caps.tb, P.pair_caps.tbw / 2) * 4, PP, false, pair_route(Tuning()));
         const PairCaps need = caps_of(PP);
         const PairCaps &cap = P.pair_caps;
         if (need.slots > cap.slots || need.groups > cap.groups || need.wf > cap.wf || need.bnd > cap.bnd ||
