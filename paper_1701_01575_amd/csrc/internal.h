@@ -61,6 +61,10 @@ struct SearchArgs {
     int32_t *unit_flags;          // per unit: 1 = rewrite saturated results, 2 = recompute all
     const int32_t *qflag;         // per query: int16 bound fails (global / semi-global)
     int32_t *counter;             // persistent-grid work counter
+    // persistent form with wavefront units: the work list, longest first;
+    // entry v >= 0 is inter-sequence unit v, v < 0 is wavefront unit -v - 1
+    const int32_t *order;
+    int32_t n_order;
 };
 
 // Intra-sequence (wavefront) work: long targets of long queries.  Targets
@@ -180,7 +184,7 @@ struct TopkArgs {
 hipError_t launch_topk(const TopkArgs &a, hipStream_t s);
 
 // Launchers (kernels.hip).  Return hipSuccess or the launch error.
-hipError_t launch_search16(const SearchArgs &a, int T, int mode, int waves_per_block,
+hipError_t launch_search16(const SearchArgs &a, const IntraArgs &w, int T, int mode, int waves_per_block,
                            int n_blocks, bool persistent, size_t lds_bytes, hipStream_t s);
 hipError_t launch_search32(const SearchArgs &a, int mode, int waves_per_block,
                            int n_blocks, bool persistent, size_t lds_bytes, hipStream_t s,

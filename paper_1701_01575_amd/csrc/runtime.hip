@@ -339,6 +339,7 @@ namespace {
 struct Round {
     int64_t first = 0, inter = 0, count = 0;  // units [first, first + count), inter first
     int64_t ifirst = 0, icount = 0;           // wavefront units
+    int64_t ofirst = 0, ocount = 0;           // work list of the persistent kernel (both kinds)
 };
 
 // ---------------------------------------------------------------------------
@@ -515,6 +516,9 @@ struct Plan {
     std::vector<SearchUnit> units;  // per round: int16 inter units, then int32-only rerun units
     std::vector<IntraUnit> iunits;
     std::vector<Round> rounds;
+    std::vector<int32_t> order;     // persistent form: per round, both unit kinds longest first
+    bool mixed = false;             // persistent form with wavefront units in one kernel
+    size_t ldsM = 0, off_order = 0;
     int64_t budget = 64000;         // strips x columns above which a group goes to the wavefront kernel
     size_t ldsI = 0;
     std::vector<QueryInfo> qinfo;
@@ -878,6 +882,7 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     const int64_t nq = a->n_q;
     P.qinfo.resize(nq);
     P.ldsI = intra16_lds_bytes(db->AP, A);
+    P.ldsM = std::max(P.lds16, P.ldsI);
     for (int64_t q = 0; q < nq; q++) {
         const int64_t m = a->q_offsets[q + 1] - a->q_offsets[q];
         if (m > kMaxLen16) return fail(DSA_E_NOTSUP, "queries longer than 65532 residues are not supported");
@@ -930,11 +935,13 @@ int make_search_plan(const dsa_args *a, Plan &P) {
                 const int32_t ridx = (int32_t)rerun.size();
                 rerun.push_back(R);
                 const int64_t pbase = (g - db->long_group0) * (kGroup / 2);
-                for (int k = 0; k < kGroup / 2; k += kIntraWaves) {
+                // the persistent kernel runs a wavefront unit with all its waves
+                const int per_unit = P.persistent ? wpb : kIntraWaves;
+                for (int k = 0; k < kGroup / 2; k += per_unit) {
                     IntraUnit I;
                     I.q = (int32_t)q;
                     I.lp0 = (int32_t)(pbase + k);
-                    I.np = kIntraWaves;
+                    I.np = std::min(per_unit, kGroup / 2 - k);
                     I.runit = ridx;  // made absolute below
                     I.qslot = qslot;
                     I.pad = 0;
@@ -971,6 +978,29 @@ int make_search_plan(const dsa_args *a, Plan &P) {
             I.runit += (int32_t)(R.first + R.inter);
             P.iunits.push_back(I);
         }
+        if (P.persistent && !P.force32 && !iu.empty()) {
+            // one work list, longest first.  Cost in lane row-columns: an
+            // inter-sequence unit walks its rows over the widest group's
+            // columns; a wavefront unit sweeps (columns + 63) steps of 16 rows
+            // per pass, with a little more work per step.
+            std::vector<std::pair<double, int32_t>> w;
+            for (int64_t k = 0; k < (int64_t)inter.size(); k++) {
+                const SearchUnit &U = inter[k];
+                w.push_back({(double)P.qinfo[U.q].strips * P.T * db->grp[U.g0 + U.ng - 1].ncols, (int32_t)k});
+            }
+            for (int64_t k = 0; k < (int64_t)iu.size(); k++) {
+                const IntraUnit &I = iu[k];
+                const int64_t strips16 = (P.qinfo[I.q].len + kTI - 1) / kTI;
+                const int64_t passes = (strips16 + kWave - 1) / kWave;
+                const double c = 1.15 * passes * (db->pairs[I.lp0 + I.np - 1].ncols + kWave - 1) * kTI;
+                w.push_back({c, -(int32_t)(R.ifirst + k) - 1});
+            }
+            std::stable_sort(w.begin(), w.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+            R.ofirst = (int64_t)P.order.size();
+            R.ocount = (int64_t)w.size();
+            for (auto &x : w) P.order.push_back(x.second);
+            P.mixed = true;
+        }
         if (R.count > 0) P.rounds.push_back(R);
     }
 
@@ -978,6 +1008,7 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     size_t o = 0;
     P.off_units = o; o = align_up(o + std::max<size_t>(P.units.size(), 1) * sizeof(SearchUnit), 256);
     P.off_iunits = o; o = align_up(o + std::max<size_t>(P.iunits.size(), 1) * sizeof(IntraUnit), 256);
+    P.off_order = o; o = align_up(o + std::max<size_t>(P.order.size(), 1) * sizeof(int32_t), 256);
     P.off_qinfo = o; o = align_up(o + 2 * nq * sizeof(QueryInfo), 256);  // int16 and int32 strips
     P.off_subst = o; o = align_up(o + (size_t)A * A, 256);
     P.off_rows = o; o = align_up(o + std::max<size_t>(P.empty_rows.size(), 1) * sizeof(int32_t), 256);
@@ -1311,6 +1342,7 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
         if (!P.units.empty()) memcpy(h + P.off_units, P.units.data(), P.units.size() * sizeof(SearchUnit));
         if (!P.iunits.empty())
             memcpy(h + P.off_iunits, P.iunits.data(), P.iunits.size() * sizeof(IntraUnit));
+        if (!P.order.empty()) memcpy(h + P.off_order, P.order.data(), P.order.size() * sizeof(int32_t));
         memcpy(h + P.off_qinfo, P.qinfo.data(), nq * sizeof(QueryInfo));
         memcpy(h + P.off_qinfo + nq * sizeof(QueryInfo), q32.data(), nq * sizeof(QueryInfo));
         memcpy(h + P.off_subst, a->subst, (size_t)A * A);
@@ -1410,7 +1442,9 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
             size_t slot;
             int trc = timing_begin(st, TK_INTER, &slot);
             if (trc) return trc;
-            HIPCHK(launch_search16(k, P.T, P.mode, P.wpb16, nb, P.persistent, P.lds16, st));
+            IntraArgs none;
+            memset(&none, 0, sizeof(none));
+            HIPCHK(launch_search16(k, none, P.T, P.mode, P.wpb16, nb, P.persistent, P.lds16, st));
             if ((trc = timing_end(st, slot))) return trc;
         } else {
             k.qinfo = qi32;
@@ -1483,10 +1517,38 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
         if (trc) return trc;
     }
 
+    // persistent form: one kernel takes both unit kinds from the round's
+    // longest-first work list (no second stream, so no dependence on which
+    // kernel the hardware dispatches first)
+    const int per_cuM = std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(P.ldsM, 1))));
+    auto mixed = [&](const Round &R) -> int {
+        SearchArgs k = K;
+        k.units = d_units + R.first;
+        k.n_units = (int32_t)R.inter;
+        k.unit_flags = K.unit_flags + R.first;
+        k.qinfo = qi16;
+        k.order = (const int32_t *)(ws + P.off_order) + R.ofirst;
+        k.n_order = (int32_t)R.ocount;
+        k.counter = counter;
+        HIPCHK(launch_fill_i32(counter, 0, 1, st));
+        IntraArgs w = I;
+        w.units = d_iunits;
+        w.n_units = (int32_t)P.iunits.size();
+        w.unit_flags = K.unit_flags;
+        const int nb = (int)std::min<int64_t>(R.ocount, (int64_t)cus * per_cuM);
+        size_t slot;
+        int trc = timing_begin(st, TK_INTER, &slot);
+        if (trc) return trc;
+        HIPCHK(launch_search16(k, w, P.T, P.mode, P.wpb16, nb, true, P.ldsM, st));
+        return timing_end(st, slot);
+    };
     int rc;
     for (const Round &R : P.rounds) {
         const SearchUnit *u = d_units + R.first;
-        if (!P.force32) {
+        if (!P.force32 && R.ocount > 0) {
+            if ((rc = mixed(R))) return rc;
+            if ((rc = pass(u, R.count, 1))) return rc;
+        } else if (!P.force32) {
             if ((rc = intra(d_iunits + R.ifirst, R.icount, K.unit_flags))) return rc;
             if ((rc = pass(u, R.inter, 0))) return rc;
             if ((rc = join(R.icount))) return rc;

@@ -32,6 +32,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "intra_unit.h"
 #include "pk16.h"
 
 namespace dsa {
@@ -94,7 +95,7 @@ hipError_t launch_profile16(const ProfileArgs &a, int T, hipStream_t s) {
 
 template <int T, int MODE, bool PERSIST>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(T <= 16 ? 4 : 2)))
-k_search16(SearchArgs P) {
+k_search16(SearchArgs P, IntraArgs W) {
     extern __shared__ uint4 lds4[];
     uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
     constexpr int SP = T + 4;  // dwords per profile row, a 16-byte multiple
@@ -111,7 +112,16 @@ k_search16(SearchArgs P) {
             __syncthreads();
             u = s_unit;
             __syncthreads();
-            if (u >= P.n_units) return;
+            if (u >= (P.order ? P.n_order : P.n_units)) return;
+            if (P.order) {
+                const int v = P.order[u];
+                if (v < 0) {  // a wavefront unit: the whole block takes it
+                    intra16_unit<MODE>(W, W.units[-v - 1], lds4);
+                    __syncthreads();
+                    continue;
+                }
+                u = v;
+            }
         } else {
             if (iter > 0) return;
             u = blockIdx.x;
@@ -466,7 +476,7 @@ __global__ void __launch_bounds__(1024) k_search32(SearchArgs P, int rerun_only)
 
 // ---------------------------------------------------------------------------
 template <int T>
-static hipError_t launch16_T(const SearchArgs &a, int mode, int wpb, int nb, bool persist,
+static hipError_t launch16_T(const SearchArgs &a, const IntraArgs &w, int mode, int wpb, int nb, bool persist,
                              size_t lds, hipStream_t s) {
     dim3 grid(nb), block(wpb * kWave);
 #define L16(MODE, PER)                                                                  \
@@ -476,7 +486,7 @@ static hipError_t launch16_T(const SearchArgs &a, int mode, int wpb, int nb, boo
                                              hipFuncAttributeMaxDynamicSharedMemorySize, \
                                              (int)lds);                                 \
         if (err != hipSuccess) return err;                                              \
-        hipLaunchKernelGGL(kfn, grid, block, lds, s, a);                                \
+        hipLaunchKernelGGL(kfn, grid, block, lds, s, a, w);                             \
         return hipGetLastError();                                                       \
     } while (0)
     if (mode == LOCAL) { if (persist) L16(LOCAL, true); else L16(LOCAL, false); }
@@ -485,11 +495,11 @@ static hipError_t launch16_T(const SearchArgs &a, int mode, int wpb, int nb, boo
 #undef L16
 }
 
-hipError_t launch_search16(const SearchArgs &a, int T, int mode, int wpb, int nb, bool persist,
-                           size_t lds, hipStream_t s) {
+hipError_t launch_search16(const SearchArgs &a, const IntraArgs &w, int T, int mode, int wpb, int nb,
+                           bool persist, size_t lds, hipStream_t s) {
     switch (T) {
-        case 16: return launch16_T<16>(a, mode, wpb, nb, persist, lds, s);
-        case 32: return launch16_T<32>(a, mode, wpb, nb, persist, lds, s);
+        case 16: return launch16_T<16>(a, w, mode, wpb, nb, persist, lds, s);
+        case 32: return launch16_T<32>(a, w, mode, wpb, nb, persist, lds, s);
         default: return hipErrorInvalidValue;
     }
 }
