@@ -39,7 +39,7 @@ def log(msg):
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ["search.hip", "intra.hip", "pk16.h", "internal.h", "runtime.hip"]:
+    for f in ["search.hip", "intra_unit.h", "pk16.h", "internal.h"]:
         h.update(open(os.path.join(ROOT, "paper_1701_01575_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
