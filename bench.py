@@ -60,10 +60,14 @@ def load_traffic(cells):
 
 
 def run_serving(args, dsa, B, torch, gen, dev):
-    """Serving leg: resident 500,000-target database, a Poisson stream of
-    requests (rate 200/s, 1..64 queries of log-uniform length in [30, 5000]),
-    top-10 hits with traceback, HBM-budget admission, continuous batching
-    over two streams.  Latency = completion - scheduled arrival."""
+    """Serving leg: resident 500,000-target database, Poisson streams of
+    requests (1..64 queries of log-uniform length in [30, 5000]), top-10 hits
+    with traceback, HBM-budget admission, continuous batching over two
+    streams.  Latency = completion - scheduled arrival.  Two windows: the
+    configured rate of 200 requests/s (far beyond one GPU, so its p99 is
+    queueing and its completion rate is the capacity), then a fresh stream
+    at 0.7 x that measured capacity, whose p50 / p99 are the latency of a
+    loaded but stable server."""
     import threading
     from paper_1701_01575_amd.serve import GpuBackend, Server
     c = gen.cfg5_db(n_targets=args.serving_targets)
@@ -72,41 +76,57 @@ def run_serving(args, dsa, B, torch, gen, dev):
     db = dsa.Database.from_seqset(T, S.shape[0])
     torch.cuda.synchronize()
     log(f"serving: {len(T)} targets resident in {time.perf_counter() - t0:.2f}s")
-    reqs = gen.cfg5_requests(args.serving)
     be = GpuBackend(db, S, 11, 1, top_k=10, traceback=True)
     free, total = torch.cuda.mem_get_info(dev)
     budget = int(free * 0.6)
-    srv = Server(be, hbm_budget_bytes=budget, slots=2, max_batch_queries=64)
-    # warm the kernels on one small request outside the window
+    residues = int(T.lengths.sum())
+
+    def window(reqs, rate):
+        srv = Server(be, hbm_budget_bytes=budget, slots=2, max_batch_queries=64)
+        srv.start()
+        futs = []
+        base = time.monotonic()
+
+        def feeder():
+            for arr, q in reqs:
+                delay = base + arr - time.monotonic()
+                if delay > 0:
+                    time.sleep(delay)
+                futs.append(srv.submit(q, arrival=base + arr))
+
+        th = threading.Thread(target=feeder)
+        th.start()
+        th.join()
+        for f in futs:
+            f.result(timeout=1200)
+        srv.stop()
+        st = srv.stats()
+        last = max(r.done for r in srv.completed)
+        cells = sum(int(q.lengths.sum()) for _, q in reqs) * residues
+        return {"requests": len(reqs), "rate_per_s": round(rate, 3), "queries": sum(len(q) for _, q in reqs),
+                "p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
+                "gcups": round(cells / (last - base) / 1e9, 1),
+                "completed_req_per_s": round(len(reqs) / (last - base), 3),
+                "batches": st["batches"], "rejected": st["rejected"]}
+
+    reqs = gen.cfg5_requests(args.serving)
+    # warm the kernels on one small request outside the windows
     be.run(reqs[0][1].subset([0]), be.make_stream())
-    srv.start()
-    futs = []
-    base = time.monotonic()
-
-    def feeder():
-        for arr, q in reqs:
-            delay = base + arr - time.monotonic()
-            if delay > 0:
-                time.sleep(delay)
-            futs.append(srv.submit(q, arrival=base + arr))
-
-    th = threading.Thread(target=feeder)
-    th.start()
-    th.join()
-    for f in futs:
-        f.result(timeout=1200)
-    srv.stop()
-    st = srv.stats()
-    last = max(r.done for r in srv.completed)
-    cells = sum(int(q.lengths.sum()) for _, q in reqs) * int(T.lengths.sum())
-    gcups = cells / (last - base) / 1e9
-    out = {"requests": len(reqs), "rate_per_s": 200, "queries": sum(len(q) for _, q in reqs),
-           "p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
-           "gcups": round(gcups, 1), "capacity_req_per_s": round(len(reqs) / (last - base), 3),
-           "batches": st["batches"], "rejected": st["rejected"],
-           "budget_gb": round(budget / 1e9, 1),
-           "note": "offered load far exceeds one GPU, so p99 measures queueing"}
-    log(f"serving: {out}")
+    over = window(reqs, 200.0)
+    log(f"serving at 200/s: {over}")
+    # a fresh stream whose offered cells per second are 0.7 x the cell rate
+    # the first window completed (request sizes vary, so the rate is set in cells)
+    unit = gen.cfg5_requests(args.serving, rate=1.0, seed_offset=1)
+    mean_cells = sum(int(q.lengths.sum()) for _, q in unit) * residues / len(unit)
+    rate = 0.7 * over["gcups"] * 1e9 / mean_cells
+    steady = window([(arr / rate, q) for arr, q in unit], rate)
+    log(f"serving at 0.7 x capacity: {steady}")
+    out = {"requests": over["requests"], "rate_per_s": 200, "queries": over["queries"],
+           "p50_s": over["p50_s"], "p99_s": over["p99_s"], "gcups": over["gcups"],
+           "capacity_req_per_s": over["completed_req_per_s"], "batches": over["batches"],
+           "rejected": over["rejected"], "budget_gb": round(budget / 1e9, 1),
+           "note": "offered load far exceeds one GPU, so this p99 measures queueing",
+           "at_0.7_capacity": steady}
     db.close()
     return out
 

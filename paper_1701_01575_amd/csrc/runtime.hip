@@ -865,12 +865,15 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     }
     P.min_s = -mn;
     P.max_abs_s = mx;
-    // pick the strip height from the LDS the pair profile needs
-    P.T = 32;
+    // defaults measured on the protein database-search workload (the tuning
+    // table overrides them per shape class): the persistent form prefers
+    // 16-row strips, which hold 4 waves per SIMD, and a high wavefront
+    // cutover; the plain form runs one query at a time, so the wavefront
+    // kernel has to take more of each query's work to keep the GPU busy
+    P.T = P.persistent ? 16 : 32;
     if (search16_lds_bytes(32, db->AP) > 80 * 1024) P.T = 16;
-    // the plain form runs one query at a time, so the wavefront kernel has to
-    // take more of each query's work to keep the GPU busy
-    P.budget = P.persistent ? 64000 : 16000;
+    P.wpb16 = 4;
+    P.budget = P.persistent ? 128000 : 8000;
     const Tuning tu = tuning_for(search_key(a, db->n_residues));
     if (tu.strip == 16 || (tu.strip == 32 && search16_lds_bytes(32, db->AP) <= 160 * 1024)) P.T = tu.strip;
     if (tu.waves >= 1 && tu.waves <= 8) P.wpb16 = tu.waves;
@@ -1893,39 +1896,61 @@ extern "C" int dsa_autotune(const dsa_args *args, const char *cache_path, dsa_tu
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    auto time_one = [&](const Tuning &t, double *ms) -> int {
+    // median of `reps` timed runs after one warm-up run
+    auto time_one = [&](const Tuning &t, int reps, double *ms) -> int {
         t_force = &t;
         int r = DSA_OK;
-        double best = 1e300;
-        for (int rep = 0; rep < 3 && r == DSA_OK; rep++) {  // the first run warms up
+        std::vector<double> v;
+        for (int rep = 0; rep <= reps && r == DSA_OK; rep++) {
             if (hipEventRecord(e0, st) != hipSuccess) { r = DSA_E_DEVICE; break; }
             r = dsa_align_batch(&a, &o);
             if (r != DSA_OK) break;
             if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { r = DSA_E_DEVICE; break; }
             float f = 0.f;
             hipEventElapsedTime(&f, e0, e1);
-            if (rep > 0) best = std::min(best, (double)f);
+            if (rep > 0) v.push_back((double)f);
         }
         t_force = nullptr;
-        *ms = best;
+        if (r == DSA_OK) {
+            std::sort(v.begin(), v.end());
+            *ms = v[v.size() / 2];
+        }
         return r;
     };
-    Tuning best;
-    double best_ms = 1e300;
+    std::vector<std::pair<double, Tuning>> timed_all;
     int tried = 0;
     auto sweep = [&](const std::vector<Tuning> &cands) -> int {
         for (const Tuning &t : cands) {
             double ms = 0;
-            const int r = time_one(t, &ms);
+            const int r = time_one(t, 3, &ms);
             if (r == DSA_E_DEVICE) return r;
             if (r != DSA_OK) continue;  // a candidate this input cannot use (e.g. LDS)
             tried++;
-            if (ms < best_ms) { best_ms = ms; best = t; }
+            timed_all.push_back({ms, t});
         }
         return DSA_OK;
     };
+    auto leader = [&]() {
+        return std::min_element(timed_all.begin(), timed_all.end(),
+                                [](const auto &x, const auto &y) { return x.first < y.first; })->second;
+    };
     rc = sweep(first);
-    if (rc == DSA_OK && tried) rc = sweep(second_of(best));
+    if (rc == DSA_OK && tried) rc = sweep(second_of(leader()));
+    // the three fastest once more, so that run-to-run noise does not pick
+    Tuning best;
+    double best_ms = 1e300;
+    if (rc == DSA_OK && tried) {
+        std::sort(timed_all.begin(), timed_all.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+        const size_t top = std::min<size_t>(3, timed_all.size());
+        for (size_t k = 0; k < top && rc == DSA_OK; k++) {
+            double ms = 0;
+            rc = time_one(timed_all[k].second, 5, &ms);
+            if (rc == DSA_OK && (ms + timed_all[k].first) / 2 < best_ms) {
+                best_ms = (ms + timed_all[k].first) / 2;
+                best = timed_all[k].second;
+            }
+        }
+    }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc) return fail(rc, std::string("autotune: ") + dsa_last_error());

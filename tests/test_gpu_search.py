@@ -39,11 +39,13 @@ CASES = [
 
 @pytest.mark.parametrize("mode,ends", CASES)
 @pytest.mark.parametrize("plain", [False, True], ids=["persistent", "plain"])
-def test_search_modes(mode, ends, plain, blosum, monkeypatch):
+@pytest.mark.parametrize("strip", ["16", "32"])
+def test_search_modes(mode, ends, plain, strip, blosum, monkeypatch):
     monkeypatch.setenv("DSA_INTRA_BUDGET", "1000000000")  # inter-sequence kernel only
+    monkeypatch.setenv("DSA_STRIP", strip)
     T = _targets(1, 300, 180, extra=[1, 2, 3, 4, 5, 399, 400])
     Q = _queries(2, QLENS)
-    log(f"search mode={mode} ends={ends} plain={plain} nq={len(Q)} nt={len(T)}")
+    log(f"search mode={mode} ends={ends} plain={plain} strip={strip} nq={len(Q)} nt={len(T)}")
     got, _ = gpu_search(Q, T, blosum, 11, 1, mode, ends, plain=plain)
     exp = oracle.search(Q, T, blosum, 11, 1, mode=mode, ends=ends)
     compare_search(got, exp, len(Q), len(T), label=f"{mode}/{ends}/{plain}")
