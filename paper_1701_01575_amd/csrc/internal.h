@@ -141,7 +141,7 @@ struct WfPair {
     int64_t tb;       // first uint2 of its direction codes (chunk-relative)
     int64_t bnd;      // first uint2 of its boundary row between passes (n entries)
     int32_t slot;     // its PairInfo and end-cell slot
-    int32_t seg;      // lanes per pair: 16, 32 or 64
+    int32_t seg;      // lanes per pair: 4, 8, 16, 32 or 64
 };
 
 struct PairArgs {

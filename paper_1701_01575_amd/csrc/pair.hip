@@ -217,8 +217,8 @@ hipError_t launch_pair32(const PairArgs &a, int mode, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Wavefront fill for large pairs: one segment of SEG lanes (16, 32 or 64)
-// per pair, 64 / SEG pairs per wave.  Segment lane l owns rows
+// Wavefront fill for large pairs: one segment of SEG lanes (4 to 64) per
+// pair, 64 / SEG pairs per wave.  Segment lane l owns rows
 // [16 s, 16 s + 16) of strip s = SEG * pass + l and at step t computes
 // column t - l + 1, so the row above (lane l - 1's last row one step
 // earlier) and the F leaving it arrive by a lane shuffle inside the
@@ -443,7 +443,9 @@ static void launch_pairwf_seg(const PairArgs &a, int mode, hipStream_t s) {
 
 hipError_t launch_pairwf(const PairArgs &a, int mode, int seg, hipStream_t s) {
     if (a.n_wf <= 0) return hipSuccess;
-    if (seg == 16) launch_pairwf_seg<16>(a, mode, s);
+    if (seg == 4) launch_pairwf_seg<4>(a, mode, s);
+    else if (seg == 8) launch_pairwf_seg<8>(a, mode, s);
+    else if (seg == 16) launch_pairwf_seg<16>(a, mode, s);
     else if (seg == 32) launch_pairwf_seg<32>(a, mode, s);
     else if (seg == 64) launch_pairwf_seg<64>(a, mode, s);
     else return hipErrorInvalidValue;

@@ -485,13 +485,17 @@ Tuning tuning_for(const std::string &key) {
 
 // Pairwise routing and region sizes (used by the pairwise plan below).
 struct PairRoute {
-    int64_t rows = 96;       // wavefront iff m >= rows ...
+    int64_t rows = 48;       // wavefront iff m >= rows ...
     int64_t cells = 32768;   // ... and m * n >= cells
 };
 
 // Lanes per wavefront pair: the narrowest segment that covers the query in
 // one pass of 16-row strips (64 lanes and several passes beyond 1024 rows).
-int wf_seg(int64_t m) { return m <= 16 * 16 ? 16 : (m <= 16 * 32 ? 32 : 64); }
+int wf_seg(int64_t m) {
+    for (int seg = 4; seg < kWave; seg *= 2)
+        if (m <= (int64_t)kTP * seg) return seg;
+    return kWave;
+}
 
 PairRoute pair_route(const Tuning &t) {
     PairRoute r;

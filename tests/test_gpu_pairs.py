@@ -129,15 +129,15 @@ def _edge_pairs(seed, alphabet, m_lens, n_lens):
 @pytest.mark.parametrize("mode,ends", CASES)
 @pytest.mark.parametrize("traceback", [True, False], ids=["tb", "score"])
 def test_pairs_wavefront(mode, ends, traceback, blosum, monkeypatch):
-    """Every pair through the wavefront kernel: 16-, 32- and 64-lane segments
-    (queries up to 256, 512 and beyond), segments of one wave with different
+    """Every pair through the wavefront kernel: 4- to 64-lane segments
+    (queries up to 64, 128, 256, 512 rows and beyond), segments of one wave with different
     target lengths, multi-pass pairs (over 1024 rows) and lengths at the
     16-row strip and segment edges."""
     all_wavefront(monkeypatch)
     Q, T = _pairs(17, 60, 0, 120, 20)
     Q2, T2 = _pairs(18, 16, 900, 2600, 20, related=True)
-    eq, et = _edge_pairs(61, 20, [1, 15, 16, 17, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 2049],
-                         [0, 1, 5, 300])
+    eq, et = _edge_pairs(61, 20, [1, 15, 16, 17, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513,
+                                  1023, 1024, 1025, 2049], [0, 1, 5, 300])
     Q = SeqSet.from_list([Q[k] for k in range(len(Q))] + [Q2[k] for k in range(len(Q2))] + eq)
     T = SeqSet.from_list([T[k] for k in range(len(T))] + [T2[k] for k in range(len(T2))] + et)
     log(f"pairs wavefront mode={mode} ends={ends} tb={traceback} n={len(Q)}")

@@ -63,7 +63,7 @@ def test_key_and_defaults():
                           "ta": B.dsa_tuning_get(a), "wsa": ws(a)}))
     """, {})
     assert out["ka"].startswith("pairs/") and out["ka"] != out["kb"]
-    assert out["ta"]["pair_rows"] == 96 and out["ta"]["pair_cells"] == 32768 and out["ta"]["ms"] == 0
+    assert out["ta"]["pair_rows"] == 48 and out["ta"]["pair_cells"] == 32768 and out["ta"]["ms"] == 0
 
 
 def test_cache_applies_to_its_class_only(tmp_path):
@@ -81,7 +81,7 @@ def test_cache_applies_to_its_class_only(tmp_path):
         print(json.dumps({"ta": B.dsa_tuning_get(a), "tb": B.dsa_tuning_get(b), "wsa": ws(a)}))
     """, {"DSA_AUTOTUNE_CACHE": str(cache)})
     assert out["ta"]["pair_rows"] == 1 << 30 and out["ta"]["pair_cells"] == 0 and out["ta"]["ms"] == 1.25
-    assert out["tb"]["pair_rows"] == 96  # other class: defaults
+    assert out["tb"]["pair_rows"] == 48  # other class: defaults
     # every pair now goes to the lane-per-pair kernel: a different workspace
     assert out["wsa"] != keys["wsa"]
 
@@ -98,4 +98,4 @@ def test_environment_overrides_cache(tmp_path):
 def test_missing_cache_file_is_ignored(tmp_path):
     out = _run("""print(json.dumps(B.dsa_tuning_get(make(300, 400, 5))))""",
                {"DSA_AUTOTUNE_CACHE": str(tmp_path / "absent.json")})
-    assert out["pair_rows"] == 96
+    assert out["pair_rows"] == 48
