@@ -220,16 +220,21 @@ def run_other_workloads(args, dsa, B, torch, gen, dev):
         rec.close()
         del rec
         n = min(args.plain_pairs, len(Q))
-        Qs, Ts = Q.subset(list(range(n))), T.subset(list(range(n)))
-        pcells = int((Qs.lengths * Ts.lengths).sum())
-        pdt = timed(prepared_call(Qs, S, o, e, mode, True, targets=Ts, traceback=True), 1)
-        bg, pg = cells / dt / 1e9, pcells / pdt / 1e9
+        bg = cells / dt / 1e9
+        pg = pdt = pcells = None
+        if n > 0:
+            Qs, Ts = Q.subset(list(range(n))), T.subset(list(range(n)))
+            pcells = int((Qs.lengths * Ts.lengths).sum())
+            pdt = timed(prepared_call(Qs, S, o, e, mode, True, targets=Ts, traceback=True), 1)
+            pg = pcells / pdt / 1e9
         res = {"pairs": len(Q), "cells": cells,
                "batched": {"gcups": round(bg, 2), "ms": round(dt * 1e3, 2), "device_ms": dev_ms,
                            "device_gcups": round(cells / (dev_ms["span"] * 1e-3) / 1e9, 2),
                            "graph_replay_ms": round(gdt * 1e3, 2)},
-               "plain": {"gcups": round(pg, 3), "ms": round(pdt * 1e3, 2), "pairs": n, "cells": pcells},
-               "batched_over_plain": round(bg / pg, 1), "traceback": "CIGAR", "autotuned": tuned}
+               "plain": None if pg is None else {"gcups": round(pg, 3), "ms": round(pdt * 1e3, 2), "pairs": n,
+                                                  "cells": pcells},
+               "batched_over_plain": None if pg is None else round(bg / pg, 1), "traceback": "CIGAR",
+               "autotuned": tuned}
         log(f"{name}: {res}")
         out[name] = res
 

@@ -144,12 +144,20 @@ struct WfPair {
     int32_t seg;      // lanes per pair: 4, 8, 16, 32 or 64
 };
 
+// One wave of the wavefront pair kernel: pairs [p0, p0 + np) of the launch's
+// wavefront pairs, each on a segment of `seg` lanes (np <= 64 / seg).
+struct WfWave {
+    int32_t p0, np, seg, pad;
+};
+
 struct PairArgs {
     const PairInfo *pairs;
     const PairGroup *groups;
     int32_t n_groups;
-    const WfPair *wf;             // wavefront pairs of this launch
+    const WfPair *wf;             // wavefront pairs of this launch (walk: one thread each)
     int32_t n_wf;
+    const WfWave *waves;          // wavefront waves of this launch (fill)
+    int32_t n_waves;
     const uint8_t *q_codes, *t_codes;
     const int8_t *subst;
     int32_t A, o, e, ends;
@@ -167,7 +175,7 @@ struct PairArgs {
 hipError_t launch_pack_targets(const PairArgs &a, int64_t n_words, hipStream_t s);
 hipError_t launch_pair32(const PairArgs &a, int mode, hipStream_t s);
 hipError_t launch_walk(const PairArgs &a, int mode, int64_t slot0, int64_t n_slots, hipStream_t s);
-hipError_t launch_pairwf(const PairArgs &a, int mode, int seg, hipStream_t s);
+hipError_t launch_pairwf(const PairArgs &a, int mode, hipStream_t s);
 hipError_t launch_walk_wf(const PairArgs &a, int mode, hipStream_t s);
 size_t pair32_lds_bytes(int A);
 

@@ -218,7 +218,8 @@ hipError_t launch_pair32(const PairArgs &a, int mode, hipStream_t s) {
 }
 
 // Wavefront fill for large pairs: one segment of SEG lanes (4 to 64) per
-// pair, 64 / SEG pairs per wave.  Segment lane l owns rows
+// pair, 64 / SEG pairs per wave, SEG chosen per wave (the waves of one launch
+// mix segment widths, longest first).  Segment lane l owns rows
 // [16 s, 16 s + 16) of strip s = SEG * pass + l and at step t computes
 // column t - l + 1, so the row above (lane l - 1's last row one step
 // earlier) and the F leaving it arrive by a lane shuffle inside the
@@ -256,7 +257,7 @@ __device__ __forceinline__ int row_of(const int (&H)[T], int r) {
     return v;
 }
 
-template <int MODE, bool TB, int SEG>
+template <int MODE, bool TB>
 __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
     constexpr int T = kTP;
     extern __shared__ int32_t sm[];
@@ -266,10 +267,14 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
         sm[k] = (r < A && c < A) ? (int)P.subst[r * A + c] : PAD32;
     }
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & (SEG - 1);
-    const int w = (blockIdx.x * kPairWaves + wave) * (kWave / SEG) + ((threadIdx.x & 63) / SEG);
-    if (w >= P.n_wf) return;  // no block barrier below; segments never read another segment's lanes
-    const WfPair W = P.wf[w];
+    const int vw = blockIdx.x * kPairWaves + (threadIdx.x >> 6);
+    if (vw >= P.n_waves) return;  // no block barrier below; segments never read another segment's lanes
+    const WfWave V = P.waves[vw];
+    const int SEG = V.seg;        // uniform across the wave
+    const int lane = threadIdx.x & (SEG - 1);
+    const int k_seg = (threadIdx.x & 63) / SEG;
+    if (k_seg >= V.np) return;
+    const WfPair W = P.wf[V.p0 + k_seg];
     const PairInfo I = P.pairs[W.slot];
     const int o = P.o, e = P.e, ends = P.ends;
     const int m = I.m, n = I.n;
@@ -426,29 +431,17 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
     }
 }
 
-template <int SEG>
-static void launch_pairwf_seg(const PairArgs &a, int mode, hipStream_t s) {
-    const int per_block = kPairWaves * (kWave / SEG);
-    const int nb = (a.n_wf + per_block - 1) / per_block;
+hipError_t launch_pairwf(const PairArgs &a, int mode, hipStream_t s) {
+    if (a.n_waves <= 0) return hipSuccess;
+    const int nb = (a.n_waves + kPairWaves - 1) / kPairWaves;
     const size_t lds = pair32_lds_bytes(a.A);
-#define LP(MODE, TBV) \
-    hipLaunchKernelGGL((k_pairwf<MODE, TBV, SEG>), dim3(nb), dim3(kPairWaves * kWave), lds, s, a)
+#define LP(MODE, TBV) hipLaunchKernelGGL((k_pairwf<MODE, TBV>), dim3(nb), dim3(kPairWaves * kWave), lds, s, a)
     if (a.traceback) {
         if (mode == LOCAL) LP(LOCAL, true); else if (mode == GLOBAL) LP(GLOBAL, true); else LP(SEMIGLOBAL, true);
     } else {
         if (mode == LOCAL) LP(LOCAL, false); else if (mode == GLOBAL) LP(GLOBAL, false); else LP(SEMIGLOBAL, false);
     }
 #undef LP
-}
-
-hipError_t launch_pairwf(const PairArgs &a, int mode, int seg, hipStream_t s) {
-    if (a.n_wf <= 0) return hipSuccess;
-    if (seg == 4) launch_pairwf_seg<4>(a, mode, s);
-    else if (seg == 8) launch_pairwf_seg<8>(a, mode, s);
-    else if (seg == 16) launch_pairwf_seg<16>(a, mode, s);
-    else if (seg == 32) launch_pairwf_seg<32>(a, mode, s);
-    else if (seg == 64) launch_pairwf_seg<64>(a, mode, s);
-    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

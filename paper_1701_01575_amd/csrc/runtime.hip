@@ -507,7 +507,7 @@ PairRoute pair_route(const Tuning &t) {
 // Sizes of a plan's device regions; a plan may be laid out with larger ones
 // (the hit traceback lays out its plan in a workspace sized for the worst case).
 struct PairCaps {
-    int64_t slots = 0, groups = 0, wf = 0, bnd = 0, tpk = 0, tb = 0, bndw = 0, tbw = 0;
+    int64_t slots = 0, groups = 0, wf = 0, bnd = 0, tpk = 0, tb = 0, bndw = 0, tbw = 0, waves = 0;
 };
 
 struct Plan {
@@ -584,12 +584,14 @@ struct PairPlan {
     bool plain = false;  // one pair per group, input order; groups run one by one and share buffers
     int64_t bnd_total = 0, tpk_total = 0;
     bool capacity_short = false;
-    std::vector<WfPair> wf;             // wavefront pairs; their slots follow the groups'
-    std::vector<int64_t> wf_chunk_first;
+    std::vector<WfPair> wf;             // wavefront pairs in wave order; their slots follow the groups'
+    std::vector<WfWave> waves;          // wavefront waves, longest first
+    std::vector<int64_t> wf_chunk_first;  // first wave of each chunk (+ end)
+    std::vector<int64_t> wf_chunk_pair;   // first pair of each chunk (+ end)
     int64_t wf_tb_max = 0, wf_tb_total = 0, wf_bnd_total = 0;  // uint32 / uint32 / uint2
     int wf_buffers = 1;                 // code buffers of wf_tb_max words each
     std::vector<std::pair<int, int64_t>> plain_seq;  // plain: (0 group | 1 wavefront, index) in input order
-    size_t off_slots = 0, off_groups = 0, off_wf = 0, off_subst = 0, table_bytes = 0;
+    size_t off_slots = 0, off_groups = 0, off_wf = 0, off_waves = 0, off_subst = 0, table_bytes = 0;
     size_t off_end = 0, off_bnd = 0, off_tpk = 0, off_tb = 0, off_bndw = 0, off_tbw = 0, total = 0;
 };
 
@@ -598,6 +600,7 @@ PairCaps caps_of(const PairPlan &P) {
     c.slots = (int64_t)P.slots.size();
     c.groups = (int64_t)P.groups.size();
     c.wf = (int64_t)P.wf.size();
+    c.waves = (int64_t)P.waves.size();
     c.bnd = P.bnd_total;
     c.tpk = P.tpk_total;
     c.tb = P.tb_max;
@@ -612,6 +615,7 @@ void layout_pair_plan(PairPlan &P, const PairCaps &c, int A) {
     P.off_slots = o; o = align_up(o + cnt(c.slots) * sizeof(PairInfo), 256);
     P.off_groups = o; o = align_up(o + cnt(c.groups) * sizeof(PairGroup), 256);
     P.off_wf = o; o = align_up(o + cnt(c.wf) * sizeof(WfPair), 256);
+    P.off_waves = o; o = align_up(o + cnt(c.waves) * sizeof(WfWave), 256);
     P.off_subst = o; o = align_up(o + (size_t)A * A, 256);
     P.table_bytes = o;
     P.off_end = o; o = align_up(o + cnt(c.slots) * 8, 256);
@@ -756,56 +760,99 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     }
     P.chunk_first.push_back((int64_t)P.groups.size());
 
-    // wavefront pairs: by segment width, then largest first (plain: input
-    // order); their slots follow the groups'
+    // wavefront pairs: waves of one segment width (64 / seg pairs each, the
+    // pairs of a width largest first), then the waves longest first across
+    // widths; codes chunked at wave boundaries.  Plain: one pair per wave, in
+    // input order.  Pairs are stored in wave order; their slots follow the
+    // groups'.
+    auto seg_of = [&](int64_t k) { return wf_seg(sp[k].m); };
     if (!plain)
         std::stable_sort(worder.begin(), worder.end(), [&](int64_t x, int64_t y) {
-            const int sx = wf_seg(sp[x].m), sy = wf_seg(sp[y].m);
-            if (sx != sy) return sx > sy;
+            if (seg_of(x) != seg_of(y)) return seg_of(x) > seg_of(y);
             return sp[x].m * sp[x].n > sp[y].m * sp[y].n;
         });
-    int64_t wchunk = 0;
+    struct WaveSpec {
+        int64_t first = 0, count = 0;  // into worder
+        int seg = 0;
+        int64_t cost = 0;              // steps: passes x (longest target + seg - 1)
+    };
+    std::vector<WaveSpec> wv;
     for (size_t k = 0; k < worder.size(); k++) {
-        const PairSpec &x = sp[worder[k]];
-        const int seg = wf_seg(x.m);
-        const int64_t strips_w = (x.m + kTP - 1) / kTP, passes = (strips_w + seg - 1) / seg;
-        const int64_t nblk = (x.n + seg - 1 + kWfBlock - 1) / kWfBlock;
-        const int64_t words = traceback ? passes * nblk * kWfBlock * seg * 2 : 0;
-        WfPair W;
-        memset(&W, 0, sizeof(W));
-        W.slot = (int32_t)P.slots.size();
-        W.seg = seg;
-        if (plain) {
-            W.tb = 0;
-            W.bnd = 0;
-            P.wf_bnd_total = std::max(P.wf_bnd_total, x.n);
-            P.wf_tb_max = std::max(P.wf_tb_max, words);
-            if (k == 0) P.wf_chunk_first.push_back(0);
-        } else {
-            if (k == 0 || (wchunk > 0 && (wchunk + words) * 4 > tb_cap) || seg != P.wf[k - 1].seg) {
-                P.wf_chunk_first.push_back((int64_t)k);
-                wchunk = 0;
-            }
-            W.tb = wchunk / 2;
-            wchunk += words;
-            P.wf_tb_max = std::max(P.wf_tb_max, wchunk);
-            W.bnd = P.wf_bnd_total;
-            P.wf_bnd_total += std::max<int64_t>(x.n, 1);
+        const int seg = seg_of(worder[k]);
+        if (plain || wv.empty() || wv.back().seg != seg || wv.back().count == kWave / seg) {
+            WaveSpec x;
+            x.first = (int64_t)k;
+            x.seg = seg;
+            wv.push_back(x);
         }
-        P.wf_tb_total += words;
-        P.wf.push_back(W);
-        PairInfo I;
-        memset(&I, 0, sizeof(I));
-        I.q_off = x.q_off;
-        I.t_off = x.t_off;
-        I.m = (int32_t)x.m;
-        I.n = (int32_t)x.n;
-        I.res = x.res;
-        I.cig_off = roff[x.res];
-        I.cig_cap = (int32_t)rcap[x.res];
-        P.slots.push_back(I);
+        WaveSpec &w = wv.back();
+        w.count++;
+        const PairSpec &x = sp[worder[k]];
+        const int64_t passes = ((x.m + kTP - 1) / kTP + seg - 1) / seg;
+        w.cost = std::max(w.cost, passes * (x.n + seg - 1));
     }
-    P.wf_chunk_first.push_back((int64_t)P.wf.size());
+    if (!plain)
+        std::stable_sort(wv.begin(), wv.end(), [](const WaveSpec &x, const WaveSpec &y) { return x.cost > y.cost; });
+    int64_t wchunk = 0;
+    for (size_t v = 0; v < wv.size(); v++) {
+        int64_t wave_words = 0;
+        for (int64_t q = 0; q < wv[v].count; q++) {
+            const PairSpec &x = sp[worder[wv[v].first + q]];
+            const int seg = wv[v].seg;
+            const int64_t passes = ((x.m + kTP - 1) / kTP + seg - 1) / seg;
+            const int64_t nblk = (x.n + seg - 1 + kWfBlock - 1) / kWfBlock;
+            wave_words += traceback ? passes * nblk * kWfBlock * seg * 2 : 0;
+        }
+        if (plain) {
+            if (v == 0) { P.wf_chunk_first.push_back(0); P.wf_chunk_pair.push_back(0); }
+            wchunk = 0;
+        } else if (v == 0 || (wchunk > 0 && (wchunk + wave_words) * 4 > tb_cap)) {
+            P.wf_chunk_first.push_back((int64_t)v);
+            P.wf_chunk_pair.push_back((int64_t)P.wf.size());
+            wchunk = 0;
+        }
+        WfWave V;
+        V.p0 = (int32_t)P.wf.size();
+        V.np = (int32_t)wv[v].count;
+        V.seg = wv[v].seg;
+        V.pad = 0;
+        P.waves.push_back(V);
+        for (int64_t q = 0; q < wv[v].count; q++) {
+            const PairSpec &x = sp[worder[wv[v].first + q]];
+            const int seg = wv[v].seg;
+            const int64_t passes = ((x.m + kTP - 1) / kTP + seg - 1) / seg;
+            const int64_t nblk = (x.n + seg - 1 + kWfBlock - 1) / kWfBlock;
+            const int64_t words = traceback ? passes * nblk * kWfBlock * seg * 2 : 0;
+            WfPair W;
+            memset(&W, 0, sizeof(W));
+            W.slot = (int32_t)P.slots.size();
+            W.seg = seg;
+            W.tb = wchunk / 2;  // plain: every pair starts at 0 (one at a time)
+            wchunk += words;
+            if (plain) {
+                W.bnd = 0;
+                P.wf_bnd_total = std::max(P.wf_bnd_total, x.n);
+            } else {
+                W.bnd = P.wf_bnd_total;
+                P.wf_bnd_total += std::max<int64_t>(x.n, 1);
+            }
+            P.wf_tb_max = std::max(P.wf_tb_max, wchunk);
+            P.wf_tb_total += words;
+            P.wf.push_back(W);
+            PairInfo I;
+            memset(&I, 0, sizeof(I));
+            I.q_off = x.q_off;
+            I.t_off = x.t_off;
+            I.m = (int32_t)x.m;
+            I.n = (int32_t)x.n;
+            I.res = x.res;
+            I.cig_off = roff[x.res];
+            I.cig_cap = (int32_t)rcap[x.res];
+            P.slots.push_back(I);
+        }
+    }
+    P.wf_chunk_first.push_back((int64_t)P.waves.size());
+    P.wf_chunk_pair.push_back((int64_t)P.wf.size());
     // with several chunks, fills and walks alternate between two code buffers
     // so that a chunk's walk overlaps the next chunk's fill
     if (traceback && !plain && P.wf_chunk_first.size() > 2) P.wf_buffers = 2;
@@ -1057,6 +1104,7 @@ int make_search_plan(const dsa_args *a, Plan &P) {
         PairCaps c = caps_of(B1);
         c.slots = (int64_t)B1.slots.size() + (int64_t)B2.wf.size();
         c.wf = (int64_t)B2.wf.size();
+        c.waves = (int64_t)B2.wf.size();  // at least one pair per wave
         c.tb = std::max(B1.tb_max, std::min(tb_budget_bytes() / 4, B1.tb_total));
         c.bndw = B2.wf_bnd_total;
         c.tbw = 2 * std::max(B2.wf_tb_max, std::min(tb_budget_bytes() / 4, B2.wf_tb_total));
@@ -1136,6 +1184,7 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
             memcpy(h + P.off_slots, P.slots.data(), P.slots.size() * sizeof(PairInfo));
             memcpy(h + P.off_groups, P.groups.data(), P.groups.size() * sizeof(PairGroup));
             memcpy(h + P.off_wf, P.wf.data(), P.wf.size() * sizeof(WfPair));
+        memcpy(h + P.off_waves, P.waves.data(), P.waves.size() * sizeof(WfWave));
             memcpy(h + P.off_subst, a->subst, (size_t)A * A);
         });
         if (rc) return rc;
@@ -1168,15 +1217,42 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
     K.cigar = out->cigar_ops;
     const PairGroup *dg = (const PairGroup *)(ws + P.off_groups);
     const WfPair *dw = (const WfPair *)(ws + P.off_wf);
+    const WfWave *dv = (const WfWave *)(ws + P.off_waves);
     PairArgs KW = K;  // the wavefront kind: its own boundary and code regions
     KW.tb = (uint32_t *)(ws + P.off_tbw);
     KW.bnd = (uint2 *)(ws + P.off_bndw);
-    auto wf_launch = [&](int64_t w0, int64_t w1, hipStream_t s) -> int {
+    // chunk c: waves [wf_chunk_first[c], +1) fill, pairs [wf_chunk_pair[c], +1) walk
+    auto wf_args = [&](size_t c, int buffer) {
         PairArgs k = KW;
-        k.wf = dw + w0;
-        k.n_wf = (int32_t)(w1 - w0);
-        HIPCHK(launch_pairwf(k, P.mode, P.wf[w0].seg, s));
-        if (P.traceback) HIPCHK(launch_walk_wf(k, P.mode, s));
+        k.waves = dv + P.wf_chunk_first[c];
+        k.n_waves = (int32_t)(P.wf_chunk_first[c + 1] - P.wf_chunk_first[c]);
+        k.wf = dw;  // waves index pairs absolutely
+        k.tb = KW.tb + buffer * P.wf_tb_max;
+        return k;
+    };
+    auto walk_args = [&](PairArgs k, size_t c) {
+        k.wf = dw + P.wf_chunk_pair[c];
+        k.n_wf = (int32_t)(P.wf_chunk_pair[c + 1] - P.wf_chunk_pair[c]);
+        return k;
+    };
+    // plain form: wave v holds pair v alone
+    auto plain_wf = [&](int64_t v, hipStream_t s) -> int {
+        PairArgs k = KW;
+        k.waves = dv + v;
+        k.n_waves = 1;
+        k.wf = dw;
+        HIPCHK(launch_pairwf(k, P.mode, s));
+        if (P.traceback) {
+            k.wf = dw + v;
+            k.n_wf = 1;
+            HIPCHK(launch_walk_wf(k, P.mode, s));
+        }
+        return DSA_OK;
+    };
+    auto wf_launch = [&](size_t c, hipStream_t s) -> int {
+        const PairArgs k = wf_args(c, 0);
+        HIPCHK(launch_pairwf(k, P.mode, s));
+        if (P.traceback) HIPCHK(launch_walk_wf(walk_args(k, c), P.mode, s));
         return DSA_OK;
     };
     // chunks of wavefront pairs with two code buffers: fills on `sf`, walks on
@@ -1191,16 +1267,12 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
                 HIPCHK(hipEventCreateWithFlags(&ax->ev[k], hipEventDisableTiming));
         }
         for (size_t c = 0; c < nch; c++) {
-            const int64_t w0 = P.wf_chunk_first[c], w1 = P.wf_chunk_first[c + 1];
-            PairArgs k = KW;
-            k.wf = dw + w0;
-            k.n_wf = (int32_t)(w1 - w0);
-            k.tb = KW.tb + (c & 1) * P.wf_tb_max;
+            const PairArgs k = wf_args(c, (int)(c & 1));
             if (c >= 2) HIPCHK(hipStreamWaitEvent(sf, ax->ev[2 * (c - 2) + 1], 0));
-            HIPCHK(launch_pairwf(k, P.mode, P.wf[w0].seg, sf));
+            HIPCHK(launch_pairwf(k, P.mode, sf));
             HIPCHK(hipEventRecord(ax->ev[2 * c], sf));
             HIPCHK(hipStreamWaitEvent(sw, ax->ev[2 * c], 0));
-            HIPCHK(launch_walk_wf(k, P.mode, sw));
+            HIPCHK(launch_walk_wf(walk_args(k, c), P.mode, sw));
             HIPCHK(hipEventRecord(ax->ev[2 * c + 1], sw));
         }
         HIPCHK(hipEventRecord(ax->ev[2 * nch], sw));
@@ -1224,7 +1296,7 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
     if ((rc = timing_begin(st, TK_SPAN, &span_slot))) return rc;
     if (P.plain) {  // one pair at a time, in input order: (pack,) fill, walk
         for (const auto &x : P.plain_seq) {
-            if ((rc = x.first ? wf_launch(x.second, x.second + 1, st) : lane_launch(x.second, x.second + 1, st)))
+            if ((rc = x.first ? plain_wf(x.second, st) : lane_launch(x.second, x.second + 1, st)))
                 return rc;
         }
         if ((rc = timing_end(st, span_slot))) return rc;
@@ -1264,7 +1336,7 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
             if ((rc = wf_pipelined(aux, ws_st))) return rc;
         } else {
             for (size_t c = 0; c + 1 < P.wf_chunk_first.size(); c++)
-                if ((rc = wf_launch(P.wf_chunk_first[c], P.wf_chunk_first[c + 1], ws_st))) return rc;
+                if ((rc = wf_launch(c, ws_st))) return rc;
         }
         if ((rc = timing_end(ws_st, slot))) return rc;
     }
@@ -1637,7 +1709,8 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
                         std::min(P.pair_caps.tb, P.pair_caps.tbw / 2) * 4, PP, false, pair_route(Tuning()));
         const PairCaps need = caps_of(PP);
         const PairCaps &cap = P.pair_caps;
-        if (need.slots > cap.slots || need.groups > cap.groups || need.wf > cap.wf || need.bnd > cap.bnd ||
+        if (need.slots > cap.slots || need.groups > cap.groups || need.wf > cap.wf || need.waves > cap.waves ||
+            need.bnd > cap.bnd ||
             need.tpk > cap.tpk || need.tb > cap.tb || need.bndw > cap.bndw || need.tbw > cap.tbw)
             return fail(DSA_E_WORKSPACE, "hit traceback plan exceeds its workspace bound");
         layout_pair_plan(PP, cap, A);

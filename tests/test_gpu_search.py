@@ -148,6 +148,22 @@ def test_search_wavefront_long_targets(mode, ends, budget, blosum, monkeypatch):
         compare_search(got, exp, len(Q), len(T), label=f"wavefront {mode}/{ends}/{plain}")
 
 
+@pytest.mark.parametrize("strip,waves", [("32", "8"), ("16", "2"), ("32", "1")])
+def test_search_wavefront_launch_shapes(strip, waves, blosum, monkeypatch):
+    """Wavefront units inside the persistent kernel at other strip heights and
+    block sizes (a unit takes as many long pairs as the block has waves)."""
+    monkeypatch.setenv("DSA_STRIP", strip)
+    monkeypatch.setenv("DSA_WAVES", waves)
+    monkeypatch.setenv("DSA_INTRA_BUDGET", "20000")
+    T = _targets(9, 260, 1500, extra=[1, 2, 1501, 1777, 2001])
+    Q = _queries(10, INTRA_QLENS)
+    for mode, ends in (("local", None), ("semiglobal", None)):
+        log(f"wavefront shapes strip={strip} waves={waves} mode={mode}")
+        got, _ = gpu_search(Q, T, blosum, 11, 1, mode, ends)
+        exp = oracle.search(Q, T, blosum, 11, 1, mode=mode, ends=ends)
+        compare_search(got, exp, len(Q), len(T), label=f"shapes {strip}/{waves}/{mode}")
+
+
 def test_search_wavefront_overflow_rerun(blosum, monkeypatch):
     monkeypatch.setenv("DSA_INTRA_BUDGET", "1")
     S = (blosum.astype(np.int32) * 5).clip(-128, 127).astype(np.int8)
