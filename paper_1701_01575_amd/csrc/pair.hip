@@ -105,9 +105,35 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pair32(PairArgs P) {
         const int rlast = m - 1 - i0;
         int res = 0, Ls = 0, Lj = 0;
         if (MODE != LOCAL && last) { res = left_value(MODE, ends, o, e, m); Ls = res; }
+        // E-extend bits of the next column, known one column early
+        uint32_t eN[2] = {0u, 0u};
 
-        for (int c4 = 0; c4 < (ncols >> 2); c4++) {
-            const uint32_t w4 = tw[(int64_t)c4 * kWave];
+        // software pipeline: the next 4 columns' target codes and boundary
+        // words are in flight while the current 4 compute
+        const int nblk4 = ncols >> 2;
+        uint32_t w4n = 0;
+        uint2 bn[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++) bn[c] = make_uint2(0u, 0u);
+        if (nblk4 > 0) {
+            w4n = tw[0];
+            if (!first) {
+#pragma unroll
+                for (int c = 0; c < 4; c++) bn[c] = bnd[(int64_t)c * kWave];
+            }
+        }
+        for (int c4 = 0; c4 < nblk4; c4++) {
+            const uint32_t w4 = w4n;
+            uint2 bc[4];
+#pragma unroll
+            for (int c = 0; c < 4; c++) bc[c] = bn[c];
+            if (c4 + 1 < nblk4) {
+                w4n = tw[(int64_t)(c4 + 1) * kWave];
+                if (!first) {
+#pragma unroll
+                    for (int c = 0; c < 4; c++) bn[c] = bnd[(int64_t)(4 * c4 + 4 + c) * kWave];
+                }
+            }
 #pragma unroll
             for (int c = 0; c < 4; c++) {
                 const int j = 4 * c4 + c + 1;
@@ -117,39 +143,42 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pair32(PairArgs P) {
                     Hup = top_value(MODE, ends, o, e, j);
                     F = Hup - o;
                 } else {
-                    const uint2 bw = bnd[(int64_t)(j - 1) * kWave];
-                    Hup = (int)bw.x;
-                    F = (int)bw.y;
+                    Hup = (int)bc[c].x;
+                    F = (int)bc[c].y;
                 }
                 int Hd = Hd_top;
                 Hd_top = Hup;
                 int ho_up = Hup - o;
                 int cm = 0;
-                uint32_t acc = 0;
+                uint32_t acc[2] = {eN[0], eN[1]};
+                eN[0] = 0u;
+                eN[1] = 0u;
 #pragma unroll
                 for (int r = 0; r < T; r++) {
                     const int t = Hd + sm[rowb[r] + b];
-                    const int Hold = H[r];
-                    Hd = Hold;
+                    Hd = H[r];
                     const int Ein = E[r], Fin = F;
                     int h = max(max(t, Ein), Fin);
                     if (MODE == LOCAL) { h = max(h, 0); cm = max(cm, h); }
                     const int ho = h - o;
-                    E[r] = max(Ein - e, ho);
+                    const int Ee = Ein - e;
+                    E[r] = max(Ee, ho);
                     F = max(Fin - e, ho);
                     H[r] = h;
                     if (TB) {
-                        uint32_t src = (h == t) ? 1u : ((h == Ein) ? 2u : 3u);
-                        if (MODE == LOCAL && h == 0) src = 0u;
-                        const uint32_t eext = (Ein != Hold - o) ? 4u : 0u;
-                        const uint32_t fext = (Fin != ho_up) ? 8u : 0u;
-                        acc |= (src | eext | fext) << (4 * (r & 7));
-                        if ((r & 7) == 7) {
-                            tb[(((int64_t)s * ncols + (j - 1)) * 2 + (r >> 3)) * kWave] = acc;
-                            acc = 0;
-                        }
+                        const int sh = 4 * (r & 7);
+                        uint32_t src = (h == t) ? (1u << sh) : ((h == Ein) ? (2u << sh) : (3u << sh));
+                        if (MODE == LOCAL && h == 0) src = 0u;  // extend bits of a zero cell are never read
+                        const uint32_t fext = (Fin != ho_up) ? (8u << sh) : 0u;
+                        acc[r >> 3] |= src | fext;
+                        // E of (i, j + 1) extends iff E - e beats H - o here (open wins ties)
+                        eN[r >> 3] |= (Ee > ho) ? (4u << sh) : 0u;
                     }
                     ho_up = ho;
+                }
+                if (TB) {
+                    tb[(((int64_t)s * ncols + (j - 1)) * 2) * kWave] = acc[0];
+                    tb[(((int64_t)s * ncols + (j - 1)) * 2 + 1) * kWave] = acc[1];
                 }
                 if (MODE == LOCAL) {
                     if (cm > B) {
@@ -158,12 +187,12 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pair32(PairArgs P) {
                         for (int r = T - 1; r >= 0; r--) rr = (H[r] == cm) ? r : rr;
                         B = cm; Bj = j; Bi = i0 + rr + 1;
                     }
-                } else if (last && j <= n) {
+                } else if (last && (j == n || ((ends & TE) && j < n))) {
                     int vl = H[0];
 #pragma unroll
                     for (int k = 1; k < T; k++) vl = (k == rlast) ? H[k] : vl;
                     if (!(ends & TE)) {
-                        if (j == n) res = vl;
+                        res = vl;
                     } else if (vl > Ls) {
                         Ls = vl; Lj = j;
                     }
@@ -525,9 +554,31 @@ __device__ void walk_pair(const PairArgs &P, const PairInfo &I, int i, int j, Co
     if (W.truncated && P.out_status) P.out_status[I.res] |= 2;  // DSA_ST_TRUNCATED
 }
 
-// Walk of the lane-per-pair kernel's pairs: one thread per pair slot.
+// Residue k (0..15) of a 16-residue window held as four uint32.
+__device__ __forceinline__ int byte_of(const uint32_t (&w)[4], int k) {
+    const uint32_t x = (k < 8) ? ((k < 4) ? w[0] : w[1]) : ((k < 12) ? w[2] : w[3]);
+    return (int)((x >> (8 * (k & 3))) & 0xffu);
+}
+
+// Residues [base, base + 16) of a sequence of `len` (zero past its end),
+// as 16 independent byte loads.
+__device__ __forceinline__ void load_window(const uint8_t *seq, int len, int base, uint32_t (&w)[4]) {
+    uint32_t v[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int k = 0; k < 16; k++)
+        if (base + k < len) v[k >> 2] |= (uint32_t)seq[base + k] << (8 * (k & 3));
+#pragma unroll
+    for (int k = 0; k < 4; k++) w[k] = v[k];
+}
+
+// Walk of the lane-per-pair kernel's pairs: one thread per pair slot.  Like
+// the wavefront walk, it fetches every 16 steps the codes of the 16x16 cells
+// it can reach next (two strips x 16 columns x 2 words, 64 independent
+// loads) into LDS and the residues before its position into registers.
+constexpr int kLaneWalkThreads = 64;
 template <int MODE>
-__global__ void k_walk(PairArgs P, int64_t slot0, int64_t n_slots) {
+__global__ void __launch_bounds__(kLaneWalkThreads) k_walk(PairArgs P, int64_t slot0, int64_t n_slots) {
+    __shared__ uint32_t cache[kLaneWalkThreads * 64];
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_slots) return;
     const int64_t slot = slot0 + k;
@@ -538,14 +589,41 @@ __global__ void k_walk(PairArgs P, int64_t slot0, int64_t n_slots) {
     const uint32_t *tb = P.tb + G.tb + lane;
     const int ncols = G.ncols;
     const uint8_t *qc = P.q_codes + I.q_off, *tc = P.t_codes + I.t_off;
+    uint32_t *mine = cache + threadIdx.x * 64;
+    int s_lo = 0, jlo = 0, qbase = 0, tbase = 0;
+    uint32_t qw[4] = {0u, 0u, 0u, 0u}, tw[4] = {0u, 0u, 0u, 0u};
+    auto refill = [&](int i, int j) {
+        s_lo = (i - 1) / kTP - 1;
+        jlo = max(j - 16, 0);
+        uint32_t v[64];
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            const int s = s_lo + c;
+#pragma unroll
+            for (int x = 0; x < 16; x++) {
+                const int col = jlo + x;
+                const bool ok = s >= 0 && col < ncols;
+#pragma unroll
+                for (int h = 0; h < 2; h++)
+                    v[c * 32 + x * 2 + h] = ok ? tb[(((int64_t)s * ncols + col) * 2 + h) * kWave] : 0u;
+            }
+        }
+        qbase = max(i - 16, 0);
+        tbase = max(j - 16, 0);
+        load_window(qc, I.m, qbase, qw);
+        load_window(tc, I.n, tbase, tw);
+#pragma unroll
+        for (int x = 0; x < 64; x++) mine[x] = v[x];
+    };
     walk_pair<MODE>(
         P, I, P.end_i[slot], P.end_j[slot],
         [&](int ii, int jj) -> uint32_t {
             const int s = (ii - 1) / kTP, r = (ii - 1) % kTP;
-            const uint32_t w = tb[(((int64_t)s * ncols + (jj - 1)) * 2 + (r >> 3)) * kWave];
+            const uint32_t w = mine[(s - s_lo) * 32 + (jj - 1 - jlo) * 2 + (r >> 3)];
             return (w >> (4 * (r & 7))) & 15u;
         },
-        [&](int ii, int jj) { return qc[ii - 1] == tc[jj - 1]; }, [](int, int) {});
+        [&](int ii, int jj) { return byte_of(qw, ii - 1 - qbase) == byte_of(tw, jj - 1 - tbase); },
+        refill);
 }
 
 // Walk of the wavefront kernel's pairs: one thread per pair.  The walk is a
@@ -555,20 +633,6 @@ __global__ void k_walk(PairArgs P, int64_t slot0, int64_t n_slots) {
 // (j - 16, j] into LDS, and the 16 query and target residues before i and j
 // into registers.  The 16 steps then read only LDS and registers.
 constexpr int kWalkThreads = 64;
-
-__device__ __forceinline__ int byte_of(const uint32_t (&w)[4], int k) {
-    const uint32_t x = (k < 8) ? ((k < 4) ? w[0] : w[1]) : ((k < 12) ? w[2] : w[3]);
-    return (int)((x >> (8 * (k & 3))) & 0xffu);
-}
-
-__device__ __forceinline__ void load_window(const uint8_t *seq, int len, int base, uint32_t (&w)[4]) {
-    uint32_t v[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-    for (int k = 0; k < 16; k++)
-        if (base + k < len) v[k >> 2] |= (uint32_t)seq[base + k] << (8 * (k & 3));
-#pragma unroll
-    for (int k = 0; k < 4; k++) w[k] = v[k];
-}
 
 template <int MODE>
 __global__ void __launch_bounds__(kWalkThreads) k_walk_wf(PairArgs P) {
@@ -644,7 +708,7 @@ hipError_t launch_walk_wf(const PairArgs &a, int mode, hipStream_t s) {
 
 hipError_t launch_walk(const PairArgs &a, int mode, int64_t slot0, int64_t n_slots, hipStream_t s) {
     if (n_slots <= 0) return hipSuccess;
-    const int bs = 64;
+    const int bs = kLaneWalkThreads;
     const unsigned nb = (unsigned)((n_slots + bs - 1) / bs);
     if (mode == LOCAL) hipLaunchKernelGGL(k_walk<LOCAL>, dim3(nb), dim3(bs), 0, s, a, slot0, n_slots);
     else if (mode == GLOBAL) hipLaunchKernelGGL(k_walk<GLOBAL>, dim3(nb), dim3(bs), 0, s, a, slot0, n_slots);
