@@ -84,6 +84,23 @@ def test_db_create_validates_before_allocating(B):
     assert st == B.DSA_E_INVAL
 
 
+def test_length_limit(B):
+    """Sequences up to 65,532 residues are supported; longer ones are
+    rejected with DSA_E_NOTSUP before any device work."""
+    codes = np.zeros(65533, np.uint8)
+    offs = np.array([0, 65533], np.int64)
+    h = ctypes.c_void_p()
+    st = B.lib().dsa_db_create(codes.ctypes.data, offs.ctypes.data, 1, 4, None, ctypes.byref(h))
+    assert st == B.DSA_E_NOTSUP and "65532" in B.dsa_last_error()
+    n = ctypes.c_size_t()
+    qo = np.array([0, 65533], np.int64)
+    to = np.array([0, 10], np.int64)
+    a = _args(B, q_offsets=qo.ctypes.data, t_offsets=to.ctypes.data)
+    assert B.lib().dsa_workspace_size(ctypes.byref(a), ctypes.byref(n)) == B.DSA_E_NOTSUP
+    qo[1] = 65532
+    assert B.lib().dsa_workspace_size(ctypes.byref(a), ctypes.byref(n)) == B.DSA_OK
+
+
 def test_no_cpu_fallback():
     import torch
     import paper_1701_01575_amd as dsa

@@ -161,6 +161,22 @@ def test_pairs_wavefront_chunked_plain(mode, blosum, monkeypatch):
     compare_pairs(got, exp, True, f"wavefront plain {mode}")
 
 
+@pytest.mark.parametrize("mode", ["local", "global", "semiglobal"])
+def test_pairs_longest(mode, blosum):
+    """Pairs at the 65,532-residue maximum on either side: a 4,096-strip
+    query (64 wavefront passes) and a 65,532-column target."""
+    rng = np.random.default_rng([170101575, 62])
+    a = gen.background_residues(rng, 65532)
+    b = gen.background_residues(rng, 100)
+    c = a[1000:1100].copy()
+    Q = SeqSet.from_list([b, a, c])
+    T = SeqSet.from_list([a, b, a])
+    log(f"longest pairs {mode}")
+    got = gpu_pairs(Q, T, blosum, 10, 1, mode)
+    exp = oracle.align_pairs(Q, T, blosum, 10, 1, mode=mode, traceback=True)
+    compare_pairs(got, exp, True, f"longest {mode}")
+
+
 def test_pairs_chunked_codes(blosum, monkeypatch):
     monkeypatch.setenv("DSA_TB_BUDGET", str(1 << 20))  # many chunks of direction codes
     Q, T = _pairs(13, 400, 20, 300, 20, related=True)

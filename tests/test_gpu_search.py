@@ -164,6 +164,22 @@ def test_search_wavefront_launch_shapes(strip, waves, blosum, monkeypatch):
         compare_search(got, exp, len(Q), len(T), label=f"shapes {strip}/{waves}/{mode}")
 
 
+@pytest.mark.parametrize("mode,ends", CASES[:3])
+def test_search_longest_targets(mode, ends, blosum):
+    """Targets at 35,000 residues (where the length law is clipped) and at the
+    65,532-residue maximum, next to ordinary ones; a short and a two-pass
+    query.  Global scores against the longest target leave the int16 range,
+    so that query also runs through the int32 path."""
+    rng = np.random.default_rng([170101575, 56])
+    lens = [35000, 65532, 20, 300, 1, 5000]
+    T = SeqSet.from_list([gen.background_residues(rng, L) for L in lens])
+    Q = _queries(11, [50, 1100])
+    log(f"longest targets mode={mode}")
+    got, _ = gpu_search(Q, T, blosum, 11, 1, mode, ends)
+    exp = oracle.search(Q, T, blosum, 11, 1, mode=mode, ends=ends)
+    compare_search(got, exp, len(Q), len(T), label=f"longest {mode}")
+
+
 def test_search_wavefront_overflow_rerun(blosum, monkeypatch):
     monkeypatch.setenv("DSA_INTRA_BUDGET", "1")
     S = (blosum.astype(np.int32) * 5).clip(-128, 127).astype(np.int8)
