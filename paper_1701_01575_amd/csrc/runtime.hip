@@ -632,8 +632,14 @@ struct PairSpec {
     int32_t res;
 };
 
+// Bytes of direction codes per chunk: a sixteenth of the device's memory,
+// at most 16 GiB (the wavefront kind keeps two chunks when it has several).
 int64_t tb_budget_bytes() {
-    int64_t b = (int64_t)8 << 30;  // bytes of direction codes per chunk
+    int64_t b = (int64_t)16 << 30;
+    int dev = 0;
+    size_t total = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceTotalMem(&total, dev) == hipSuccess && total > 0)
+        b = std::min<int64_t>(b, std::max<int64_t>((int64_t)(total / 16), (int64_t)1 << 28));
     if (const char *v = getenv("DSA_TB_BUDGET")) b = std::max<int64_t>(atoll(v), 1 << 20);
     return b;
 }

@@ -165,6 +165,23 @@ def test_search_wavefront_launch_shapes(strip, waves, blosum, monkeypatch):
 
 
 @pytest.mark.parametrize("mode,ends", CASES[:3])
+def test_search_small_databases_full_alphabet(mode, ends, blosum):
+    """A one-target database, a database of length-1 targets only, and
+    residues drawn from all 24 BLOSUM62 letters (B, Z, X and * included)."""
+    rng = np.random.default_rng([170101575, 57])
+    Q = SeqSet.from_list([rng.integers(0, 24, size=L).astype(np.uint8) for L in (1, 7, 40, 300)])
+    dbs = [SeqSet.from_list([rng.integers(0, 24, size=120).astype(np.uint8)]),
+           SeqSet.from_list([rng.integers(0, 24, size=1).astype(np.uint8) for _ in range(200)]),
+           SeqSet.from_list([rng.integers(0, 24, size=int(L)).astype(np.uint8)
+                             for L in rng.integers(0, 400, size=300)])]
+    for k, T in enumerate(dbs):
+        log(f"small db {k} mode={mode}")
+        got, _ = gpu_search(Q, T, blosum, 11, 1, mode, ends)
+        exp = oracle.search(Q, T, blosum, 11, 1, mode=mode, ends=ends)
+        compare_search(got, exp, len(Q), len(T), label=f"small db {k} {mode}")
+
+
+@pytest.mark.parametrize("mode,ends", CASES[:3])
 def test_search_longest_targets(mode, ends, blosum):
     """Targets at 35,000 residues (where the length law is clipped) and at the
     65,532-residue maximum, next to ordinary ones; a short and a two-pass
