@@ -31,6 +31,15 @@
  *
  * Plain O(m*n) dynamic programming in int64 with full matrices when a
  * traceback is asked for, two rolling rows otherwise; no SIMD, no blocking.
+ *
+ * Pins (tests that do not run this code's formulas again):
+ *   scores and end cells: brute force over every alignment of short
+ *   sequences, closed forms, textbook reductions (linear gaps, LCS,
+ *   Levenshtein, Kadane) and invariants; paths: membership of every CIGAR
+ *   in the brute-forced optimal set, rescoring, and hand-worked cases.
+ *   Parity unpinned by the paper: which optimal path is reported among
+ *   equal-score paths.  The tie rule above fixes it; an independently written
+ *   Python traceback (pyref.py) and the hand-worked cases agree with it.
  */
 #include <pthread.h>
 #include <stdint.h>
