@@ -57,54 +57,57 @@ using namespace dsa;
 // lanes); 5 = HBM copy of `bytes` (result: bytes read + written per second).
 extern "C" int dsa_probe(int which, int64_t size, double *rate) {
     if (!rate || which < 0 || which > 5 || size <= 0) return DSA_E_INVAL;
-    hipEvent_t a, b;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return DSA_E_DEVICE;
     int dev = 0, cus = 256;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess) return DSA_E_DEVICE;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    hipEvent_t a = nullptr, b = nullptr;
+    void *p0 = nullptr, *p1 = nullptr;
     int rc = DSA_OK;
-    if (which < 5) {
-        uint32_t *out = nullptr;
-        const int blocks = cus * 8;  // 8 x 4 waves per CU
-        if (hipMalloc(&out, blocks * sizeof(uint32_t)) != hipSuccess) return DSA_E_DEVICE;
-        const int iters = (int)std::min<int64_t>(size, 1 << 30);
-        auto launch = [&]() {
-            switch (which) {
-                case 0: hipLaunchKernelGGL(k_probe<0>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
-                case 1: hipLaunchKernelGGL(k_probe<1>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
-                case 2: hipLaunchKernelGGL(k_probe<2>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
-                case 3: hipLaunchKernelGGL(k_probe<3>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
-                default: hipLaunchKernelGGL(k_probe<4>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
+    auto ok = [&](hipError_t e) {
+        if (e != hipSuccess && rc == DSA_OK) rc = DSA_E_DEVICE;
+        return rc == DSA_OK;
+    };
+    if (ok(hipEventCreate(&a)) && ok(hipEventCreate(&b))) {
+        float ms = 0.f;
+        if (which < 5) {
+            const int blocks = cus * 8;  // 8 x 4 waves per CU
+            const int iters = (int)std::min<int64_t>(size, 1 << 30);
+            uint32_t *out = nullptr;
+            if (ok(hipMalloc(&p0, blocks * sizeof(uint32_t)))) {
+                out = (uint32_t *)p0;
+                auto launch = [&]() {
+                    switch (which) {
+                        case 0: hipLaunchKernelGGL(k_probe<0>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
+                        case 1: hipLaunchKernelGGL(k_probe<1>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
+                        case 2: hipLaunchKernelGGL(k_probe<2>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
+                        case 3: hipLaunchKernelGGL(k_probe<3>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
+                        default: hipLaunchKernelGGL(k_probe<4>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
+                    }
+                    return hipGetLastError();
+                };
+                if (ok(launch()) && ok(hipEventRecord(a, 0)) && ok(launch()) && ok(hipEventRecord(b, 0)) &&
+                    ok(hipEventSynchronize(b)) && ok(hipEventElapsedTime(&ms, a, b)))
+                    *rate = (double)blocks * 256.0 * 16.0 * iters / (ms * 1e-3);
             }
-        };
-        launch();
-        hipEventRecord(a, 0);
-        launch();
-        hipEventRecord(b, 0);
-        if (hipEventSynchronize(b) != hipSuccess) rc = DSA_E_DEVICE;
-        float ms = 0;
-        hipEventElapsedTime(&ms, a, b);
-        *rate = (double)blocks * 256.0 * 16.0 * iters / (ms * 1e-3);
-        hipFree(out);
-    } else {
-        uint4 *src = nullptr, *dst = nullptr;
-        const int64_t n = size / 16;
-        if (hipMalloc(&src, n * 16) != hipSuccess) return DSA_E_DEVICE;
-        if (hipMalloc(&dst, n * 16) != hipSuccess) { hipFree(src); return DSA_E_DEVICE; }
-        hipMemset(src, 1, n * 16);
-        hipLaunchKernelGGL(k_stream_copy, dim3(cus * 16), dim3(256), 0, 0, src, dst, n);
-        hipEventRecord(a, 0);
-        for (int r = 0; r < 5; r++)
-            hipLaunchKernelGGL(k_stream_copy, dim3(cus * 16), dim3(256), 0, 0, src, dst, n);
-        hipEventRecord(b, 0);
-        if (hipEventSynchronize(b) != hipSuccess) rc = DSA_E_DEVICE;
-        float ms = 0;
-        hipEventElapsedTime(&ms, a, b);
-        *rate = 5.0 * 2.0 * (double)n * 16.0 / (ms * 1e-3);
-        hipFree(src);
-        hipFree(dst);
+        } else {
+            const int64_t n = size / 16;
+            if (ok(hipMalloc(&p0, n * 16)) && ok(hipMalloc(&p1, n * 16)) && ok(hipMemset(p0, 1, n * 16))) {
+                const uint4 *src = (const uint4 *)p0;
+                uint4 *dst = (uint4 *)p1;
+                hipLaunchKernelGGL(k_stream_copy, dim3(cus * 16), dim3(256), 0, 0, src, dst, n);
+                if (ok(hipGetLastError()) && ok(hipEventRecord(a, 0))) {
+                    for (int r = 0; r < 5; r++)
+                        hipLaunchKernelGGL(k_stream_copy, dim3(cus * 16), dim3(256), 0, 0, src, dst, n);
+                    if (ok(hipGetLastError()) && ok(hipEventRecord(b, 0)) && ok(hipEventSynchronize(b)) &&
+                        ok(hipEventElapsedTime(&ms, a, b)))
+                        *rate = 5.0 * 2.0 * (double)n * 16.0 / (ms * 1e-3);
+                }
+            }
+        }
     }
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    if (p0) (void)hipFree(p0);
+    if (p1) (void)hipFree(p1);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
     return rc;
 }

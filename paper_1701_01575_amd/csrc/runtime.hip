@@ -153,16 +153,16 @@ static_assert(kTI == kT32, "the wavefront and int32 kernels share the 16-row str
 
 static void db_free(dsa_db *db) {
     if (!db) return;
-    hipFree(db->d_packed);
-    hipFree(db->d_grp);
-    hipFree(db->d_slot_target);
-    hipFree(db->d_slot_len);
-    hipFree(db->d_pair_dec);
-    hipFree(db->d_inv_map);
-    hipFree(db->d_len);
-    hipFree(db->d_pairs);
-    hipFree(db->d_lcodes);
-    hipFree(db->d_codes);
+    (void)hipFree(db->d_packed);
+    (void)hipFree(db->d_grp);
+    (void)hipFree(db->d_slot_target);
+    (void)hipFree(db->d_slot_len);
+    (void)hipFree(db->d_pair_dec);
+    (void)hipFree(db->d_inv_map);
+    (void)hipFree(db->d_len);
+    (void)hipFree(db->d_pairs);
+    (void)hipFree(db->d_lcodes);
+    (void)hipFree(db->d_codes);
     delete db;
 }
 
@@ -194,7 +194,6 @@ extern "C" int dsa_db_create(const uint8_t *codes, const int64_t *offsets, int64
     }
 
     dsa_db *db = new dsa_db();
-    hipGetDevice(&db->device);
     db->A = alphabet_size;
     db->n_targets = n_targets;
     db->n_residues = total;
@@ -291,6 +290,13 @@ extern "C" int dsa_db_create(const uint8_t *codes, const int64_t *offsets, int64
         pair_dec[2 * p + 1] = (uint8_t)(p % AP);
     }
 
+    {
+        const hipError_t e = hipGetDevice(&db->device);
+        if (e != hipSuccess) {
+            db_free(db);
+            return fail(DSA_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+        }
+    }
     int rc;
     if ((rc = upload(reinterpret_cast<uint16_t **>(&db->d_packed), packed.data(), packed.size(),
                      &db->device_bytes)) ||
@@ -1406,7 +1412,7 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
     std::vector<QueryInfo> q32 = P.qinfo;
     for (auto &q : q32) q.strips = (q.len + kT32 - 1) / kT32;
     int dev = 0;
-    hipGetDevice(&dev);
+    HIPCHK(hipGetDevice(&dev));
     Staging &S = g_staging[dev & 63];
     if (phase != RUN_KERNELS) {
         std::lock_guard<std::mutex> lk(S.mu);
@@ -1750,7 +1756,7 @@ static int align_phase(const dsa_args *args, const dsa_out *out, int phase) {
     if (rc) return rc;
     if ((rc = check_workspace(args, P.total))) return rc;
     int dev = 0;
-    hipGetDevice(&dev);
+    HIPCHK(hipGetDevice(&dev));
     if (args->db && args->db->device != dev)
         return fail(DSA_E_INVAL, "database lives on another device");
     if (phase != RUN_ALL && P.K > 0 && P.traceback)
@@ -1770,8 +1776,8 @@ struct dsa_graph {
 
 static void graph_free(dsa_graph *g) {
     if (!g) return;
-    if (g->exec) hipGraphExecDestroy(g->exec);
-    if (g->graph) hipGraphDestroy(g->graph);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
     delete g;
 }
 
@@ -1782,7 +1788,13 @@ extern "C" int dsa_graph_create(const dsa_args *args, const dsa_out *out, dsa_gr
     hipStream_t st = (hipStream_t)args->stream;
     if (!st) return fail(DSA_E_INVAL, "recording a graph needs a stream other than the null stream");
     dsa_graph *g = new dsa_graph();
-    hipGetDevice(&g->device);
+    {
+        const hipError_t e = hipGetDevice(&g->device);
+        if (e != hipSuccess) {
+            graph_free(g);
+            return fail(DSA_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+        }
+    }
     {
         Aux *aux = nullptr;  // created outside the recording
         int arc = aux_get(g->device, &aux);
@@ -1801,12 +1813,12 @@ extern "C" int dsa_graph_create(const dsa_args *args, const dsa_out *out, dsa_gr
     hipGraph_t gr = nullptr;
     e = hipStreamEndCapture(st, &gr);
     if (rc != DSA_OK && rc != DSA_E_CAPACITY) {
-        if (gr) hipGraphDestroy(gr);
+        if (gr) (void)hipGraphDestroy(gr);
         graph_free(g);
         return rc;
     }
     if (e != hipSuccess || !gr) {
-        if (gr) hipGraphDestroy(gr);
+        if (gr) (void)hipGraphDestroy(gr);
         graph_free(g);
         return fail(DSA_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
     }
@@ -1823,7 +1835,7 @@ extern "C" int dsa_graph_create(const dsa_args *args, const dsa_out *out, dsa_gr
 extern "C" int dsa_graph_launch(dsa_graph *g, void *stream) {
     if (!g || !g->exec) return fail(DSA_E_INVAL, "graph is NULL");
     int dev = 0;
-    hipGetDevice(&dev);
+    HIPCHK(hipGetDevice(&dev));
     if (dev != g->device) return fail(DSA_E_INVAL, "graph was recorded on another device");
     HIPCHK(hipGraphLaunch(g->exec, (hipStream_t)stream));
     return DSA_OK;
@@ -1884,7 +1896,7 @@ extern "C" int dsa_tuning_get(const dsa_args *args, dsa_tuning *out) {
 namespace {
 struct DevBuf {
     void *p = nullptr;
-    ~DevBuf() { if (p) hipFree(p); }
+    ~DevBuf() { if (p) (void)hipFree(p); }
 };
 }  // namespace
 
@@ -1990,7 +2002,7 @@ extern "C" int dsa_autotune(const dsa_args *args, const char *cache_path, dsa_tu
             if (r != DSA_OK) break;
             if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { r = DSA_E_DEVICE; break; }
             float f = 0.f;
-            hipEventElapsedTime(&f, e0, e1);
+            (void)hipEventElapsedTime(&f, e0, e1);
             if (rep > 0) v.push_back((double)f);
         }
         t_force = nullptr;
@@ -2034,8 +2046,8 @@ extern "C" int dsa_autotune(const dsa_args *args, const char *cache_path, dsa_tu
             }
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc) return fail(rc, std::string("autotune: ") + dsa_last_error());
     if (!tried) return fail(DSA_E_NOTSUP, "autotune: no candidate ran for these arguments");
     best.ms = best_ms;
