@@ -21,7 +21,8 @@
  *   semiglobal   the query end to end, the target's prefix/suffix free by
  *                default; free_ends (DSA_QB|DSA_QE|DSA_TB|DSA_TE) selects which
  *                ends are free (0 = DSA_TB|DSA_TE); the result is the best of
- *                H[m][n], the last row if TE, the last column if QE
+ *                H[m][n], the last row if TE, the last column if QE (a search
+ *                with QE runs the exact int32 kernel, as DSA_FORCE_INT32)
  *   end cell     among the cells reaching the result: smallest target end,
  *                then smallest query end
  *   traceback    priority zero (local) > diagonal > gap in query (D) > gap in

@@ -89,6 +89,9 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pair32(PairArgs P) {
     const int ncols = G.ncols;
 
     int Gs = (MODE == LOCAL) ? 0 : PAD32, Gj = 0, Gi = 0;
+    // free query end: the last column's best, starting from row 0
+    const bool qe_free = (MODE == SEMIGLOBAL) && (ends & QE);
+    int Qs = top_value(MODE, ends, o, e, n), Qi = 0;
     for (int s = 0; s < S; s++) {
         const int i0 = s * T;
         const bool first = (s == 0), wave_last = (s == S - 1), last = (s == Sl - 1);
@@ -187,15 +190,18 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pair32(PairArgs P) {
                         for (int r = T - 1; r >= 0; r--) rr = (H[r] == cm) ? r : rr;
                         B = cm; Bj = j; Bi = i0 + rr + 1;
                     }
-                } else if (last && (j == n || ((ends & TE) && j < n))) {
-                    int vl = H[0];
+                } else {
+                    if (last && (j == n || ((ends & TE) && j < n))) {
+                        int vl = H[0];
 #pragma unroll
-                    for (int k = 1; k < T; k++) vl = (k == rlast) ? H[k] : vl;
-                    if (!(ends & TE)) {
-                        res = vl;
-                    } else if (vl > Ls) {
-                        Ls = vl; Lj = j;
+                        for (int k = 1; k < T; k++) vl = (k == rlast) ? H[k] : vl;
+                        if (!(ends & TE)) {
+                            res = vl;
+                        } else if (vl > Ls) {
+                            Ls = vl; Lj = j;
+                        }
                     }
+                    if (qe_free && j == n && s < Sl) last_column_scan<T>(H, i0, m, Qs, Qi);
                 }
                 if (!wave_last) bnd[(int64_t)(j - 1) * kWave] = make_uint2((uint32_t)H[T - 1], (uint32_t)F);
             }
@@ -210,6 +216,10 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pair32(PairArgs P) {
         }
     }
     if (!act) return;
+    if (qe_free && Sl > 0) {  // the last row's candidate against the last column's
+        const uint64_t gk = umax64(end_key(Gs, Gj, Gi), end_key(Qs, n, Qi));
+        Gs = key_score(gk); Gj = key_j(gk); Gi = key_i(gk);
+    }
     if (Sl == 0) {  // empty query: the last row is the top boundary row
         if (MODE == LOCAL) { Gs = 0; }
         else if (MODE == SEMIGLOBAL && (ends & TE)) { Gs = 0; Gj = 0; }
@@ -218,7 +228,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pair32(PairArgs P) {
     }
     int qe, te;
     if (MODE == LOCAL) { qe = Gs > 0 ? Gi - 1 : -1; te = Gs > 0 ? Gj - 1 : -1; }
-    else { qe = m - 1; te = Gj - 1; }
+    else { qe = Gi - 1; te = Gj - 1; }
     P.out_score[I.res] = Gs;
     if (P.out_qend) P.out_qend[I.res] = qe;
     if (P.out_tend) P.out_tend[I.res] = te;
@@ -316,6 +326,9 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
 
     uint64_t gk = end_key(0, 0, 0);  // local: this lane's best over its strips
     int gs = 0, gj = 0;              // global / semi: held by the lane of the last strip
+    // free query end: each lane's best of the last column over its strips
+    const bool qe_free = (MODE == SEMIGLOBAL) && (ends & QE);
+    int Qs = PAD32, Qi = 0;
     for (int pass = 0; pass < passes; pass++) {
         const int s = pass * SEG + lane;
         const bool act = s < S, last = (s == S - 1);
@@ -400,13 +413,16 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
                         for (int r = T - 1; r >= 0; r--) rr = (H[r] == cm) ? r : rr;
                         B = cm; Bj = j; Bi = i0 + rr + 1;
                     }
-                } else if (last && ((ends & TE) || j == n)) {
-                    const int vl = row_of<T>(H, rlast);
-                    if (!(ends & TE)) {
-                        res = vl;
-                    } else if (vl > Ls) {
-                        Ls = vl; Lj = j;
+                } else {
+                    if (last && ((ends & TE) || j == n)) {
+                        const int vl = row_of<T>(H, rlast);
+                        if (!(ends & TE)) {
+                            res = vl;
+                        } else if (vl > Ls) {
+                            Ls = vl; Lj = j;
+                        }
                     }
+                    if (qe_free && j == n) last_column_scan<T>(H, i0, m, Qs, Qi);
                 }
                 outH = H[T - 1];
                 outF = F;
@@ -436,6 +452,19 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
         Gs = __shfl(gs, src, SEG);
         Gj = __shfl(gj, src, SEG);
         Gi = m;
+        if (qe_free) {
+            // the last column's best over the lanes (row 0 included), then
+            // against the last row's candidate
+            uint64_t qk = (lane == 0) ? end_key(top_value(MODE, ends, o, e, n), n, 0) : end_key(PAD32, n, 0);
+            if (Qs > PAD32) qk = umax64(qk, end_key(Qs, n, Qi));
+            for (int d = 1; d < SEG; d <<= 1) {
+                const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)qk, d, SEG);
+                const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(qk >> 32), d, SEG);
+                qk = umax64(qk, ((uint64_t)hi << 32) | lo);
+            }
+            const uint64_t gk2 = umax64(end_key(Gs, Gj, Gi), qk);
+            Gs = key_score(gk2); Gj = key_j(gk2); Gi = key_i(gk2);
+        }
     }
     if (lane != 0) return;
     if (S == 0) {  // empty query: the last row is the top boundary row
@@ -446,7 +475,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
     }
     int qe, te;
     if (MODE == LOCAL) { qe = Gs > 0 ? Gi - 1 : -1; te = Gs > 0 ? Gj - 1 : -1; }
-    else { qe = m - 1; te = Gj - 1; }
+    else { qe = Gi - 1; te = Gj - 1; }
     P.out_score[I.res] = Gs;
     if (P.out_qend) P.out_qend[I.res] = qe;
     if (P.out_tend) P.out_tend[I.res] = te;

@@ -64,6 +64,20 @@ __device__ __forceinline__ int key_j(uint64_t k) { return 0xffff - (int)((k >> 1
 __device__ __forceinline__ int key_i(uint64_t k) { return 0xffff - (int)(k & 0xffff); }
 __device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
 
+// Free query end (semi-global QE): the best cell of the last column, over
+// rows i0 + 1 .. of one strip that are real (i <= m); strictly greater, rows
+// in order, so the smallest i wins ties (strips are visited in order too).
+template <int T>
+__device__ __forceinline__ void last_column_scan(const int (&H)[T], int i0, int m, int &Qs, int &Qi) {
+#pragma unroll
+    for (int r = 0; r < T; r++) {
+        if (i0 + r < m && H[r] > Qs) {
+            Qs = H[r];
+            Qi = i0 + r + 1;
+        }
+    }
+}
+
 template <int T>
 __device__ __forceinline__ uint32_t pick_row(const uint32_t (&H)[T], int r) {
     uint32_t v = H[0];

@@ -889,7 +889,6 @@ int make_pair_plan(const dsa_args *a, const dsa_out *out, PairPlan &P) {
         if (a->t_offsets[k + 1] < a->t_offsets[k]) return fail(DSA_E_INVAL, "t_offsets must be non-decreasing");
     if (a->top_k) return fail(DSA_E_INVAL, "top_k applies to database search only");
     const int ends = a->mode == DSA_SEMIGLOBAL ? (a->free_ends ? a->free_ends : (DSA_TB | DSA_TE)) : 0;
-    if (ends & DSA_QE) return fail(DSA_E_NOTSUP, "free query end (QE) is not supported");
     std::vector<PairSpec> sp(n);
     for (int64_t k = 0; k < n; k++) {
         sp[k].q_off = a->q_offsets[k];
@@ -910,7 +909,6 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     const dsa_db *db = a->db;
     if (db->A != a->alphabet_size) return fail(DSA_E_INVAL, "alphabet_size differs from the database's");
     const int ends = a->mode == DSA_SEMIGLOBAL ? (a->free_ends ? a->free_ends : (DSA_TB | DSA_TE)) : 0;
-    if (ends & DSA_QE) return fail(DSA_E_NOTSUP, "free query end (QE) is not supported in database search");
     if (a->top_k < 0 || a->top_k > 64) return fail(DSA_E_INVAL, "top_k must be in [0, 64]");
     if ((a->flags & DSA_TRACEBACK) && a->top_k == 0)
         return fail(DSA_E_NOTSUP, "database-search traceback needs top_k (trace the hits)");
@@ -919,7 +917,8 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     P.mode = a->mode;
     P.ends = ends;
     P.persistent = !(a->flags & DSA_PLAIN);
-    P.force32 = (a->flags & DSA_FORCE_INT32) != 0;
+    // a free query end is tracked by the exact int32 kernel only
+    P.force32 = (a->flags & DSA_FORCE_INT32) != 0 || (ends & DSA_QE) != 0;
     const int A = a->alphabet_size;
     int mn = 0, mx = 0;
     for (int k = 0; k < A * A; k++) {

@@ -354,6 +354,9 @@ __global__ void __launch_bounds__(1024) k_search32(SearchArgs P, int rerun_only)
                      (int64_t)half * G.ncols * 64 + lane;
 
         int Gs = (MODE == LOCAL) ? 0 : PAD32, Gj = 0, Gi = 0;
+        // free query end: the last column's best, starting from row 0
+        const bool qe_free = (MODE == SEMIGLOBAL) && (ends & QE);
+        int Qs = top_value(MODE, ends, o, e, nt), Qi = 0;
         for (int s = 0; s < S; s++) {
             const int i0 = s * T;
             __syncthreads();
@@ -428,15 +431,18 @@ __global__ void __launch_bounds__(1024) k_search32(SearchArgs P, int rerun_only)
                             for (int r = T - 1; r >= 0; r--) rr = (H[r] == cm) ? r : rr;
                             B = cm; Bj = j; Bi = i0 + rr + 1;
                         }
-                    } else if (last) {
-                        int vl = H[0];
+                    } else {
+                        if (last) {
+                            int vl = H[0];
 #pragma unroll
-                        for (int k = 1; k < T; k++) vl = (k == rlast) ? H[k] : vl;
-                        if (!(ends & TE)) {
-                            if (j == nt) res = vl;
-                        } else if (j <= nt && vl > Ls) {
-                            Ls = vl; Lj = j;
+                            for (int k = 1; k < T; k++) vl = (k == rlast) ? H[k] : vl;
+                            if (!(ends & TE)) {
+                                if (j == nt) res = vl;
+                            } else if (j <= nt && vl > Ls) {
+                                Ls = vl; Lj = j;
+                            }
                         }
+                        if (qe_free && j == nt) last_column_scan<T>(H, i0, m, Qs, Qi);
                     }
                     if (!last) bnd[(int64_t)(j - 1) * 64] = make_uint2((uint32_t)H[T - 1], (uint32_t)F);
                 }
@@ -447,7 +453,12 @@ __global__ void __launch_bounds__(1024) k_search32(SearchArgs P, int rerun_only)
             } else if (last) {
                 if (ends & TE) { Gs = Ls; Gj = Lj; }
                 else { Gs = res; Gj = nt; }
+                Gi = m;
             }
+        }
+        if (qe_free) {  // the last row's candidate against the last column's
+            const uint64_t gk = umax64(end_key(Gs, Gj, Gi), end_key(Qs, nt, Qi));
+            Gs = key_score(gk); Gj = key_j(gk); Gi = key_i(gk);
         }
 
         if (active) {
@@ -462,7 +473,7 @@ __global__ void __launch_bounds__(1024) k_search32(SearchArgs P, int rerun_only)
                 if (write) {
                     int qe, te;
                     if (MODE == LOCAL) { qe = Gs > 0 ? Gi - 1 : -1; te = Gs > 0 ? Gj - 1 : -1; }
-                    else { qe = m - 1; te = Gj - 1; }
+                    else { qe = Gi - 1; te = Gj - 1; }
                     P.out_score[oi] = Gs;
                     if (P.out_qend) P.out_qend[oi] = qe;
                     if (P.out_tend) P.out_tend[oi] = te;

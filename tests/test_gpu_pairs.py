@@ -177,6 +177,31 @@ def test_pairs_longest(mode, blosum):
     compare_pairs(got, exp, True, f"longest {mode}")
 
 
+@pytest.mark.parametrize("ends", [2, 2 | 8, 1 | 2, 2 | 4, 15])
+@pytest.mark.parametrize("route", ["lanes", "wavefront"])
+@pytest.mark.parametrize("traceback", [True, False], ids=["tb", "score"])
+def test_pairs_free_query_end(ends, route, traceback, blosum, monkeypatch):
+    """Semi-global with a free query end, through either pair kernel: the
+    alignment may stop before the last query residue, or at row 0."""
+    if route == "lanes":
+        monkeypatch.setenv("DSA_PAIR_WF_ROWS", str(1 << 30))
+    else:
+        all_wavefront(monkeypatch)
+    Q, T = _pairs(20, 80, 0, 150, 20)
+    Q2, T2 = _pairs(21, 30, 50, 1200, 20, related=True)
+    # queries whose tail matches nothing: the free end pays off
+    rng = np.random.default_rng([170101575, 63])
+    tails = [np.concatenate([T2[k][:60], np.full(40, 22, np.uint8)]) for k in range(10)]
+    Q = SeqSet.from_list([Q[k] for k in range(len(Q))] + [Q2[k] for k in range(len(Q2))] + tails)
+    T = SeqSet.from_list([T[k] for k in range(len(T))] + [T2[k] for k in range(len(T2))] +
+                         [T2[k] for k in range(10)])
+    log(f"pairs QE ends={ends} route={route} tb={traceback}")
+    got = gpu_pairs(Q, T, blosum, 10, 1, "semiglobal", ends, traceback)
+    exp = oracle.align_pairs(Q, T, blosum, 10, 1, mode="semiglobal", ends=ends, traceback=traceback)
+    compare_pairs(got, exp, traceback, f"QE {ends} {route}")
+    assert (np.asarray(exp["q_end"]) < Q.lengths - 1).any()
+
+
 def test_pairs_chunked_codes(blosum, monkeypatch):
     monkeypatch.setenv("DSA_TB_BUDGET", str(1 << 20))  # many chunks of direction codes
     Q, T = _pairs(13, 400, 20, 300, 20, related=True)

@@ -51,6 +51,24 @@ def test_search_modes(mode, ends, plain, strip, blosum, monkeypatch):
     compare_search(got, exp, len(Q), len(T), label=f"{mode}/{ends}/{plain}")
 
 
+QE_ENDS = [2, 2 | 8, 1 | 2, 2 | 4, 15]
+
+
+@pytest.mark.parametrize("ends", QE_ENDS)
+@pytest.mark.parametrize("plain", [False, True], ids=["persistent", "plain"])
+def test_search_free_query_end(ends, plain, blosum):
+    """Semi-global with a free query end (the last column is a candidate
+    too, row 0 included): the search runs the exact int32 kernel."""
+    T = _targets(12, 300, 400, extra=[1, 2, 1200])
+    Q = _queries(13, [0, 1, 15, 16, 17, 33, 100, 700])
+    log(f"search QE ends={ends} plain={plain}")
+    got, _ = gpu_search(Q, T, blosum, 11, 1, "semiglobal", ends, plain=plain)
+    exp = oracle.search(Q, T, blosum, 11, 1, mode="semiglobal", ends=ends)
+    compare_search(got, exp, len(Q), len(T), label=f"QE {ends}/{plain}")
+    # some results end before the last query residue
+    assert (exp["q_end"] < np.repeat(Q.lengths - 1, len(T))).any()
+
+
 @pytest.mark.parametrize("mode,ends", CASES[:3])
 def test_search_force_int32(mode, ends, blosum):
     T = _targets(3, 200, 150)

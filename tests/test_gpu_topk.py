@@ -81,3 +81,23 @@ def test_topk_fewer_hits_than_k(dna):
     full, hits = expected_topk(Q, T, dna, 5, 2, 6, "local")
     assert (got["t_index"].reshape(2, 6) == hits).all()
     assert (got["t_index"] == -1).any()
+
+
+def test_topk_free_query_end_traceback(blosum):
+    """Top-K of a semi-global search with free query and target ends, the
+    hits traced: the search and the hit traceback both run int32 kernels."""
+    c = gen.cfg2(n_targets=800, query_lengths=(40, 300))
+    Q, T = c["queries"], c["targets"]
+    K, ends = 6, 2 | 8
+    got = run_topk(Q, T, blosum, 11, 1, K, "semiglobal", traceback=True, ends=ends)
+    full, hits = expected_topk(Q, T, blosum, 11, 1, K, "semiglobal", ends=ends)
+    nq, nt = len(Q), len(T)
+    assert (got["t_index"].reshape(nq, K) == hits).all()
+    qi = np.repeat(np.arange(nq), K)
+    ti = hits.reshape(-1)
+    exp = oracle.align_index(qi, ti, Q, T, blosum, 11, 1, mode="semiglobal", ends=ends, traceback=True)
+    for f in ("score", "q_begin", "q_end", "t_begin", "t_end"):
+        assert (got[f] == np.asarray(exp[f])).all(), f
+    for k in range(len(qi)):
+        assert (got["cigars"][k] == exp["cigars"][k]).all(), k
+
