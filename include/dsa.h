@@ -174,7 +174,10 @@ int dsa_cigar_capacity(const dsa_args *args, int64_t *entries);
  * dsa_align_batch - align (Sections II.B.1 and II.C.2; top-K per
  * Section II.B.2).  Asynchronous on args->stream.  Scores are exact: a
  * packed int16 pass is followed by an exact int32 rerun of every result
- * that could have saturated.
+ * that could have saturated (local search: every score above 29568, the
+ * exact range of its offset int16 values; global / semi-global: every score
+ * at either int16 bound), and these carry DSA_ST_INT32.  A local search with
+ * gap_open above 1024 runs the int32 kernel throughout.
  * Errors: DSA_E_INVAL, DSA_E_RANGE, DSA_E_WORKSPACE, DSA_E_NOTSUP,
  * DSA_E_DEVICE.
  */
@@ -262,9 +265,12 @@ int dsa_timing_reset(void);
 /*
  * dsa_probe - measured ceilings on the current device (blocking; allocates
  * its own scratch).  which: 0 v_pk_add_i16 (clamp), 1 v_pk_max_i16,
- * 2 v_pk_sub_u16 (clamp), 3 v_add_u32, 4 v_max_i32 -> *rate = instructions
- * per second summed over lanes, size = loop iterations; 5 -> HBM copy of
- * `size` bytes, *rate = bytes read + written per second.
+ * 2 v_pk_sub_u16 (clamp), 3 v_add_u32, 4 v_max_i32, 6 v_pk_maximum3_f16
+ * -> *rate = instructions per second summed over lanes, size = loop
+ * iterations; 5 -> HBM copy of `size` bytes, *rate = bytes read + written
+ * per second; 7 -> *rate = the number of wrong results of the packed
+ * binary16 three-way maximum over every operand pattern the local-mode int16
+ * search produces (must be 0; size is ignored but must be positive).
  */
 int dsa_probe(int which, int64_t size, double *rate);
 

@@ -11,6 +11,21 @@ constexpr int kPadLen = 4;           // group column count is a multiple of this
 constexpr int kMaxAlphabet = 32;
 constexpr int kMaxLen16 = 65532;     // int16 kernels index rows/columns with uint16
 constexpr int kT32 = 16;             // strip height of the int32 kernels
+// Local-mode int16 search holds H, E and F as value + an offset of at least
+// kBias16: every value is then a positive normal binary16 bit pattern, whose
+// binary16 order is its integer order, so one packed binary16 three-way
+// maximum does the work of two integer maxima.  The inter-sequence kernel
+// adds up to kShift16 more (a per-column offset that grows by gap_extend per
+// column and is taken back every few columns).  Exact while every H <=
+// kLocal16Max (H + offset + s stays at most 0x7bff, the largest finite
+// binary16, for s <= 127), and while H - gap_open stays normal
+// (gap_open <= kLocal16GapMax) and the column offset stays within kShift16
+// (gap_extend <= kLocal16ExtMax).
+constexpr int kBias16 = 2048;
+constexpr int kShift16 = 1024;
+constexpr int kLocal16Max = 0x7b80 - kBias16 - kShift16;
+constexpr int kLocal16GapMax = kBias16 - 1024;
+constexpr int kLocal16ExtMax = kShift16 / 4;
 
 enum Mode { LOCAL = 0, GLOBAL = 1, SEMIGLOBAL = 2 };
 enum Ends { QB = 1, QE = 2, TB = 4, TE = 8 };
@@ -225,6 +240,7 @@ struct ProfileArgs {
     const uint8_t *pair_dec;
     uint32_t *prof;
     int64_t total_dwords;
+    int32_t add;                  // added to every real score (local: gap_extend)
 };
 hipError_t launch_profile16(const ProfileArgs &a, int T, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);

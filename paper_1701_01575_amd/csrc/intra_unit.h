@@ -71,12 +71,14 @@ __device__ __forceinline__ void intra16_unit(const IntraArgs &P, const IntraUnit
         uint32_t H[T], E[T];
 #pragma unroll
         for (int r = 0; r < T; r++) {
-            H[r] = dup(left_value(MODE, ends, o, e, i0 + r + 1));
-            E[r] = (MODE == LOCAL) ? 0u : subs(H[r], o2);
+            H[r] = (MODE == LOCAL) ? dup(kBias16) : dup(left_value(MODE, ends, o, e, i0 + r + 1));
+            E[r] = (MODE == LOCAL) ? dup(kBias16) : subs(H[r], o2);
         }
-        uint32_t Hd_top = dup(left_value(MODE, ends, o, e, i0));
+        uint32_t Hd_top = (MODE == LOCAL) ? dup(kBias16) : dup(left_value(MODE, ends, o, e, i0));
+        // local: values offset by the bias, as in the inter-sequence kernel
         uint32_t B = 0, Bj = 0, Bi = 0;
-        if (MODE == LOCAL) B = pack2(max(key_score(gk[0]) - 1, 0), max(key_score(gk[1]) - 1, 0));
+        if (MODE == LOCAL)
+            B = pack2(max(key_score(gk[0]) - 1, 0) + kBias16, max(key_score(gk[1]) - 1, 0) + kBias16);
         const int rlast = m - 1 - i0;
         uint32_t res = 0, Ls = 0, Lj = 0;
         if (MODE != LOCAL && last) {
@@ -98,9 +100,8 @@ __device__ __forceinline__ void intra16_unit(const IntraArgs &P, const IntraUnit
             if (colok) {
                 if (lane == 0) {
                     if (pass == 0) {
-                        const int tv = top_value(MODE, ends, o, e, j);
-                        rH = dup(tv);
-                        rF = (MODE == LOCAL) ? 0u : subs(rH, o2);
+                        rH = (MODE == LOCAL) ? dup(kBias16) : dup(top_value(MODE, ends, o, e, j));
+                        rF = (MODE == LOCAL) ? dup(kBias16) : subs(rH, o2);
                     } else {
                         const uint2 b = bnd[j - 1];
                         rH = b.x;
@@ -125,14 +126,13 @@ __device__ __forceinline__ void intra16_unit(const IntraArgs &P, const IntraUnit
                     }
                 }
                 if (MODE == LOCAL) {
-                    const uint32_t cm = column16_local<T>(sc, H, E, Hd, F, o2, e2);
-                    const uint32_t nb = maxs(B, cm);
+                    const uint32_t nb = column16_local<T>(sc, H, E, Hd, F, o2, e2, B);
                     if (nb != B) {
                         const uint32_t mask = nzmask(nb ^ B);
-                        const uint32_t idx = first_row_of<T>(H, cm);
+                        const uint32_t idx = first_row_of<T>(H, nb);
                         Bi = bfi(mask, addu(idx, dup(i0 + 1)), Bi);
                         Bj = bfi(mask, dup(j), Bj);
-                        B = nb;
+                        B = maxs(B, nb);
                     }
                 } else {
                     column16_global<T>(sc, H, E, Hd, F, o2, e2);
@@ -156,7 +156,7 @@ __device__ __forceinline__ void intra16_unit(const IntraArgs &P, const IntraUnit
         }
         if (act) {
             if (MODE == LOCAL) {
-                const int b[2] = {lo16(B), hi16(B)};
+                const int b[2] = {lo16(B) - kBias16, hi16(B) - kBias16};
                 const int bj[2] = {(int)(Bj & 0xffff), (int)(Bj >> 16)};
                 const int bi[2] = {(int)(Bi & 0xffff), (int)(Bi >> 16)};
 #pragma unroll
@@ -206,7 +206,7 @@ __device__ __forceinline__ void intra16_unit(const IntraArgs &P, const IntraUnit
             if (MODE == LOCAL) {
                 qe = sc > 0 ? gi[h] - 1 : -1;
                 te = sc > 0 ? gj[h] - 1 : -1;
-                ovf |= sc >= 32767;
+                ovf |= sc > kLocal16Max;
             } else {
                 qe = m - 1;
                 te = gj[h] - 1;

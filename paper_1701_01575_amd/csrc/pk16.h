@@ -23,6 +23,14 @@ __device__ __forceinline__ uint32_t maxu(uint32_t a, uint32_t b) { return Bu(__b
 __device__ __forceinline__ uint32_t minu(uint32_t a, uint32_t b) { return Bu(__builtin_elementwise_min(U2(a), U2(b))); }
 __device__ __forceinline__ uint32_t addu(uint32_t a, uint32_t b) { return Bu(U2(a) + U2(b)); }
 __device__ __forceinline__ uint32_t mulu(uint32_t a, uint32_t b) { return Bu(U2(a) * U2(b)); }
+__device__ __forceinline__ uint32_t subw(uint32_t a, uint32_t b) { return Bu(U2(a) - U2(b)); }
+// Three-way maximum of two binary16 pairs (v_pk_maximum3_f16).  On positive
+// normal patterns it is the unsigned integer maximum of the bit patterns.
+__device__ __forceinline__ uint32_t max3h(uint32_t a, uint32_t b, uint32_t c) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const h2 x = __builtin_bit_cast(h2, a), y = __builtin_bit_cast(h2, b), z = __builtin_bit_cast(h2, c);
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_maximum(__builtin_elementwise_maximum(x, y), z));
+}
 
 __device__ __forceinline__ uint32_t pack2(int lo, int hi) {
     return (uint32_t)(uint16_t)lo | ((uint32_t)(uint16_t)hi << 16);
@@ -86,23 +94,60 @@ __device__ __forceinline__ uint32_t pick_row(const uint32_t (&H)[T], int r) {
     return v;
 }
 
-// One column of a strip, local mode, packed int16 (E, F clamped at 0 by the
-// unsigned saturating subtractions, so the 0 of the H maximum is implied).
-// Returns the column maximum.
+// One column of a strip, local mode, packed int16 held as value + kBias16.
+// E and F are floored at the bias (a zero floor on the values), which
+// implies the 0 of the H maximum.  The floors and the H maximum are binary16
+// three-way maxima; the additions and subtractions are integer.  Returns the
+// maximum of B and the column, also a three-way maximum chain.
 template <int T>
 __device__ __forceinline__ uint32_t column16_local(const uint32_t (&sc)[T], uint32_t (&H)[T],
                                                    uint32_t (&E)[T], uint32_t Hd, uint32_t &F,
-                                                   uint32_t o2, uint32_t e2) {
-    uint32_t cm = 0;
+                                                   uint32_t o2, uint32_t e2, uint32_t B) {
+    static_assert(T % 2 == 0, "rows are taken in pairs by the maximum chain");
+    const uint32_t K2 = dup(kBias16);
+    uint32_t cm = B, held = 0;
 #pragma unroll
     for (int r = 0; r < T; r++) {
-        const uint32_t t = adds(Hd, sc[r]);
+        const uint32_t t = addu(Hd, sc[r]);
         Hd = H[r];
-        const uint32_t h = maxs(maxs(t, E[r]), F);
-        cm = maxs(cm, h);
-        const uint32_t ho = subu(h, o2);
-        E[r] = maxu(subu(E[r], e2), ho);
-        F = maxu(subu(F, e2), ho);
+        const uint32_t h = max3h(t, E[r], F);
+        if (r & 1) cm = max3h(cm, held, h);
+        else held = h;
+        const uint32_t ho = subw(h, o2);
+        E[r] = max3h(subw(E[r], e2), ho, K2);
+        F = max3h(subw(F, e2), ho, K2);
+        H[r] = h;
+    }
+    return cm;
+}
+
+// One column, local mode, in the column-shifted frame of the inter-sequence
+// kernel: every value of column j is held as value + c_j, where c_j grows by
+// e from column to column (the caller takes a multiple of e back between
+// column blocks).  In that frame the gap-extend decrement of E disappears,
+// E[j+1] = max(E[j], H[j] - (o - e)), and F is formed as X = max(F, H - (o -
+// e)), the next row's F being X - e, so E and F share one subtraction.
+// phi = c_j + e is the floor of E[j+1] and of X (a zero floor on E and F,
+// which implies the 0 of the H maximum); the profile carries s + e, which
+// moves the diagonal term into this column's frame.  oe2 = o - e.  Returns
+// max(Bc, column), Bc being the running best in this column's frame.
+template <int T>
+__device__ __forceinline__ uint32_t column16_local_cs(const uint32_t (&sc)[T], uint32_t (&H)[T],
+                                                      uint32_t (&E)[T], uint32_t Hd, uint32_t &F,
+                                                      uint32_t oe2, uint32_t e2, uint32_t phi,
+                                                      uint32_t Bc) {
+    static_assert(T % 2 == 0, "rows are taken in pairs by the maximum chain");
+    uint32_t cm = Bc, held = 0;
+#pragma unroll
+    for (int r = 0; r < T; r++) {
+        const uint32_t t = addu(Hd, sc[r]);
+        Hd = H[r];
+        const uint32_t h = max3h(t, E[r], F);
+        if (r & 1) cm = max3h(cm, held, h);
+        else held = h;
+        const uint32_t hx = subw(h, oe2);
+        E[r] = max3h(E[r], hx, phi);
+        F = subw(max3h(F, hx, phi), e2);
         H[r] = h;
     }
     return cm;

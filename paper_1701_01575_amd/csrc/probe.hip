@@ -1,16 +1,17 @@
 // Peak probes: measured issue rate of the VALU instructions the alignment
 // kernels are built from (packed int16 add/sub with clamp, packed max,
-// plain 32-bit ops) and an HBM stream copy.  They give the measured
-// ceilings the roofline fractions are compared against.
+// packed binary16 three-way maximum, plain 32-bit ops) and an HBM stream
+// copy.  They give the measured ceilings the roofline fractions are
+// compared against.  One more probe checks, over every operand the offset
+// local-mode search can produce, that the binary16 three-way maximum orders
+// bit patterns as that search assumes.
 #include <algorithm>
 
 #include "dsa.h"
 #include "internal.h"
+#include "pk16.h"
 
 namespace dsa {
-
-typedef short s16x2 __attribute__((ext_vector_type(2)));
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 template <int OP>
 __device__ __forceinline__ uint32_t probe_op(uint32_t a, uint32_t b) {
@@ -21,6 +22,7 @@ __device__ __forceinline__ uint32_t probe_op(uint32_t a, uint32_t b) {
     if (OP == 2) return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(
                                               __builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b)));
     if (OP == 3) return a + b;
+    if (OP == 5) return max3h(a, b, 0x3c003c00u);
     return (uint32_t)max((int)a, (int)b);
 }
 
@@ -42,6 +44,29 @@ __global__ void __launch_bounds__(256) k_probe(uint32_t *out, int iters, uint32_
     if (r == 0x12345678u) out[blockIdx.x] = r;  // keeps the chains alive
 }
 
+// Order of a binary16 bit pattern as an integer (sign and magnitude).
+__device__ __forceinline__ int h_order(uint32_t p) { return p < 0x8000u ? (int)p : 0x7fff - (int)p; }
+
+// Every a in [0x0400, 0x7bff] and its negative, every b in [0x0400, 0x7bff],
+// c = the offset floor: max3h must return the operand of greatest order in
+// both halves (the high half gets b and a swapped).  Counts the failures.
+__global__ void k_max3_order(unsigned long long *bad) {
+    const uint32_t c = kBias16;
+    unsigned long long nbad = 0;
+    const int64_t na = 2 * 0x7800, nb = 0x7800, total = na * nb;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int ia = (int)(k / nb), ib = (int)(k - (int64_t)ia * nb);
+        const uint32_t a = (ia < 0x7800 ? 0x0400u : 0x8400u) + (uint32_t)(ia % 0x7800);
+        const uint32_t b = 0x0400u + (uint32_t)ib;
+        const uint32_t r = max3h(a | (b << 16), b | (a << 16), c | (c << 16));
+        uint32_t want = h_order(a) > h_order(b) ? a : b;
+        want = h_order(want) > h_order(c) ? want : c;
+        nbad += ((r & 0xffffu) != want) + ((r >> 16) != want);
+    }
+    if (nbad) atomicAdd(bad, nbad);
+}
+
 __global__ void k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -53,10 +78,12 @@ __global__ void k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__
 using namespace dsa;
 
 // which: 0 = v_pk_add_i16 clamp, 1 = v_pk_max_i16, 2 = v_pk_sub_u16 clamp,
-// 3 = v_add_u32, 4 = v_max_i32 (result: instructions per second summed over
-// lanes); 5 = HBM copy of `bytes` (result: bytes read + written per second).
+// 3 = v_add_u32, 4 = v_max_i32, 6 = v_pk_maximum3_f16 (result: instructions
+// per second summed over lanes); 5 = HBM copy of `bytes` (result: bytes read
+// + written per second); 7 = the three-way maximum order check (result: the
+// number of wrong results).
 extern "C" int dsa_probe(int which, int64_t size, double *rate) {
-    if (!rate || which < 0 || which > 5 || size <= 0) return DSA_E_INVAL;
+    if (!rate || which < 0 || which > 7 || size <= 0) return DSA_E_INVAL;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) != hipSuccess) return DSA_E_DEVICE;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
@@ -69,7 +96,14 @@ extern "C" int dsa_probe(int which, int64_t size, double *rate) {
     };
     if (ok(hipEventCreate(&a)) && ok(hipEventCreate(&b))) {
         float ms = 0.f;
-        if (which < 5) {
+        if (which == 7) {
+            unsigned long long bad = 0;
+            if (ok(hipMalloc(&p0, sizeof(bad))) && ok(hipMemset(p0, 0, sizeof(bad)))) {
+                hipLaunchKernelGGL(k_max3_order, dim3(cus * 8), dim3(256), 0, 0, (unsigned long long *)p0);
+                if (ok(hipGetLastError()) && ok(hipMemcpy(&bad, p0, sizeof(bad), hipMemcpyDeviceToHost)))
+                    *rate = (double)bad;
+            }
+        } else if (which != 5) {
             const int blocks = cus * 8;  // 8 x 4 waves per CU
             const int iters = (int)std::min<int64_t>(size, 1 << 30);
             uint32_t *out = nullptr;
@@ -81,6 +115,7 @@ extern "C" int dsa_probe(int which, int64_t size, double *rate) {
                         case 1: hipLaunchKernelGGL(k_probe<1>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
                         case 2: hipLaunchKernelGGL(k_probe<2>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
                         case 3: hipLaunchKernelGGL(k_probe<3>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
+                        case 6: hipLaunchKernelGGL(k_probe<5>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
                         default: hipLaunchKernelGGL(k_probe<4>, dim3(blocks), dim3(256), 0, 0, out, iters, 7u); break;
                     }
                     return hipGetLastError();

@@ -917,8 +917,10 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     P.mode = a->mode;
     P.ends = ends;
     P.persistent = !(a->flags & DSA_PLAIN);
-    // a free query end is tracked by the exact int32 kernel only
-    P.force32 = (a->flags & DSA_FORCE_INT32) != 0 || (ends & DSA_QE) != 0;
+    // a free query end is tracked by the exact int32 kernel only, and so is
+    // a local search whose gap penalties leave the offset int16 range
+    P.force32 = (a->flags & DSA_FORCE_INT32) != 0 || (ends & DSA_QE) != 0 ||
+                (a->mode == DSA_LOCAL && (a->gap_open > kLocal16GapMax || a->gap_extend > kLocal16ExtMax));
     const int A = a->alphabet_size;
     int mn = 0, mx = 0;
     for (int k = 0; k < A * A; k++) {
@@ -1503,6 +1505,7 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
         pa.pair_dec = db->d_pair_dec;
         pa.prof = (uint32_t *)(ws + P.off_prof);
         pa.total_dwords = P.prof_dwords;
+        pa.add = P.mode == DSA_LOCAL ? a->gap_extend : 0;  // the column-shifted local frame
         HIPCHK(launch_profile16(pa, P.T, st));
     }
     if (so.q_begin) HIPCHK(launch_fill_i32(so.q_begin, -1, nq * db->n_targets, st));

@@ -77,8 +77,8 @@ __global__ void k_profile16(ProfileArgs a) {
         if (r < T && i < Q.len) {
             const int c = min((int)a.q_codes[Q.off + i], A - 1);  // codes >= A are caller errors
             const int clo = a.inv_map[a.pair_dec[2 * p]], chi = a.inv_map[a.pair_dec[2 * p + 1]];
-            if (clo != 0xff) slo = a.subst[c * A + clo];
-            if (chi != 0xff) shi = a.subst[c * A + chi];
+            if (clo != 0xff) slo = a.subst[c * A + clo] + a.add;
+            if (chi != 0xff) shi = a.subst[c * A + chi] + a.add;
         }
         a.prof[k] = pack2(slo, shi);
     }
@@ -104,6 +104,12 @@ k_search16(SearchArgs P, IntraArgs W) {
     const int o = P.o, e = P.e, ends = P.ends, AP = P.AP;
     const uint32_t o2 = dup(o), e2 = dup(e);
     const int strip4 = AP * AP * SP / 4;  // uint4 per strip profile
+    // local mode, column-shifted frame: column j (1-based) holds value +
+    // kBias16 + ((j - 1) mod 4*rb) * e; every 4*rb columns the frame is taken
+    // back by 4*rb*e (at most kShift16)
+    const uint32_t oe2 = dup(o - e);
+    const int rb = e > 0 ? max(1, (kShift16 / 4) / e) : (1 << 28);
+    const uint32_t back2 = dup(4 * rb * e);
 
     for (int iter = 0;; iter++) {
         int u;
@@ -163,14 +169,15 @@ k_search16(SearchArgs P, IntraArgs W) {
             uint32_t H[T], E[T];
 #pragma unroll
             for (int r = 0; r < T; r++) {
-                H[r] = dup(left_value(MODE, ends, o, e, i0 + r + 1));
-                E[r] = (MODE == LOCAL) ? 0u : subs(H[r], o2);
+                // local: column 0 sits one e below column 1's frame
+                H[r] = (MODE == LOCAL) ? dup(kBias16 - e) : dup(left_value(MODE, ends, o, e, i0 + r + 1));
+                E[r] = (MODE == LOCAL) ? dup(kBias16) : subs(H[r], o2);
             }
-            uint32_t Hd_top = dup(left_value(MODE, ends, o, e, i0));
+            uint32_t Hd_top = (MODE == LOCAL) ? dup(kBias16 - e) : dup(left_value(MODE, ends, o, e, i0));
 
-            // strip-local running best (local mode): starts just below the
-            // best of earlier strips so only cells that can still win are
-            // recorded.
+            // strip-local running best (local mode, plain values): starts
+            // just below the best of earlier strips so only cells that can
+            // still win are recorded.
             uint32_t B = 0, Bj = 0, Bi = 0;
             if (MODE == LOCAL) B = maxs(subs(Gs, dup(1)), 0u);
             // last-strip capture (global / semi-global)
@@ -195,6 +202,15 @@ k_search16(SearchArgs P, IntraArgs W) {
                 }
             }
             for (int c4 = 0; c4 < nblk; c4++) {
+                if (MODE == LOCAL && c4 > 0 && c4 % rb == 0) {  // take the column frame back
+#pragma unroll
+                    for (int r = 0; r < T; r++) {
+                        H[r] = subw(H[r], back2);
+                        E[r] = subw(E[r], back2);
+                    }
+                    Hd_top = subw(Hd_top, back2);
+                }
+                const int cbase = kBias16 + (c4 % rb) * 4 * e;  // frame of the block's first column
                 const uint2 cd = cd_n;
                 uint2 hf[4];
 #pragma unroll
@@ -211,10 +227,10 @@ k_search16(SearchArgs P, IntraArgs W) {
                     const int j = c4 * 4 + c + 1;
                     const uint32_t p = ((c < 2 ? cd.x : cd.y) >> ((c & 1) * 16)) & 0xffffu;
                     uint32_t Hup, F;
+                    const int cj = cbase + c * e;  // local: this column's frame
                     if (first) {
-                        const int tv = top_value(MODE, ends, o, e, j);
-                        Hup = dup(tv);
-                        F = (MODE == LOCAL) ? 0u : subs(Hup, o2);
+                        Hup = (MODE == LOCAL) ? dup(cj) : dup(top_value(MODE, ends, o, e, j));
+                        F = (MODE == LOCAL) ? dup(cj) : subs(Hup, o2);
                     } else {
                         Hup = hf[c].x;
                         F = hf[c].y;
@@ -224,16 +240,18 @@ k_search16(SearchArgs P, IntraArgs W) {
                     uint32_t sc[T];
                     load_profile<T>(lds, p * SP, sc);
                     if (MODE == LOCAL) {
-                        const uint32_t cm = column16_local<T>(sc, H, E, Hd, F, o2, e2);
-                        const uint32_t nb = maxs(B, cm);
-                        if (nb != B) {
+                        const uint32_t Bc = addu(B, dup(cj));
+                        const uint32_t nb = column16_local_cs<T>(sc, H, E, Hd, F, oe2, e2, dup(cj + e), Bc);
+                        if (nb != Bc) {
                             // some half improved: find the first row reaching
-                            // the column maximum
-                            const uint32_t mask = nzmask(nb ^ B);
-                            const uint32_t idx = first_row_of<T>(H, cm);
+                            // the column maximum.  The integer maximum keeps B
+                            // from falling if a cell beyond the exact range
+                            // (flagged below) left a non-number pattern.
+                            const uint32_t mask = nzmask(nb ^ Bc);
+                            const uint32_t idx = first_row_of<T>(H, nb);
                             Bi = bfi(mask, addu(idx, dup(i0 + 1)), Bi);
                             Bj = bfi(mask, dup(j), Bj);
-                            B = nb;
+                            B = maxs(B, subw(nb, dup(cj)));
                         }
                     } else {
                         column16_global<T>(sc, H, E, Hd, F, o2, e2);
@@ -288,7 +306,7 @@ k_search16(SearchArgs P, IntraArgs W) {
                     const int ii = h ? (int)(Gi >> 16) : (int)(Gi & 0xffff);
                     qe = sc > 0 ? ii - 1 : -1;
                     te = sc > 0 ? jj - 1 : -1;
-                    ovf |= sc >= 32767;
+                    ovf |= sc > kLocal16Max;
                 } else {
                     qe = m - 1;
                     te = jj - 1;
@@ -468,7 +486,7 @@ __global__ void __launch_bounds__(1024) k_search32(SearchArgs P, int rerun_only)
                 bool write = true;
                 if (uflag == 1) {
                     const int prev = P.out_score[oi];
-                    write = (prev >= 32767) || (prev <= -32768);
+                    write = (MODE == LOCAL) ? prev > kLocal16Max : (prev >= 32767) || (prev <= -32768);
                 }
                 if (write) {
                     int qe, te;

@@ -12,7 +12,9 @@ if __package__ in (None, ""):
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 from paper_1701_01575_amd import binding as B  # noqa: E402
 
-NAMES = ["v_pk_add_i16 (clamp)", "v_pk_max_i16", "v_pk_sub_u16 (clamp)", "v_add_u32", "v_max_i32"]
+# which -> (name, 16-bit results per instruction)
+NAMES = {0: ("v_pk_add_i16 (clamp)", 2), 1: ("v_pk_max_i16", 2), 2: ("v_pk_sub_u16 (clamp)", 2),
+         6: ("v_pk_maximum3_f16", 2), 3: ("v_add_u32", 1), 4: ("v_max_i32", 1)}
 
 
 def main(argv):
@@ -22,12 +24,13 @@ def main(argv):
         r = B.dsa_probe(5, int(argv[1]))
         print(f"copy of {int(argv[1])} bytes x 6 launches: {r / 1e9:.0f} GB/s (read + write)")
         return
-    for w, n in enumerate(NAMES):
+    for w, (n, per) in NAMES.items():
         r = B.dsa_probe(w, 20000)
-        per16 = r * 2 if w < 3 else r
-        print(f"{n:22s} {r / 1e12:7.2f} T lane-instructions/s  ({per16 / 1e12:.2f} T 16-bit ops/s)")
+        print(f"{n:22s} {r / 1e12:7.2f} T lane-instructions/s  ({r * per / 1e12:.2f} T 16-bit ops/s)")
     r = B.dsa_probe(5, 4 << 30)
     print(f"HBM copy of 4 GiB: {r / 1e9:.0f} GB/s (read + write)")
+    bad = B.dsa_probe(7, 1)
+    print(f"v_pk_maximum3_f16 order check (offset local-mode operands): {int(bad)} wrong results")
 
 
 if __name__ == "__main__":

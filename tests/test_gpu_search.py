@@ -239,3 +239,53 @@ def test_search_rounds_of_one_query(mode, ends, blosum, monkeypatch):
     got, _ = gpu_search(Q, T, blosum, 11, 1, mode, ends)
     exp = oracle.search(Q, T, blosum, 11, 1, mode=mode, ends=ends)
     compare_search(got, exp, len(Q), len(T), label=f"rounds {mode}")
+
+
+LOCAL16_MAX = 28544  # highest local score the offset int16 pass computes exactly
+
+
+@pytest.mark.parametrize("budget", [None, "1"], ids=["inter", "wavefront"])
+def test_search_local_exact_range_edge(budget, blosum, monkeypatch):
+    """Scores on both sides of the offset int16 range's top: those at or
+    below it come from the int16 pass, those above (still below 32767, where
+    the packed values would not saturate) must come from the int32 rerun.
+    Self-similar prefixes under a x5 matrix place scores around the edge."""
+    if budget:
+        monkeypatch.setenv("DSA_INTRA_BUDGET", budget)
+    S = (blosum.astype(np.int32) * 5).clip(-128, 127).astype(np.int8)
+    rng = np.random.default_rng([170101575, 57])
+    base = gen.background_residues(rng, 1400)
+    diag = np.cumsum(S[base, base].astype(np.int64))
+    picks = [int(np.searchsorted(diag, v)) + 1 for v in
+             (28000, 28400, 28500, 28520, 28540, 28548, 28560, 28700, 29600, 31500, 32600)]
+    seqs = [base[:k] for k in picks] + [gen.background_residues(rng, 400) for _ in range(30)]
+    T = SeqSet.from_list(seqs)
+    Q = SeqSet.from_list([base, base[:1000]])
+    log(f"local exact-range edge budget={budget}")
+    got, _ = gpu_search(Q, T, S, 40, 4, "local")
+    exp = oracle.search(Q, T, S, 40, 4, mode="local")
+    compare_search(got, exp, len(Q), len(T), label="local edge")
+    sc = np.asarray(exp["score"])
+    above = (sc > LOCAL16_MAX) & (sc < 32767)
+    near = (sc <= LOCAL16_MAX) & (sc > LOCAL16_MAX - 600)
+    assert above.any() and near.any(), sorted(sc[sc > 20000])
+    assert (got["status"][above] & 1).all()
+
+
+@pytest.mark.parametrize("o,e,int32", [(1500, 1100, True), (1000, 300, True), (1024, 256, False),
+                                       (900, 0, False), (60, 60, False), (7, 3, False)])
+def test_search_local_gap_penalties(o, e, int32, blosum):
+    """Gap penalties at and beyond the offset int16 range (gap_open <= 1024,
+    gap_extend <= 256): beyond it a local search runs the exact int32 kernel;
+    at its edge, with no extension cost and with open = extend, the int16
+    pass (whose column frame is taken back every 4 * max(1, 256 // e)
+    columns) must still be exact.  Targets reach 1,500 residues so that the
+    frame is taken back several times."""
+    rng = np.random.default_rng([170101575, 58])
+    lens = list(rng.integers(0, 400, size=90)) + [1100, 1500]
+    T = SeqSet.from_list([gen.background_residues(rng, int(L)) for L in lens])
+    Q = _queries(12, [40, 300])
+    got, _ = gpu_search(Q, T, blosum, o, e, "local")
+    exp = oracle.search(Q, T, blosum, o, e, mode="local")
+    compare_search(got, exp, len(Q), len(T), label=f"gaps {o}/{e}")
+    assert bool((got["status"] & 1).all()) == int32
