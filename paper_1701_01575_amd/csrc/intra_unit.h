@@ -49,6 +49,13 @@ __device__ __forceinline__ void intra16_unit(const IntraArgs &P, const IntraUnit
     uint64_t gk[2] = {end_key(0, 0, 0), end_key(0, 0, 0)};
     int gs[2] = {NEG16, NEG16}, gj[2] = {0, 0};
     bool ovf = false;
+    // local: every lane works on the same two targets, so a cell scoring
+    // below the best any lane has seen cannot be the end cell.  Lanes record
+    // a cell only above a threshold, and every 16 steps the thresholds rise
+    // to one below the wave's best (ties stay recordable; the end-key merge
+    // orders them).  This keeps the end-cell branch as rare as in the
+    // inter-sequence kernel.  Wb: that floor carried across passes.
+    uint32_t Wb = dup(kBias16);
 
     for (int pass = 0; pass < passes; pass++) {
         __syncthreads();
@@ -76,9 +83,11 @@ __device__ __forceinline__ void intra16_unit(const IntraArgs &P, const IntraUnit
         }
         uint32_t Hd_top = (MODE == LOCAL) ? dup(kBias16) : dup(left_value(MODE, ends, o, e, i0));
         // local: values offset by the bias, as in the inter-sequence kernel
-        uint32_t B = 0, Bj = 0, Bi = 0;
+        // B: the recording threshold; Bs, Bj, Bi: the best cell recorded in
+        // this strip (Bs = 0: none), all offset by the bias
+        uint32_t B = 0, Bs = 0, Bj = 0, Bi = 0;
         if (MODE == LOCAL)
-            B = pack2(max(key_score(gk[0]) - 1, 0) + kBias16, max(key_score(gk[1]) - 1, 0) + kBias16);
+            B = maxs(Wb, pack2(max(key_score(gk[0]) - 1, 0) + kBias16, max(key_score(gk[1]) - 1, 0) + kBias16));
         const int rlast = m - 1 - i0;
         uint32_t res = 0, Ls = 0, Lj = 0;
         if (MODE != LOCAL && last) {
@@ -128,11 +137,15 @@ __device__ __forceinline__ void intra16_unit(const IntraArgs &P, const IntraUnit
                 if (MODE == LOCAL) {
                     const uint32_t nb = column16_local<T>(sc, H, E, Hd, F, o2, e2, B);
                     if (nb != B) {
+                        // the integer maximum keeps B and Bs from falling if a
+                        // cell beyond the exact range (flagged below) left a
+                        // non-number pattern
                         const uint32_t mask = nzmask(nb ^ B);
                         const uint32_t idx = first_row_of<T>(H, nb);
+                        B = maxs(B, nb);
+                        Bs = bfi(mask, B, Bs);
                         Bi = bfi(mask, addu(idx, dup(i0 + 1)), Bi);
                         Bj = bfi(mask, dup(j), Bj);
-                        B = maxs(B, nb);
                     }
                 } else {
                     column16_global<T>(sc, H, E, Hd, F, o2, e2);
@@ -153,10 +166,17 @@ __device__ __forceinline__ void intra16_unit(const IntraArgs &P, const IntraUnit
                 outF = F;
                 if (lane == kWave - 1 && pass + 1 < passes) bnd[j - 1] = make_uint2(outH, outF);
             }
+            if (MODE == LOCAL && ((t & 15) == 15 || t == nsteps - 1)) {
+                uint32_t w = B;
+#pragma unroll
+                for (int d = 1; d < kWave; d <<= 1) w = maxs(w, (uint32_t)__shfl_xor((int)w, d, kWave));
+                Wb = subw(w, dup(1));
+                B = maxs(B, Wb);
+            }
         }
         if (act) {
             if (MODE == LOCAL) {
-                const int b[2] = {lo16(B) - kBias16, hi16(B) - kBias16};
+                const int b[2] = {lo16(Bs) - kBias16, hi16(Bs) - kBias16};
                 const int bj[2] = {(int)(Bj & 0xffff), (int)(Bj >> 16)};
                 const int bi[2] = {(int)(Bi & 0xffff), (int)(Bi >> 16)};
 #pragma unroll
