@@ -10,11 +10,18 @@ namespace dsa {
 constexpr int kPassRows = kWave * kTI;   // 1024 rows per pass
 constexpr int kProfStride = kPassRows + 16;  // int16 per letter row (bank shift)
 
+constexpr int kIntraShiftExtMax = 4;  // local units use the column frame up to this gap_extend
+
 // One unit (a query against np long target pairs, one wave per pair) by the
 // whole block; every thread of the block calls it.  lds4 holds the pass
-// profile and the substitution matrix.
-template <int MODE>
-__device__ __forceinline__ void intra16_unit(const IntraArgs &P, const IntraUnit &U, uint4 *lds4) {
+// profile and the substitution matrix.  SHIFT (local mode): the column-shifted
+// frame of the inter-sequence kernel, here per lane (each lane is at its own
+// column): column j is held as value + kBias16 + ((j - 1) mod R) * e, R the
+// largest power of two with R * e <= kShift16, and a lane takes its frame back
+// by R * e when it enters column j = kR + 1.  Lanes hand rows to each other for
+// the same column, so no value changes frame in transit.
+template <int MODE, bool SHIFT>
+__device__ __forceinline__ void intra16_run(const IntraArgs &P, const IntraUnit &U, uint4 *lds4) {
     constexpr int T = kTI;
     int16_t *qp = reinterpret_cast<int16_t *>(lds4);                 // [AP][kProfStride]
     int8_t *sub = reinterpret_cast<int8_t *>(qp + P.AP * kProfStride);  // A*A
@@ -55,7 +62,10 @@ __device__ __forceinline__ void intra16_unit(const IntraArgs &P, const IntraUnit
     // to one below the wave's best (ties stay recordable; the end-key merge
     // orders them).  This keeps the end-cell branch as rare as in the
     // inter-sequence kernel.  Wb: that floor carried across passes.
-    uint32_t Wb = dup(kBias16);
+    uint32_t Wb = 0;
+    const uint32_t K2 = dup(kBias16), oe2 = dup(o - e);
+    const int R = e > 0 ? (1 << (31 - __builtin_clz(kShift16 / e))) : (1 << 30);
+    const uint32_t back2 = dup(R * e);
 
     for (int pass = 0; pass < passes; pass++) {
         __syncthreads();
@@ -65,7 +75,7 @@ __device__ __forceinline__ void intra16_unit(const IntraArgs &P, const IntraUnit
             const int i = pass * kPassRows + r;
             int v = NEG16;
             const int mc = P.inv_map[c];
-            if (i < m && mc != 0xff) v = sub[min((int)qc[i], A - 1) * A + mc];
+            if (i < m && mc != 0xff) v = sub[min((int)qc[i], A - 1) * A + mc] + (SHIFT ? e : 0);
             qp[c * kProfStride + r] = (int16_t)v;
         }
         __syncthreads();
@@ -76,18 +86,21 @@ __device__ __forceinline__ void intra16_unit(const IntraArgs &P, const IntraUnit
         const bool last = (s == S - 1);
         const int i0 = s * T;
         uint32_t H[T], E[T];
+        // local: values offset by the bias (and, with SHIFT, column 0 one e
+        // below column 1's frame), as in the inter-sequence kernel
+        const int h0 = SHIFT ? kBias16 - e : kBias16;
 #pragma unroll
         for (int r = 0; r < T; r++) {
-            H[r] = (MODE == LOCAL) ? dup(kBias16) : dup(left_value(MODE, ends, o, e, i0 + r + 1));
-            E[r] = (MODE == LOCAL) ? dup(kBias16) : subs(H[r], o2);
+            H[r] = (MODE == LOCAL) ? dup(h0) : dup(left_value(MODE, ends, o, e, i0 + r + 1));
+            E[r] = (MODE == LOCAL) ? K2 : subs(H[r], o2);
         }
-        uint32_t Hd_top = (MODE == LOCAL) ? dup(kBias16) : dup(left_value(MODE, ends, o, e, i0));
-        // local: values offset by the bias, as in the inter-sequence kernel
+        uint32_t Hd_top = (MODE == LOCAL) ? dup(h0) : dup(left_value(MODE, ends, o, e, i0));
+        uint32_t cj2 = K2;  // SHIFT: this lane's frame for its current column
         // B: the recording threshold; Bs, Bj, Bi: the best cell recorded in
-        // this strip (Bs = 0: none), all offset by the bias
+        // this strip (Bs = 0: none); plain values
         uint32_t B = 0, Bs = 0, Bj = 0, Bi = 0;
         if (MODE == LOCAL)
-            B = maxs(Wb, pack2(max(key_score(gk[0]) - 1, 0) + kBias16, max(key_score(gk[1]) - 1, 0) + kBias16));
+            B = maxs(Wb, pack2(max(key_score(gk[0]) - 1, 0), max(key_score(gk[1]) - 1, 0)));
         const int rlast = m - 1 - i0;
         uint32_t res = 0, Ls = 0, Lj = 0;
         if (MODE != LOCAL && last) {
@@ -107,10 +120,23 @@ __device__ __forceinline__ void intra16_unit(const IntraArgs &P, const IntraUnit
             const uint32_t cc = cnext;
             if (colok && j < ncols) cnext = codes[j];
             if (colok) {
+                if (SHIFT && j > 1) {
+                    if (((j - 1) & (R - 1)) == 0) {  // take this lane's frame back
+#pragma unroll
+                        for (int r = 0; r < T; r++) {
+                            H[r] = subw(H[r], back2);
+                            E[r] = subw(E[r], back2);
+                        }
+                        Hd_top = subw(Hd_top, back2);
+                        cj2 = K2;
+                    } else {
+                        cj2 = addu(cj2, e2);
+                    }
+                }
                 if (lane == 0) {
                     if (pass == 0) {
-                        rH = (MODE == LOCAL) ? dup(kBias16) : dup(top_value(MODE, ends, o, e, j));
-                        rF = (MODE == LOCAL) ? dup(kBias16) : subs(rH, o2);
+                        rH = (MODE == LOCAL) ? cj2 : dup(top_value(MODE, ends, o, e, j));
+                        rF = (MODE == LOCAL) ? cj2 : subs(rH, o2);
                     } else {
                         const uint2 b = bnd[j - 1];
                         rH = b.x;
@@ -135,14 +161,17 @@ __device__ __forceinline__ void intra16_unit(const IntraArgs &P, const IntraUnit
                     }
                 }
                 if (MODE == LOCAL) {
-                    const uint32_t nb = column16_local<T>(sc, H, E, Hd, F, o2, e2, B);
-                    if (nb != B) {
+                    const uint32_t frame = SHIFT ? cj2 : K2;
+                    const uint32_t Bc = addu(B, frame);
+                    const uint32_t nb = SHIFT ? column16_local_cs<T>(sc, H, E, Hd, F, oe2, e2, addu(cj2, e2), Bc)
+                                              : column16_local<T>(sc, H, E, Hd, F, o2, e2, Bc);
+                    if (nb != Bc) {
                         // the integer maximum keeps B and Bs from falling if a
                         // cell beyond the exact range (flagged below) left a
                         // non-number pattern
-                        const uint32_t mask = nzmask(nb ^ B);
+                        const uint32_t mask = nzmask(nb ^ Bc);
                         const uint32_t idx = first_row_of<T>(H, nb);
-                        B = maxs(B, nb);
+                        B = maxs(B, subw(nb, frame));
                         Bs = bfi(mask, B, Bs);
                         Bi = bfi(mask, addu(idx, dup(i0 + 1)), Bi);
                         Bj = bfi(mask, dup(j), Bj);
@@ -176,7 +205,7 @@ __device__ __forceinline__ void intra16_unit(const IntraArgs &P, const IntraUnit
         }
         if (act) {
             if (MODE == LOCAL) {
-                const int b[2] = {lo16(Bs) - kBias16, hi16(Bs) - kBias16};
+                const int b[2] = {lo16(Bs), hi16(Bs)};
                 const int bj[2] = {(int)(Bj & 0xffff), (int)(Bj >> 16)};
                 const int bi[2] = {(int)(Bi & 0xffff), (int)(Bi >> 16)};
 #pragma unroll
@@ -240,6 +269,17 @@ __device__ __forceinline__ void intra16_unit(const IntraArgs &P, const IntraUnit
         }
         if (ovf) P.unit_flags[U.runit] = 1;
     }
+}
+
+template <int MODE>
+__device__ __forceinline__ void intra16_unit(const IntraArgs &P, const IntraUnit &U, uint4 *lds4) {
+    if constexpr (MODE == LOCAL) {
+        if (P.e <= kIntraShiftExtMax) {
+            intra16_run<MODE, true>(P, U, lds4);
+            return;
+        }
+    }
+    intra16_run<MODE, false>(P, U, lds4);
 }
 
 }  // namespace dsa

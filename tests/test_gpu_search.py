@@ -272,15 +272,21 @@ def test_search_local_exact_range_edge(budget, blosum, monkeypatch):
     assert (got["status"][above] & 1).all()
 
 
+@pytest.mark.parametrize("budget", [None, "1"], ids=["inter", "wavefront"])
 @pytest.mark.parametrize("o,e,int32", [(1500, 1100, True), (1000, 300, True), (1024, 256, False),
-                                       (900, 0, False), (60, 60, False), (7, 3, False)])
-def test_search_local_gap_penalties(o, e, int32, blosum):
+                                       (900, 0, False), (60, 60, False), (7, 3, False), (11, 1, False),
+                                       (6, 4, False), (9, 5, False)])
+def test_search_local_gap_penalties(o, e, int32, budget, blosum, monkeypatch):
     """Gap penalties at and beyond the offset int16 range (gap_open <= 1024,
     gap_extend <= 256): beyond it a local search runs the exact int32 kernel;
     at its edge, with no extension cost and with open = extend, the int16
-    pass (whose column frame is taken back every 4 * max(1, 256 // e)
-    columns) must still be exact.  Targets reach 1,500 residues so that the
-    frame is taken back several times."""
+    pass must still be exact.  Its column frame is taken back every
+    4 * max(1, 256 // e) columns in the inter-sequence kernel, and in
+    wavefront units (which use the frame up to gap_extend 4) every R
+    columns, R the largest power of two with R * e <= 1024; targets reach
+    1,500 residues so that this happens several times."""
+    if budget:
+        monkeypatch.setenv("DSA_INTRA_BUDGET", budget)
     rng = np.random.default_rng([170101575, 58])
     lens = list(rng.integers(0, 400, size=90)) + [1100, 1500]
     T = SeqSet.from_list([gen.background_residues(rng, int(L)) for L in lens])
