@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_INT16_TOPS = 78.6      # 256 CUs x 4 SIMD x 16 lanes x 2 halves x 2.4 GHz
 OPS_PER_CELL = 10           # local score + end, algorithmic int16 ops per cell
+PEAK_LANE_INSTR_T = 39.3    # VALU lane-instructions/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
 
 
@@ -44,9 +45,10 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(cells):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
-    or None when the kernels changed since it was taken."""
+def load_pmc():
+    """The committed rocprofv3 counter summary of the search launch (HBM
+    bytes and VALU instructions per launch), or None when the kernels changed
+    since it was taken."""
     p = os.path.join(ROOT, "profiles", "search_cfg2_pmc.json")
     if not os.path.exists(p):
         return None
@@ -56,7 +58,7 @@ def load_traffic(cells):
         return None
     if d.get("source_hash") != source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d
 
 
 def run_serving(args, dsa, B, torch, gen, dev):
@@ -389,7 +391,17 @@ def main():
         log(f"plain: {plain_ms:.2f} ms/step, {plain_gcups:.1f} GCUPS")
 
     achieved = cells * OPS_PER_CELL / (replay_avg * 1e-3) / 1e12
-    traffic = load_traffic(cells)
+    pmc = load_pmc()
+    traffic = pmc.get("hbm_bytes_per_launch") if pmc else None
+    # counter view: VALU wave-instructions per launch (SQ_INSTS_VALU) x 64
+    # lanes over this run's launch time, against the nominal issue rate
+    counter = None
+    if pmc and pmc.get("valu_wave_insts_per_launch"):
+        lane_rate = pmc["valu_wave_insts_per_launch"] * 64 / (replay_avg * 1e-3) / 1e12
+        counter = {"valu_lane_instr_per_s_T": round(lane_rate, 2), "peak_T": PEAK_LANE_INSTR_T,
+                   "frac": round(lane_rate / PEAK_LANE_INSTR_T, 4),
+                   "valu_wave_insts_per_launch": pmc["valu_wave_insts_per_launch"],
+                   "source": "profiles/search_cfg2_pmc.json (SQ_INSTS_VALU)"}
     per_kernel = {}
     strip = dsa.tuning(Q, db=db, matrix=S)["strip"]
     for name, label in (("inter", f"k_search16<{strip},local,persistent>"), ("intra", "k_intra16<local>")):
@@ -404,7 +416,7 @@ def main():
                           "profile, flag and int32-rerun launches",
                 "duration_ms": round(replay_avg, 3), "timing": "HIP events around each replay on its stream",
                 "eager_kernels": per_kernel, "eager_span_ms": round(span_ms, 3),
-                "ops_per_cell": OPS_PER_CELL, "cells_per_launch": cells}
+                "ops_per_cell": OPS_PER_CELL, "cells_per_launch": cells, "counter": counter}
 
     score = outs["score"].cpu().numpy().reshape(nq, nt)
     q_end = outs["q_end"].cpu().numpy().reshape(nq, nt)

@@ -936,7 +936,7 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     // kernel has to take more of each query's work to keep the GPU busy
     P.T = P.persistent ? 16 : 32;
     if (search16_lds_bytes(32, db->AP) > 80 * 1024) P.T = 16;
-    P.wpb16 = 4;
+    P.wpb16 = P.persistent ? 8 : 4;
     P.budget = P.persistent ? 128000 : 8000;
     const Tuning tu = tuning_for(search_key(a, db->n_residues));
     if (tu.strip == 16 || (tu.strip == 32 && search16_lds_bytes(32, db->AP) <= 160 * 1024)) P.T = tu.strip;
