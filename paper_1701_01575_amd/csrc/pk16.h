@@ -150,6 +150,10 @@ __device__ __forceinline__ uint32_t column16_local_cs(const uint32_t (&sc)[T], u
         F = subw(max3h(F, hx, phi), e2);
         H[r] = h;
     }
+    // keep the E updates in this column's block, where they fill the gaps
+    // of the F chain, rather than sunk past the caller's end-cell branch
+#pragma unroll
+    for (int r = 0; r < T; r++) asm volatile("" : "+v"(E[r]));
     return cm;
 }
 
