@@ -650,6 +650,32 @@ int64_t tb_budget_bytes() {
     return b;
 }
 
+// Reorder idx by key(idx) descending, equal keys keeping their order (the
+// result of a stable sort).  Keys below 2^40 and fewer than 2^24 entries pack
+// (key, position) into one 64-bit word, so the sort compares plain integers;
+// otherwise (key, position) records are sorted.
+template <class Key>
+static void sort_desc_stable(std::vector<int64_t> &idx, Key key) {
+    const size_t n = idx.size();
+    uint64_t kmax = 0;
+    std::vector<uint64_t> keys(n);
+    for (size_t p = 0; p < n; p++) kmax = std::max(kmax, keys[p] = key(idx[p]));
+    if (kmax < ((uint64_t)1 << 40) && n < ((size_t)1 << 24)) {
+        std::vector<uint64_t> w(n);
+        for (size_t p = 0; p < n; p++) w[p] = (keys[p] << 24) | (uint64_t)(((size_t)1 << 24) - 1 - p);
+        std::sort(w.begin(), w.end(), std::greater<uint64_t>());
+        std::vector<int64_t> out(n);
+        for (size_t p = 0; p < n; p++) out[p] = idx[((size_t)1 << 24) - 1 - (size_t)(w[p] & 0xffffff)];
+        idx.swap(out);
+        return;
+    }
+    struct R { uint64_t k; int64_t pos, v; };
+    std::vector<R> rec(n);
+    for (size_t p = 0; p < n; p++) rec[p] = R{keys[p], (int64_t)p, idx[p]};
+    std::sort(rec.begin(), rec.end(), [](const R &a, const R &b) { return a.k != b.k ? a.k > b.k : a.pos < b.pos; });
+    for (size_t p = 0; p < n; p++) idx[p] = rec[p].v;
+}
+
 // Group and lay out a list of pairs.  n_results sizes the CIGAR regions (one
 // per result index, in result order); tb_cap caps the codes of one chunk.
 void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mode, int ends,
@@ -661,6 +687,8 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     P.plain = plain;
     auto is_wf = [&](const PairSpec &x) { return x.m >= route.rows && x.m * x.n >= route.cells; };
     std::vector<int64_t> order, worder;
+    order.reserve(sp.size());
+    worder.reserve(sp.size());
     for (int64_t k = 0; k < (int64_t)sp.size(); k++) {
         if (is_wf(sp[k])) worder.push_back(k); else order.push_back(k);
         if (plain) P.plain_seq.push_back({is_wf(sp[k]) ? 1 : 0,
@@ -669,11 +697,8 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     const int64_t n = (int64_t)order.size();
     auto strips = [&](int64_t k) { return (sp[k].m + kTP - 1) / kTP; };
     // batched: length-binned, longest first; plain: input order, one pair per group
-    if (!plain)
-        std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
-            if (strips(x) != strips(y)) return strips(x) > strips(y);
-            return sp[x].n > sp[y].n;
-        });
+    if (!plain)  // strips, then target length (both below 2^17)
+        sort_desc_stable(order, [&](int64_t k) { return ((uint64_t)strips(k) << 17) | (uint64_t)sp[k].n; });
     // CIGAR regions in result order: m + n + 1 runs each while capacity lasts
     std::vector<int64_t> need(std::max<int64_t>(n_results, 1), 0), roff(need.size(), 0), rcap(need.size(), 0);
     for (const auto &x : sp) need[x.res] = x.m + x.n + 1;
@@ -777,11 +802,12 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     // widths; codes chunked at wave boundaries.  Plain: one pair per wave, in
     // input order.  Pairs are stored in wave order; their slots follow the
     // groups'.
-    auto seg_of = [&](int64_t k) { return wf_seg(sp[k].m); };
-    if (!plain)
-        std::stable_sort(worder.begin(), worder.end(), [&](int64_t x, int64_t y) {
-            if (seg_of(x) != seg_of(y)) return seg_of(x) > seg_of(y);
-            return sp[x].m * sp[x].n > sp[y].m * sp[y].n;
+    std::vector<int> segk(sp.size(), 0);
+    for (int64_t k : worder) segk[k] = wf_seg(sp[k].m);
+    auto seg_of = [&](int64_t k) { return segk[k]; };
+    if (!plain)  // segment width, then cells (m, n < 2^16: cells < 2^32)
+        sort_desc_stable(worder, [&](int64_t k) {
+            return ((uint64_t)segk[k] << 33) | (uint64_t)(sp[k].m * sp[k].n);
         });
     struct WaveSpec {
         int64_t first = 0, count = 0;  // into worder
@@ -803,8 +829,17 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
         const int64_t passes = ((x.m + kTP - 1) / kTP + seg - 1) / seg;
         w.cost = std::max(w.cost, passes * (x.n + seg - 1));
     }
-    if (!plain)
-        std::stable_sort(wv.begin(), wv.end(), [](const WaveSpec &x, const WaveSpec &y) { return x.cost > y.cost; });
+    if (!plain) {
+        std::vector<int64_t> wi(wv.size());
+        for (size_t v = 0; v < wv.size(); v++) wi[v] = (int64_t)v;
+        sort_desc_stable(wi, [&](int64_t v) { return (uint64_t)wv[v].cost; });
+        std::vector<WaveSpec> sorted(wv.size());
+        for (size_t v = 0; v < wv.size(); v++) sorted[v] = wv[wi[v]];
+        wv.swap(sorted);
+    }
+    P.waves.reserve(P.waves.size() + wv.size());
+    P.wf.reserve(P.wf.size() + worder.size());
+    P.slots.reserve(P.slots.size() + worder.size());
     int64_t wchunk = 0;
     for (size_t v = 0; v < wv.size(); v++) {
         int64_t wave_words = 0;
@@ -871,11 +906,16 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     layout_pair_plan(P, caps_of(P), A);
 }
 
-int check_pair_range(const dsa_args *a, int64_t m, int64_t n) {
-    if (m > kMaxLen16 || n > kMaxLen16)
-        return fail(DSA_E_NOTSUP, "sequences longer than 65532 residues are not supported");
+int max_abs_score(const dsa_args *a) {
     int mx = 0;
     for (int k = 0; k < a->alphabet_size * a->alphabet_size; k++) mx = std::max(mx, std::abs((int)a->subst[k]));
+    return mx;
+}
+
+// mx: max_abs_score(a)
+int check_pair_range(const dsa_args *a, int mx, int64_t m, int64_t n) {
+    if (m > kMaxLen16 || n > kMaxLen16)
+        return fail(DSA_E_NOTSUP, "sequences longer than 65532 residues are not supported");
     const int64_t bound = (int64_t)mx * std::min(m, n) + 3LL * a->gap_open + (m + n + 64) * (int64_t)a->gap_extend;
     if (bound >= (1LL << 30)) return fail(DSA_E_RANGE, "scores could leave the int32 range");
     return DSA_OK;
@@ -890,13 +930,14 @@ int make_pair_plan(const dsa_args *a, const dsa_out *out, PairPlan &P) {
     if (a->top_k) return fail(DSA_E_INVAL, "top_k applies to database search only");
     const int ends = a->mode == DSA_SEMIGLOBAL ? (a->free_ends ? a->free_ends : (DSA_TB | DSA_TE)) : 0;
     std::vector<PairSpec> sp(n);
+    const int mx = max_abs_score(a);
     for (int64_t k = 0; k < n; k++) {
         sp[k].q_off = a->q_offsets[k];
         sp[k].t_off = a->t_offsets[k];
         sp[k].m = a->q_offsets[k + 1] - a->q_offsets[k];
         sp[k].n = a->t_offsets[k + 1] - a->t_offsets[k];
         sp[k].res = (int32_t)k;
-        const int rc = check_pair_range(a, sp[k].m, sp[k].n);
+        const int rc = check_pair_range(a, mx, sp[k].m, sp[k].n);
         if (rc) return rc;
     }
     const bool tb = (a->flags & DSA_TRACEBACK) != 0;
@@ -1094,6 +1135,8 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     if (P.K > 0 && P.traceback) {
         // worst case for the hits: K per query, each as long as the longest target
         std::vector<PairSpec> sp;
+        sp.reserve(nq * P.K);
+        const int mx = max_abs_score(a);
         for (int64_t q = 0; q < nq; q++)
             for (int k = 0; k < P.K; k++) {
                 PairSpec x;
@@ -1102,7 +1145,7 @@ int make_search_plan(const dsa_args *a, Plan &P) {
                 x.n = db->max_len;
                 x.res = (int32_t)(q * P.K + k);
                 sp.push_back(x);
-                const int rc = check_pair_range(a, x.m, x.n);
+                const int rc = check_pair_range(a, mx, x.m, x.n);
                 if (rc) return rc;
             }
         // bound each region by the plan with every pair in that kind; a hit
