@@ -295,3 +295,28 @@ def test_search_local_gap_penalties(o, e, int32, budget, blosum, monkeypatch):
     exp = oracle.search(Q, T, blosum, o, e, mode="local")
     compare_search(got, exp, len(Q), len(T), label=f"gaps {o}/{e}")
     assert bool((got["status"] & 1).all()) == int32
+
+
+@pytest.mark.parametrize("seed", range(7))
+@pytest.mark.parametrize("budget", [None, "1"], ids=["inter", "wavefront"])
+def test_search_local_random_scoring(seed, budget, monkeypatch):
+    """Random alphabets (4 to 24 letters), random matrices that reach the
+    int8 extremes (-128, +127) and random gap penalties within the offset
+    int16 range, so that profile entries s + e span their whole range; both
+    unit kinds, bit-exact against the oracle."""
+    if budget:
+        monkeypatch.setenv("DSA_INTRA_BUDGET", budget)
+    rng = np.random.default_rng([170101575, 59, seed])
+    A = int(rng.integers(4, 25))
+    S = rng.integers(-12, 9, size=(A, A)).astype(np.int8)
+    S[rng.integers(0, A), rng.integers(0, A)] = 127
+    S[rng.integers(0, A), rng.integers(0, A)] = -128
+    e = [0, 1, 2, 4, 5, 17, 256][seed]
+    o = int(rng.integers(e, min(1024, e + 60) + 1))
+    T = SeqSet.from_list([rng.integers(0, A, size=int(L)).astype(np.uint8)
+                          for L in list(rng.integers(0, 500, size=150)) + [1200]])
+    Q = SeqSet.from_list([rng.integers(0, A, size=int(L)).astype(np.uint8) for L in (1, 37, 260, 1100)])
+    log(f"random scoring seed={seed} A={A} o={o} e={e} budget={budget}")
+    got, _ = gpu_search(Q, T, S, o, e, "local")
+    exp = oracle.search(Q, T, S, o, e, mode="local")
+    compare_search(got, exp, len(Q), len(T), label=f"random {seed}")
