@@ -14,7 +14,7 @@ timed too.  GCUPS counts the full m x n rectangle of every (query, target)
 pair.
 
 Prints one JSON line (rank 0).  `--gpus N` with N > 1 exits with a message:
-this build runs on one GPU.
+the library runs on one GPU (it has no multi-GPU path).
 """
 from __future__ import annotations
 
@@ -270,7 +270,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); "
+        print("bench.py: the library runs on one GPU only (no multi-GPU path); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

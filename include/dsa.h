@@ -67,7 +67,7 @@ typedef enum {
     DSA_E_WORKSPACE = 3,  /* workspace smaller than dsa_workspace_size */
     DSA_E_CAPACITY = 4,   /* CIGAR buffer too small (results still valid) */
     DSA_E_DEVICE = 5,     /* a HIP call failed; see dsa_last_error */
-    DSA_E_NOTSUP = 6      /* combination not supported by this build */
+    DSA_E_NOTSUP = 6      /* combination not supported by the library */
 } dsa_status;
 
 enum { DSA_LOCAL = 0, DSA_GLOBAL = 1, DSA_SEMIGLOBAL = 2 };
