@@ -101,3 +101,35 @@ def test_topk_free_query_end_traceback(blosum):
     for k in range(len(qi)):
         assert (got["cigars"][k] == exp["cigars"][k]).all(), k
 
+
+
+def test_cfg5_full_size_topk_sampled(blosum):
+    """Top-10 with traceback against the full 500,000-target serving database
+    (the benchmark's serving configuration), checked by properties that hold
+    at any size: every hit is recomputed by the oracle (score, ends, begins,
+    CIGAR), and no sampled non-hit beats the tenth hit under the (score
+    descending, index ascending) order."""
+    c = gen.cfg5_db()
+    T = c["targets"]
+    rng = np.random.default_rng([170101575, 61])
+    Q = SeqSet.from_list([gen.background_residues(rng, L) for L in (60, 400, 1500)])
+    K = 10
+    log("cfg5 full size: 3 queries x 500,000 targets, top-10 with traceback")
+    got = run_topk(Q, T, blosum, 11, 1, K, "local", traceback=True)
+    nq, nt = len(Q), len(T)
+    hits = got["t_index"].reshape(nq, K)
+    assert (hits >= 0).all()
+    qi = np.repeat(np.arange(nq), K)
+    exp = oracle.align_index(qi, hits.reshape(-1), Q, T, blosum, 11, 1, mode="local", traceback=True)
+    for f in ("score", "q_end", "t_end", "q_begin", "t_begin"):
+        assert (got[f] == exp[f]).all(), f
+    for oi in range(nq * K):
+        assert (got["cigars"][oi] == exp["cigars"][oi]).all(), oi
+    sc = got["score"].reshape(nq, K)
+    for q in range(nq):
+        assert (np.diff(sc[q]) <= 0).all()
+        others = np.setdiff1d(rng.integers(0, nt, size=3000), hits[q])
+        o = oracle.align_index(np.full(len(others), q), others, Q, T, blosum, 11, 1, mode="local")
+        worst, worst_t = int(sc[q, -1]), int(hits[q, -1])
+        assert (o["score"] <= worst).all()
+        assert not ((o["score"] == worst) & (others < worst_t)).any()
