@@ -981,7 +981,14 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     P.budget = P.persistent ? 128000 : 8000;
     const Tuning tu = tuning_for(search_key(a, db->n_residues));
     if (tu.strip == 16 || (tu.strip == 32 && search16_lds_bytes(32, db->AP) <= 160 * 1024)) P.T = tu.strip;
-    if (tu.waves >= 1 && tu.waves <= 8) P.wpb16 = tu.waves;
+    if (tu.waves >= 1 && tu.waves <= 8) {
+        P.wpb16 = tu.waves;
+    } else if (P.persistent) {
+        // a small search (few queries x groups) gets fewer waves per block,
+        // so that its units still spread over every CU
+        const int64_t work = std::max<int64_t>(1, a->n_q) * std::max<int64_t>(1, db->n_groups);
+        while (P.wpb16 > 1 && (work + P.wpb16 - 1) / P.wpb16 < 2LL * device_cus(db->device)) P.wpb16 /= 2;
+    }
     if (tu.intra_budget >= 0) P.budget = tu.intra_budget;
     P.lds16 = search16_lds_bytes(P.T, db->AP);
     P.lds32 = search32_lds_bytes(db->AP);
