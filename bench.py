@@ -412,7 +412,8 @@ def main():
                 "unit": "TOP/s (packed int16 VALU ops)", "frac": round(achieved / PEAK_INT16_TOPS, 4),
                 "traffic": traffic,
                 "kernel": "search phase, one graph replay: one persistent k_search16 launch over a "
-                          "longest-first work list of inter-sequence and wavefront units, plus the "
+                          "longest-first work list of inter-sequence, strip-pipelined and wavefront "
+                          "units, plus the "
                           "profile, flag and int32-rerun launches",
                 "duration_ms": round(replay_avg, 3), "timing": "HIP events around each replay on its stream",
                 "eager_kernels": per_kernel, "eager_span_ms": round(span_ms, 3),

@@ -210,9 +210,10 @@ int dsa_graph_destroy(dsa_graph *graph);
 
 /*
  * Autotuning of launch choices that never change results: the strip height
- * (16 or 32 rows) and waves per block of the inter-sequence kernel and the
- * cell budget above which a target group goes to the wavefront kernel
- * (database search), or the query rows and cells above which a pair goes
+ * (16 or 32 rows) and waves per block of the inter-sequence kernel, the
+ * cell budget above which a target group goes to the wavefront kernel and,
+ * for local searches, the budget up to which such a group is instead one
+ * strip-pipelined unit (database search), or the query rows and cells above which a pair goes
  * to the wavefront pairwise kernel (pairwise).  Choices are kept per shape
  * class: kind, mode, form (plain or batched), traceback, top-K, alphabet and
  * power-of-two buckets of the query residues and database residues (search)
@@ -223,20 +224,23 @@ int dsa_graph_destroy(dsa_graph *graph);
  * arguments (blocking; it allocates its own workspace and outputs, so
  * args->workspace is not used), keeps the fastest for the class in the
  * process, merges it into the JSON file cache_path when that is not NULL,
- * and returns it in *chosen (NULL allowed).  Later calls of the class,
+ * and returns in *chosen (NULL allowed) the values calls of the class now
+ * use, as dsa_tuning_get does.  Later calls of the class,
  * dsa_workspace_size included, use it: the caller sizes the workspace after
  * tuning.  A file named by the environment variable DSA_AUTOTUNE_CACHE is
  * read once, at the first call that plans.  Environment variables DSA_STRIP,
- * DSA_WAVES, DSA_INTRA_BUDGET, DSA_PAIR_WF_ROWS and DSA_PAIR_WF_CELLS
- * override the table.
+ * DSA_WAVES, DSA_INTRA_BUDGET, DSA_KS_BUDGET, DSA_PAIR_WF_ROWS and
+ * DSA_PAIR_WF_CELLS override the table.
  * dsa_tuning_get returns the values a call with these arguments would use
- * now (search: strip, waves, intra_budget; pairwise: pair_rows, pair_cells;
+ * now (search: strip, waves, intra_budget, ks_budget; pairwise: pair_rows, pair_cells;
  * the others -1), with ms = the tuned time (0 if untuned).
  */
 typedef struct {
     int32_t strip;           /* rows per strip of the inter-sequence kernel */
     int32_t waves;           /* waves per block of the inter-sequence kernel */
     int64_t intra_budget;    /* strips x columns above which a group goes to the wavefront kernel */
+    int64_t ks_budget;       /* such a group of a local search is one strip-pipelined unit when
+                                ceil(strips / waves) x columns <= ks_budget (0 = never) */
     int64_t pair_rows;       /* pairwise: wavefront iff query rows >= pair_rows ... */
     int64_t pair_cells;      /* ... and rows x columns >= pair_cells */
     double ms;               /* time of the chosen candidate when tuned */

@@ -169,6 +169,7 @@ class dsa_tuning(ctypes.Structure):
         ("strip", ctypes.c_int32),
         ("waves", ctypes.c_int32),
         ("intra_budget", ctypes.c_int64),
+        ("ks_budget", ctypes.c_int64),
         ("pair_rows", ctypes.c_int64),
         ("pair_cells", ctypes.c_int64),
         ("ms", ctypes.c_double),

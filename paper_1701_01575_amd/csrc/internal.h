@@ -11,6 +11,7 @@ constexpr int kPadLen = 4;           // group column count is a multiple of this
 constexpr int kMaxAlphabet = 32;
 constexpr int kMaxLen16 = 65532;     // int16 kernels index rows/columns with uint16
 constexpr int kT32 = 16;             // strip height of the int32 kernels
+constexpr int32_t kKsBase = 1 << 29;  // work-list code of strip-pipelined units
 // Local-mode int16 search holds H, E and F as value + an offset of at least
 // kBias16: every value is then a positive normal binary16 bit pattern, whose
 // binary16 order is its integer order, so one packed binary16 three-way
@@ -77,7 +78,9 @@ struct SearchArgs {
     const int32_t *qflag;         // per query: int16 bound fails (global / semi-global)
     int32_t *counter;             // persistent-grid work counter
     // persistent form with wavefront units: the work list, longest first;
-    // entry v >= 0 is inter-sequence unit v, v < 0 is wavefront unit -v - 1
+    // entry v in [0, kKsBase) is inter-sequence unit v, v >= kKsBase is
+    // strip-pipelined unit v - kKsBase (an entry of units, one group), v < 0
+    // is wavefront unit -v - 1
     const int32_t *order;
     int32_t n_order;
 };
@@ -125,6 +128,15 @@ constexpr int kTI = 16;           // rows per lane in the wavefront kernel
 constexpr int kIntraWaves = 4;    // waves (pairs) per block
 hipError_t launch_intra16(const IntraArgs &a, int mode, int n_blocks, size_t lds, hipStream_t s);
 size_t intra16_lds_bytes(int AP, int A);
+
+// Strip-pipelined unit (persistent local int16 search): LDS bytes with W
+// waves and AP letters.
+constexpr int kKsRowPad = 16;     // int16 of padding per letter row (bank shift)
+__host__ __device__ constexpr size_t ks16_lds_bytes(int W, int AP) {
+    return (size_t)2 * AP * (16 * W + kKsRowPad) * 2      // two round profiles, int16
+           + (size_t)(W - 1) * 2 * 4 * kWave * 8           // hand-over ring, uint2
+           + (size_t)AP * AP * 2 + 16;                      // pair code -> two letters
+}
 
 // Pairwise alignment (query k against target k): one pair per lane, pairs
 // sorted by (strips, target length) into groups of 64 so a wave's lanes share

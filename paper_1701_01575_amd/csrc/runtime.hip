@@ -359,6 +359,7 @@ struct Tuning {
     int32_t strip = 0;           // 16 or 32 rows per strip of the inter-sequence kernel
     int32_t waves = 0;           // waves per block of the inter-sequence kernel (1..8)
     int64_t intra_budget = -1;   // strips x columns above which a group goes to the wavefront kernel
+    int64_t ks_budget = -1;      // rounds x columns up to which such a group is one strip-pipelined unit
     int64_t pair_rows = -1;      // pairwise: wavefront iff m >= pair_rows ...
     int64_t pair_cells = -1;     // ... and m * n >= pair_cells
     double ms = 0.0;             // time of the chosen candidate when it was tuned
@@ -439,6 +440,7 @@ void load_cache_file(const char *path, std::map<std::string, Tuning> *into) {
         if (json_num(obj, "strip", &v)) t.strip = (int32_t)v;
         if (json_num(obj, "waves", &v)) t.waves = (int32_t)v;
         if (json_num(obj, "intra_budget", &v)) t.intra_budget = (int64_t)v;
+        if (json_num(obj, "ks_budget", &v)) t.ks_budget = (int64_t)v;
         if (json_num(obj, "pair_rows", &v)) t.pair_rows = (int64_t)v;
         if (json_num(obj, "pair_cells", &v)) t.pair_cells = (int64_t)v;
         if (json_num(obj, "ms", &v)) t.ms = v;
@@ -456,9 +458,9 @@ bool save_cache_file(const char *path, const std::map<std::string, Tuning> &entr
         const Tuning &t = e.second;
         fprintf(f,
                 "  {\"key\": \"%s\", \"strip\": %d, \"waves\": %d, \"intra_budget\": %lld, "
-                "\"pair_rows\": %lld, \"pair_cells\": %lld, \"ms\": %.4f}%s\n",
-                e.first.c_str(), t.strip, t.waves, (long long)t.intra_budget, (long long)t.pair_rows,
-                (long long)t.pair_cells, t.ms, (++k < entries.size()) ? "," : "");
+                "\"ks_budget\": %lld, \"pair_rows\": %lld, \"pair_cells\": %lld, \"ms\": %.4f}%s\n",
+                e.first.c_str(), t.strip, t.waves, (long long)t.intra_budget, (long long)t.ks_budget,
+                (long long)t.pair_rows, (long long)t.pair_cells, t.ms, (++k < entries.size()) ? "," : "");
     }
     fprintf(f, "]\n");
     const bool ok = fclose(f) == 0;
@@ -484,6 +486,7 @@ Tuning tuning_for(const std::string &key) {
     if (const char *v = getenv("DSA_STRIP")) t.strip = atoi(v);
     if (const char *v = getenv("DSA_WAVES")) t.waves = atoi(v);
     if (const char *v = getenv("DSA_INTRA_BUDGET")) t.intra_budget = atoll(v);
+    if (const char *v = getenv("DSA_KS_BUDGET")) t.ks_budget = atoll(v);
     if (const char *v = getenv("DSA_PAIR_WF_ROWS")) t.pair_rows = atoll(v);
     if (const char *v = getenv("DSA_PAIR_WF_CELLS")) t.pair_cells = atoll(v);
     return t;
@@ -530,6 +533,7 @@ struct Plan {
     bool mixed = false;             // persistent form with wavefront units in one kernel
     size_t ldsM = 0, off_order = 0;
     int64_t budget = 64000;         // strips x columns above which a group goes to the wavefront kernel
+    int64_t ks_budget = 0;          // rounds x columns up to which such a group is one strip-pipelined unit
     size_t ldsI = 0;
     std::vector<QueryInfo> qinfo;
     std::vector<int32_t> empty_rows;
@@ -989,7 +993,19 @@ int make_search_plan(const dsa_args *a, Plan &P) {
         const int64_t work = std::max<int64_t>(1, a->n_q) * std::max<int64_t>(1, db->n_groups);
         while (P.wpb16 > 1 && (work + P.wpb16 - 1) / P.wpb16 < 2LL * device_cus(db->device)) P.wpb16 /= 2;
     }
+    // strip-pipelined units: local int16 persistent searches with 16-row
+    // strips and at least two waves per block.  They take the long groups
+    // of long queries at about the inter-sequence kernel's cost per cell, so
+    // the cutover moves down and the long inter-sequence units that bound
+    // the makespan get shorter.
+    const bool ks_ok = P.persistent && !P.force32 && P.mode == DSA_LOCAL && P.T == 16 && P.wpb16 >= 2;
+    if (ks_ok) {
+        P.budget = 112000;
+        P.ks_budget = 32000;
+    }
     if (tu.intra_budget >= 0) P.budget = tu.intra_budget;
+    if (tu.ks_budget >= 0) P.ks_budget = tu.ks_budget;
+    if (!ks_ok) P.ks_budget = 0;
     P.lds16 = search16_lds_bytes(P.T, db->AP);
     P.lds32 = search32_lds_bytes(db->AP);
     if (P.lds16 > 160 * 1024) return fail(DSA_E_NOTSUP, "alphabet too large for the LDS profile");
@@ -998,6 +1014,7 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     P.qinfo.resize(nq);
     P.ldsI = intra16_lds_bytes(db->AP, A);
     P.ldsM = std::max(P.lds16, P.ldsI);
+    if (ks_ok) P.ldsM = std::max(P.ldsM, ks16_lds_bytes(P.wpb16, db->AP));
     for (int64_t q = 0; q < nq; q++) {
         const int64_t m = a->q_offsets[q + 1] - a->q_offsets[q];
         if (m > kMaxLen16) return fail(DSA_E_NOTSUP, "queries longer than 65532 residues are not supported");
@@ -1025,6 +1042,7 @@ int make_search_plan(const dsa_args *a, Plan &P) {
         const int64_t q1 = std::min(nq, q0 + QS);
         std::vector<SearchUnit> inter, rerun;
         std::vector<IntraUnit> iu;
+        std::vector<int32_t> ks;  // strip-pipelined units: indices into rerun
         for (int64_t q = q0; q < q1; q++) {
             if (P.qinfo[q].len == 0) continue;
             // groups from gc on go to the wavefront kernel: their inter-sequence
@@ -1049,6 +1067,14 @@ int make_search_plan(const dsa_args *a, Plan &P) {
                 R.qslot = qslot;
                 const int32_t ridx = (int32_t)rerun.size();
                 rerun.push_back(R);
+                // a group whose strips, shared out over the block's waves,
+                // stay within the budget is one strip-pipelined unit (its
+                // pipeline needs more 4-column blocks than waves)
+                const int64_t rounds_ks = (P.qinfo[q].strips + wpb - 1) / wpb;
+                if (ks_ok && (db->grp[g].ncols >> 2) > wpb && rounds_ks * db->grp[g].ncols <= P.ks_budget) {
+                    ks.push_back(ridx);
+                    continue;
+                }
                 const int64_t pbase = (g - db->long_group0) * (kGroup / 2);
                 // the persistent kernel runs a wavefront unit with all its waves
                 const int per_unit = P.persistent ? wpb : kIntraWaves;
@@ -1093,7 +1119,7 @@ int make_search_plan(const dsa_args *a, Plan &P) {
             I.runit += (int32_t)(R.first + R.inter);
             P.iunits.push_back(I);
         }
-        if (P.persistent && !P.force32 && !iu.empty()) {
+        if (P.persistent && !P.force32 && (!iu.empty() || !ks.empty())) {
             // one work list, longest first.  Cost in lane row-columns: an
             // inter-sequence unit walks its rows over the widest group's
             // columns; a wavefront unit sweeps (columns + 63) steps of 16 rows
@@ -1109,6 +1135,15 @@ int make_search_plan(const dsa_args *a, Plan &P) {
                 const int64_t passes = (strips16 + kWave - 1) / kWave;
                 const double c = 1.15 * passes * (db->pairs[I.lp0 + I.np - 1].ncols + kWave - 1) * kTI;
                 w.push_back({c, -(int32_t)(R.ifirst + k) - 1});
+            }
+            // a strip-pipelined unit: one 4-column block of 16 rows per
+            // wave and barrier step, rounds x columns / 4 steps plus the
+            // pipeline fill
+            for (int32_t r : ks) {
+                const SearchUnit &U = rerun[r];
+                const int64_t rounds_ks = (P.qinfo[U.q].strips + wpb - 1) / wpb;
+                const double c = 1.1 * (rounds_ks * db->grp[U.g0].ncols + 4.0 * (wpb - 1)) * kTI;
+                w.push_back({c, kKsBase + (int32_t)(R.inter + r)});
             }
             std::stable_sort(w.begin(), w.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
             R.ofirst = (int64_t)P.order.size();
@@ -1905,6 +1940,7 @@ static void to_public(const Tuning &t, dsa_tuning *o) {
     o->strip = t.strip;
     o->waves = t.waves;
     o->intra_budget = t.intra_budget;
+    o->ks_budget = t.ks_budget;
     o->pair_rows = t.pair_rows;
     o->pair_cells = t.pair_cells;
     o->ms = t.ms;
@@ -1932,6 +1968,7 @@ extern "C" int dsa_tuning_get(const dsa_args *args, dsa_tuning *out) {
         t.strip = P.T;
         t.waves = P.wpb16;
         t.intra_budget = P.budget;
+        t.ks_budget = P.ks_budget;
         t.ms = tuning_for(search_key(args, args->db->n_residues)).ms;
     } else {
         if (!args->t_codes || !args->t_offsets) return fail(DSA_E_INVAL, "pairwise needs t_codes and t_offsets");
@@ -1967,7 +2004,7 @@ extern "C" int dsa_autotune(const dsa_args *args, const char *cache_path, dsa_tu
     if (search) {
         const int64_t none = (int64_t)1 << 60;  // no wavefront kernel
         const std::vector<int64_t> budgets = plain ? std::vector<int64_t>{4000, 8000, 16000, 32000, 64000, none}
-                                                   : std::vector<int64_t>{16000, 32000, 64000, 128000, 256000, none};
+                                                   : std::vector<int64_t>{16000, 32000, 64000, 96000, 112000, 128000, 256000, none};
         for (int strip : {32, 16})
             for (int64_t b : budgets) {
                 Tuning t;
@@ -1990,6 +2027,12 @@ extern "C" int dsa_autotune(const dsa_args *args, const char *cache_path, dsa_tu
         std::vector<Tuning> v;
         if (search) {
             for (int w : {2, 4}) { Tuning t = b; t.waves = w; v.push_back(t); }
+            if (args->mode == DSA_LOCAL && !plain && b.strip == 16)
+                for (int64_t k : {(int64_t)0, (int64_t)16000, (int64_t)64000}) {
+                    Tuning t = b;
+                    t.ks_budget = k;
+                    v.push_back(t);
+                }
         } else {
             for (int64_t c : {(int64_t)0, (int64_t)8192, (int64_t)131072, (int64_t)524288}) {
                 Tuning t = b; t.pair_cells = c; v.push_back(t);
@@ -2114,7 +2157,8 @@ extern "C" int dsa_autotune(const dsa_args *args, const char *cache_path, dsa_tu
                 return fail(DSA_E_INVAL, std::string("autotune: cannot write ") + cache_path);
         }
     }
-    if (chosen) to_public(best, chosen);
+    // report the values calls of the class now use (defaults filled in)
+    if (chosen) return dsa_tuning_get(args, chosen);
     return DSA_OK;
 }
 

@@ -33,6 +33,7 @@
 
 #include "internal.h"
 #include "intra_unit.h"
+#include "ks_unit.h"
 #include "pk16.h"
 
 namespace dsa {
@@ -123,6 +124,11 @@ k_search16(SearchArgs P, IntraArgs W) {
                 const int v = P.order[u];
                 if (v < 0) {  // a wavefront unit: the whole block takes it
                     intra16_unit<MODE>(W, W.units[-v - 1], lds4);
+                    __syncthreads();
+                    continue;
+                }
+                if (v >= kKsBase) {  // a strip-pipelined unit: the whole block takes it
+                    if (MODE == LOCAL && T == 16) ks16_unit(P, P.units[v - kKsBase], v - kKsBase, lds4);
                     __syncthreads();
                     continue;
                 }

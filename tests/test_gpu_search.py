@@ -147,19 +147,29 @@ def test_cfg2_full_size_sampled():
 
 
 INTRA_QLENS = [1, 15, 16, 17, 100, 700, 1023, 1024, 1025, 2100]
+ROUTES = [None, "wavefront", "pipelined"]
+
+
+def _route(monkeypatch, route):
+    """Send every group at least 128 columns wide (the long groups) to the
+    wavefront units, or to the strip-pipelined units (local mode, 16-row
+    strips, persistent form; elsewhere the wavefront units take them)."""
+    if route is not None:
+        monkeypatch.setenv("DSA_INTRA_BUDGET", "1")
+        monkeypatch.setenv("DSA_KS_BUDGET", "0" if route == "wavefront" else str(1 << 40))
 
 
 @pytest.mark.parametrize("mode,ends", CASES)
-@pytest.mark.parametrize("budget", ["1", None], ids=["all-long-groups-wavefront", "default-routing"])
-def test_search_wavefront_long_targets(mode, ends, budget, blosum, monkeypatch):
+@pytest.mark.parametrize("route", ROUTES, ids=["default-routing", "wavefront", "pipelined"])
+def test_search_wavefront_long_targets(mode, ends, route, blosum, monkeypatch):
     """Long targets of long queries go through the wavefront kernel (lanes =
-    16-row strips, up to three 1024-row passes); the routing budget 1 sends
+    16-row strips, up to three 1024-row passes) or the strip-pipelined units
+    (a block's waves share a query's strips); the routing budget 1 sends
     every group wider than 128 columns there."""
-    if budget is not None:
-        monkeypatch.setenv("DSA_INTRA_BUDGET", budget)
+    _route(monkeypatch, route)
     T = _targets(5, 260, 1500, extra=[1, 2, 1501, 1777, 2001])
     Q = _queries(6, INTRA_QLENS)
-    log(f"wavefront mode={mode} ends={ends} budget={budget}")
+    log(f"wavefront mode={mode} ends={ends} route={route}")
     for plain in (False, True):
         got, _ = gpu_search(Q, T, blosum, 11, 1, mode, ends, plain=plain)
         exp = oracle.search(Q, T, blosum, 11, 1, mode=mode, ends=ends)
@@ -180,6 +190,23 @@ def test_search_wavefront_launch_shapes(strip, waves, blosum, monkeypatch):
         got, _ = gpu_search(Q, T, blosum, 11, 1, mode, ends)
         exp = oracle.search(Q, T, blosum, 11, 1, mode=mode, ends=ends)
         compare_search(got, exp, len(Q), len(T), label=f"shapes {strip}/{waves}/{mode}")
+
+
+@pytest.mark.parametrize("waves", ["8", "4", "3", "2"])
+def test_search_strip_pipelined_block_sizes(waves, blosum, monkeypatch):
+    """Strip-pipelined units with 8, 4, 3 and 2 waves per block: queries of
+    fewer strips than waves (idle waves), of a ragged last round, and of many
+    rounds (the last wave hands its strip to the first wave's next one
+    through the boundary row), against groups from 128 columns up."""
+    monkeypatch.setenv("DSA_STRIP", "16")
+    monkeypatch.setenv("DSA_WAVES", waves)
+    _route(monkeypatch, "pipelined")
+    T = _targets(13, 300, 1500, extra=[1, 2, 128, 1501, 1777, 2001])
+    Q = _queries(14, INTRA_QLENS + [33, 48, 49, 129, 4000])
+    log(f"strip-pipelined waves={waves}")
+    got, _ = gpu_search(Q, T, blosum, 11, 1, "local")
+    exp = oracle.search(Q, T, blosum, 11, 1, mode="local")
+    compare_search(got, exp, len(Q), len(T), label=f"pipelined {waves}")
 
 
 @pytest.mark.parametrize("mode,ends", CASES[:3])
@@ -215,8 +242,9 @@ def test_search_longest_targets(mode, ends, blosum):
     compare_search(got, exp, len(Q), len(T), label=f"longest {mode}")
 
 
-def test_search_wavefront_overflow_rerun(blosum, monkeypatch):
-    monkeypatch.setenv("DSA_INTRA_BUDGET", "1")
+@pytest.mark.parametrize("route", ROUTES[1:])
+def test_search_wavefront_overflow_rerun(route, blosum, monkeypatch):
+    _route(monkeypatch, route)
     S = (blosum.astype(np.int32) * 5).clip(-128, 127).astype(np.int8)
     rng = np.random.default_rng([170101575, 55])
     base = gen.background_residues(rng, 1600)
@@ -244,14 +272,13 @@ def test_search_rounds_of_one_query(mode, ends, blosum, monkeypatch):
 LOCAL16_MAX = 28544  # highest local score the offset int16 pass computes exactly
 
 
-@pytest.mark.parametrize("budget", [None, "1"], ids=["inter", "wavefront"])
-def test_search_local_exact_range_edge(budget, blosum, monkeypatch):
+@pytest.mark.parametrize("route", ROUTES, ids=["inter", "wavefront", "pipelined"])
+def test_search_local_exact_range_edge(route, blosum, monkeypatch):
     """Scores on both sides of the offset int16 range's top: those at or
     below it come from the int16 pass, those above (still below 32767, where
     the packed values would not saturate) must come from the int32 rerun.
     Self-similar prefixes under a x5 matrix place scores around the edge."""
-    if budget:
-        monkeypatch.setenv("DSA_INTRA_BUDGET", budget)
+    _route(monkeypatch, route)
     S = (blosum.astype(np.int32) * 5).clip(-128, 127).astype(np.int8)
     rng = np.random.default_rng([170101575, 57])
     base = gen.background_residues(rng, 1400)
@@ -261,7 +288,7 @@ def test_search_local_exact_range_edge(budget, blosum, monkeypatch):
     seqs = [base[:k] for k in picks] + [gen.background_residues(rng, 400) for _ in range(30)]
     T = SeqSet.from_list(seqs)
     Q = SeqSet.from_list([base, base[:1000]])
-    log(f"local exact-range edge budget={budget}")
+    log(f"local exact-range edge route={route}")
     got, _ = gpu_search(Q, T, S, 40, 4, "local")
     exp = oracle.search(Q, T, S, 40, 4, mode="local")
     compare_search(got, exp, len(Q), len(T), label="local edge")
@@ -272,11 +299,11 @@ def test_search_local_exact_range_edge(budget, blosum, monkeypatch):
     assert (got["status"][above] & 1).all()
 
 
-@pytest.mark.parametrize("budget", [None, "1"], ids=["inter", "wavefront"])
+@pytest.mark.parametrize("route", ROUTES, ids=["inter", "wavefront", "pipelined"])
 @pytest.mark.parametrize("o,e,int32", [(1500, 1100, True), (1000, 300, True), (1024, 256, False),
                                        (900, 0, False), (60, 60, False), (7, 3, False), (11, 1, False),
                                        (6, 4, False), (9, 5, False)])
-def test_search_local_gap_penalties(o, e, int32, budget, blosum, monkeypatch):
+def test_search_local_gap_penalties(o, e, int32, route, blosum, monkeypatch):
     """Gap penalties at and beyond the offset int16 range (gap_open <= 1024,
     gap_extend <= 256): beyond it a local search runs the exact int32 kernel;
     at its edge, with no extension cost and with open = extend, the int16
@@ -285,8 +312,7 @@ def test_search_local_gap_penalties(o, e, int32, budget, blosum, monkeypatch):
     wavefront units (which use the frame up to gap_extend 4) every R
     columns, R the largest power of two with R * e <= 1024; targets reach
     1,500 residues so that this happens several times."""
-    if budget:
-        monkeypatch.setenv("DSA_INTRA_BUDGET", budget)
+    _route(monkeypatch, route)
     rng = np.random.default_rng([170101575, 58])
     lens = list(rng.integers(0, 400, size=90)) + [1100, 1500]
     T = SeqSet.from_list([gen.background_residues(rng, int(L)) for L in lens])
@@ -298,14 +324,13 @@ def test_search_local_gap_penalties(o, e, int32, budget, blosum, monkeypatch):
 
 
 @pytest.mark.parametrize("seed", range(7))
-@pytest.mark.parametrize("budget", [None, "1"], ids=["inter", "wavefront"])
-def test_search_local_random_scoring(seed, budget, monkeypatch):
+@pytest.mark.parametrize("route", ROUTES, ids=["inter", "wavefront", "pipelined"])
+def test_search_local_random_scoring(seed, route, monkeypatch):
     """Random alphabets (4 to 24 letters), random matrices that reach the
     int8 extremes (-128, +127) and random gap penalties within the offset
     int16 range, so that profile entries s + e span their whole range; both
-    unit kinds, bit-exact against the oracle."""
-    if budget:
-        monkeypatch.setenv("DSA_INTRA_BUDGET", budget)
+    unit kinds and routes, bit-exact against the oracle."""
+    _route(monkeypatch, route)
     rng = np.random.default_rng([170101575, 59, seed])
     A = int(rng.integers(4, 25))
     S = rng.integers(-12, 9, size=(A, A)).astype(np.int8)
@@ -316,7 +341,7 @@ def test_search_local_random_scoring(seed, budget, monkeypatch):
     T = SeqSet.from_list([rng.integers(0, A, size=int(L)).astype(np.uint8)
                           for L in list(rng.integers(0, 500, size=150)) + [1200]])
     Q = SeqSet.from_list([rng.integers(0, A, size=int(L)).astype(np.uint8) for L in (1, 37, 260, 1100)])
-    log(f"random scoring seed={seed} A={A} o={o} e={e} budget={budget}")
+    log(f"random scoring seed={seed} A={A} o={o} e={e} route={route}")
     got, _ = gpu_search(Q, T, S, o, e, "local")
     exp = oracle.search(Q, T, S, o, e, mode="local")
     compare_search(got, exp, len(Q), len(T), label=f"random {seed}")

@@ -30,7 +30,9 @@ def test_autotune_search(plain, blosum, tmp_path):
     ch = dsa.autotune(Q, db=db, matrix=blosum, plain=plain, cache_path=path)
     assert ch["strip"] in (16, 32) and ch["waves"] in (2, 4, 8) and ch["ms"] > 0
     now = dsa.tuning(Q, db=db, matrix=blosum, plain=plain)
-    assert (now["strip"], now["waves"], now["intra_budget"]) == (ch["strip"], ch["waves"], ch["intra_budget"])
+    assert (now["strip"], now["waves"], now["intra_budget"], now["ks_budget"]) == \
+        (ch["strip"], ch["waves"], ch["intra_budget"], ch["ks_budget"])
+    assert ch["ks_budget"] >= 0 and (ch["ks_budget"] == 0 or (not plain and ch["strip"] == 16))
     after = _host(dsa.align(Q, db=db, matrix=blosum, plain=plain))
     torch.cuda.synchronize()
     for k in before:
