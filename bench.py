@@ -40,7 +40,7 @@ def log(msg):
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ["search.hip", "intra_unit.h", "pk16.h", "internal.h"]:
+    for f in ["search.hip", "intra_unit.h", "ks_unit.h", "pk16.h", "internal.h"]:
         h.update(open(os.path.join(ROOT, "paper_1701_01575_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
