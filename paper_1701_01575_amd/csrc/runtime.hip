@@ -1034,23 +1034,48 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     // n_q.  The plain form uses rounds of one query and one launch per pass.
     const int wpb = P.wpb16;
     const int64_t slot_bytes = db->bnd_slot_uint2 * 8 + std::max<int64_t>(db->long_bnd_slot, 1) * 8;
-    int64_t cap_bytes = (int64_t)8 << 30;
+    // a sixteenth of the device's memory, at most 16 GiB: on a large
+    // database a round of only a few queries leaves a long launch tail
+    int64_t cap_bytes = (int64_t)16 << 30;
+    {
+        size_t total = 0;
+        if (hipDeviceTotalMem(&total, db->device) == hipSuccess && total > 0)
+            cap_bytes = std::min<int64_t>(cap_bytes, std::max<int64_t>((int64_t)(total / 16), (int64_t)1 << 30));
+    }
     if (const char *v = getenv("DSA_BND_BUDGET")) cap_bytes = std::max<int64_t>(atoll(v), 1);
-    int64_t QS = P.persistent ? std::max<int64_t>(1, std::min<int64_t>(nq, cap_bytes / std::max<int64_t>(slot_bytes, 1))) : 1;
-    P.n_slots = (int)QS;
-    for (int64_t q0 = 0; q0 < nq; q0 += QS) {
-        const int64_t q1 = std::min(nq, q0 + QS);
+    const int64_t QS = P.persistent ? std::max<int64_t>(1, std::min<int64_t>(nq, cap_bytes / std::max<int64_t>(slot_bytes, 1))) : 1;
+    // Each round is one launch with its own tail, so when the persistent form
+    // needs several, the queries are dealt longest first in snake order: the
+    // rounds get like mixes and differ in size by at most one query.
+    const int64_t n_rounds = (nq + QS - 1) / QS;
+    std::vector<std::vector<int64_t>> round_q((size_t)n_rounds);
+    if (P.persistent && n_rounds > 1) {
+        std::vector<int64_t> by_len((size_t)nq);
+        std::iota(by_len.begin(), by_len.end(), 0);
+        std::stable_sort(by_len.begin(), by_len.end(),
+                         [&](int64_t x, int64_t y) { return P.qinfo[x].len > P.qinfo[y].len; });
+        for (int64_t k = 0; k < nq; k++) {
+            const int64_t pass = k / n_rounds, pos = k % n_rounds;
+            round_q[(size_t)((pass & 1) ? n_rounds - 1 - pos : pos)].push_back(by_len[(size_t)k]);
+        }
+    } else {
+        for (int64_t q = 0; q < nq; q++) round_q[(size_t)(q / QS)].push_back(q);
+    }
+    P.n_slots = 1;
+    for (const auto &members : round_q) P.n_slots = std::max<int>(P.n_slots, (int)members.size());
+    for (const auto &members : round_q) {
         std::vector<SearchUnit> inter, rerun;
         std::vector<IntraUnit> iu;
         std::vector<int32_t> ks;  // strip-pipelined units: indices into rerun
-        for (int64_t q = q0; q < q1; q++) {
+        for (size_t qi = 0; qi < members.size(); qi++) {
+            const int64_t q = members[qi];
             if (P.qinfo[q].len == 0) continue;
             // groups from gc on go to the wavefront kernel: their inter-sequence
             // unit would be one long sequential task (strips x columns > budget)
             int64_t gc = db->n_groups;
             for (int64_t g = db->long_group0; g < db->n_groups; g++)
                 if ((int64_t)P.qinfo[q].strips * db->grp[g].ncols > P.budget) { gc = g; break; }
-            const int32_t qslot = (int32_t)(q - q0);
+            const int32_t qslot = (int32_t)qi;
             for (int64_t g0 = 0; g0 < gc; g0 += wpb) {
                 SearchUnit U;
                 U.q = (int32_t)q;

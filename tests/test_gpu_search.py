@@ -269,6 +269,37 @@ def test_search_rounds_of_one_query(mode, ends, blosum, monkeypatch):
     compare_search(got, exp, len(Q), len(T), label=f"rounds {mode}")
 
 
+def _slot_bytes(T):
+    """Boundary bytes of one query slot for database T: per group of 128
+    length-sorted targets, (H, F) int32-sized per column and lane; per pair
+    of a group at least 128 columns wide, one word per column."""
+    lens = np.sort(np.asarray(T.lengths, dtype=np.int64), kind="stable")
+    total = 0
+    long_words = 0
+    for g0 in range(0, len(lens), 128):
+        grp = lens[g0:g0 + 128]
+        ncols = (int(grp.max()) + 3) // 4 * 4
+        total += 2 * ncols * 64 * 8
+        if ncols >= 128:
+            grp = np.concatenate([grp, np.zeros(128 - len(grp), dtype=np.int64)])
+            long_words += int(np.maximum(grp[0::2], grp[1::2]).sum())
+    return total + max(long_words, 1) * 8
+
+
+@pytest.mark.parametrize("per_round", [2, 3])
+def test_search_rounds_of_several_queries(per_round, blosum, monkeypatch):
+    """A boundary budget of a few query slots splits the queries into rounds
+    of 2 or 3; they are dealt longest first in snake order (an empty query
+    among them)."""
+    T = _targets(15, 300, 1200, extra=[1, 1300])
+    Q = _queries(16, [5, 40, 700, 1500, 0, 300, 2000, 64])
+    monkeypatch.setenv("DSA_BND_BUDGET", str(per_round * _slot_bytes(T) + 7))
+    log(f"rounds of {per_round}")
+    got, _ = gpu_search(Q, T, blosum, 11, 1, "local")
+    exp = oracle.search(Q, T, blosum, 11, 1, mode="local")
+    compare_search(got, exp, len(Q), len(T), label=f"rounds of {per_round}")
+
+
 LOCAL16_MAX = 28544  # highest local score the offset int16 pass computes exactly
 
 
