@@ -175,14 +175,17 @@ __device__ __forceinline__ void column16_global(const uint32_t (&sc)[T], uint32_
 }
 
 // First row r (0-based) whose H equals the column maximum cm, per half,
-// as a packed uint16 pair (0x8000 + r marks "not equal").
+// as a packed uint16 pair.
 template <int T>
 __device__ __forceinline__ uint32_t first_row_of(const uint32_t (&H)[T], uint32_t cm) {
-    uint32_t idx = 0xffffffffu;
+    // per half: a stays 1 while every row so far differs from cm, and idx
+    // counts those rows, which is the index of the first equal row (T when
+    // there is none): three packed ops per row
+    uint32_t a = 0x00010001u, idx = 0;
 #pragma unroll
     for (int r = 0; r < T; r++) {
-        const uint32_t z = minu(H[r] ^ cm, 0x00010001u);
-        idx = minu(idx, addu(mulu(z, 0x80008000u), dup(r)));
+        a = minu(a, H[r] ^ cm);
+        idx = addu(idx, a);
     }
     return idx;
 }
