@@ -30,6 +30,7 @@
 // reaching the column maximum is located.  Strips are then merged
 // lexicographically (score desc, j asc, i asc).
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 #include "intra_unit.h"
@@ -195,19 +196,11 @@ k_search16(SearchArgs P, IntraArgs W) {
             }
 
             const int nblk = G.ncols >> 2;
-            // software pipeline: the next block's codes and boundary words are
-            // in flight while the current block computes
-            uint2 cd_n = make_uint2(0, 0), hf_n[4];
-#pragma unroll
-            for (int c = 0; c < 4; c++) hf_n[c] = make_uint2(0, 0);
-            if (nblk > 0) {
-                cd_n = pk[0];
-                if (!first) {
-#pragma unroll
-                    for (int c = 0; c < 4; c++) hf_n[c] = bnd[(int64_t)c * 64];
-                }
-            }
-            for (int c4 = 0; c4 < nblk; c4++) {
+            // one 4-column block; on the first strip the row above is the
+            // top boundary (a compile-time case, so the other strips carry
+            // no selects for it)
+            auto block = [&](auto first_strip, const int c4, const uint2 cd, const uint2 (&hf)[4]) {
+                constexpr bool FIRST = decltype(first_strip)::value;
                 if (MODE == LOCAL && c4 > 0 && c4 % rb == 0) {  // take the column frame back
 #pragma unroll
                     for (int r = 0; r < T; r++) {
@@ -217,24 +210,13 @@ k_search16(SearchArgs P, IntraArgs W) {
                     Hd_top = subw(Hd_top, back2);
                 }
                 const int cbase = kBias16 + (c4 % rb) * 4 * e;  // frame of the block's first column
-                const uint2 cd = cd_n;
-                uint2 hf[4];
-#pragma unroll
-                for (int c = 0; c < 4; c++) hf[c] = hf_n[c];
-                if (c4 + 1 < nblk) {
-                    cd_n = pk[(int64_t)(c4 + 1) * 64];
-                    if (!first) {
-#pragma unroll
-                        for (int c = 0; c < 4; c++) hf_n[c] = bnd[(int64_t)(4 * c4 + 4 + c) * 64];
-                    }
-                }
 #pragma unroll
                 for (int c = 0; c < 4; c++) {
                     const int j = c4 * 4 + c + 1;
                     const uint32_t p = ((c < 2 ? cd.x : cd.y) >> ((c & 1) * 16)) & 0xffffu;
                     uint32_t Hup, F;
                     const int cj = cbase + c * e;  // local: this column's frame
-                    if (first) {
+                    if constexpr (FIRST) {
                         Hup = (MODE == LOCAL) ? dup(cj) : dup(top_value(MODE, ends, o, e, j));
                         F = (MODE == LOCAL) ? dup(cj) : subs(Hup, o2);
                     } else {
@@ -276,7 +258,33 @@ k_search16(SearchArgs P, IntraArgs W) {
                     }
                     if (!last) bnd[(int64_t)(j - 1) * 64] = make_uint2(H[T - 1], F);
                 }
-            }
+            };
+            // software pipeline: the next block's codes and boundary words
+            // are in flight while the current block computes
+            auto sweep = [&](auto first_strip) {
+                constexpr bool FIRST = decltype(first_strip)::value;
+                uint2 cd_n = make_uint2(0, 0), hf_n[4];
+#pragma unroll
+                for (int c = 0; c < 4; c++) hf_n[c] = make_uint2(0, 0);
+                auto fetch = [&](const int c4) {
+                    cd_n = pk[(int64_t)c4 * 64];
+                    if constexpr (!FIRST) {
+#pragma unroll
+                        for (int c = 0; c < 4; c++) hf_n[c] = bnd[(int64_t)(4 * c4 + c) * 64];
+                    }
+                };
+                if (nblk > 0) fetch(0);
+                for (int c4 = 0; c4 < nblk; c4++) {
+                    const uint2 cd = cd_n;
+                    uint2 hf[4];
+#pragma unroll
+                    for (int c = 0; c < 4; c++) hf[c] = hf_n[c];
+                    if (c4 + 1 < nblk) fetch(c4 + 1);
+                    block(first_strip, c4, cd, hf);
+                }
+            };
+            if (first) sweep(std::true_type{});
+            else sweep(std::false_type{});
 
             if (MODE == LOCAL) {
                 const int b[2] = {lo16(B), hi16(B)};
