@@ -135,7 +135,7 @@ constexpr int kKsRowPad = 16;     // int16 of padding per letter row (bank shift
 __host__ __device__ constexpr size_t ks16_lds_bytes(int W, int AP) {
     return (size_t)2 * AP * (16 * W + kKsRowPad) * 2      // two round profiles, int16
            + (size_t)(W - 1) * 2 * 4 * kWave * 8           // hand-over ring, uint2
-           + (size_t)AP * AP * 2 + 16;                      // pair code -> two letters
+           + (size_t)AP * AP * 4;                           // pair code -> two letters' rows
 }
 
 // Pairwise alignment (query k against target k): one pair per lane, pairs

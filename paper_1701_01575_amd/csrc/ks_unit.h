@@ -41,14 +41,16 @@ __device__ __forceinline__ void ks16_unit(const SearchArgs &P, const SearchUnit 
     const int stride = 16 * W + kKsRowPad;  // int16 per letter row of a round profile
     int16_t *qp = reinterpret_cast<int16_t *>(lds4);                          // [2][AP][stride]
     uint2 *ring = reinterpret_cast<uint2 *>(qp + 2 * AP * stride);            // [W-1][2][4][64]
-    uint8_t *dec = reinterpret_cast<uint8_t *>(ring + (W - 1) * 2 * 4 * kWave);  // [AP*AP][2]
+    // per pair code: byte offsets of its two letters' rows in a round profile
+    uint32_t *rows = reinterpret_cast<uint32_t *>(ring + (W - 1) * 2 * 4 * kWave);  // [AP*AP]
 
     const QueryInfo Q = P.qinfo[U.q];
     const GroupInfo G = P.grp[U.g0];
     const int m = Q.len, S = (m + T - 1) / T, R = (S + W - 1) / W;
     const int nblk = G.ncols >> 2;
     const uint8_t *qc = P.q_codes + Q.off;
-    for (int k = tid; k < AP * AP * 2; k += blockDim.x) dec[k] = P.pair_dec[k];
+    for (int k = tid; k < AP * AP; k += blockDim.x)
+        rows[k] = (uint32_t)(P.pair_dec[2 * k] * stride * 2) | ((uint32_t)(P.pair_dec[2 * k + 1] * stride * 2) << 16);
 
     // single-letter profile of round r (rows 16 W r ...), scores + e (the frame)
     auto build = [&](int r) {
@@ -139,15 +141,15 @@ __device__ __forceinline__ void ks16_unit(const SearchArgs &P, const SearchUnit 
             }
             const uint2 cd = cd_n;
             cd_n = pk[(int64_t)(c4 + 1 < nblk ? c4 + 1 : 0) * 64];
-            const int16_t *prow = qp + (r & 1) * AP * stride + wave * 16;
+            const char *prow = reinterpret_cast<const char *>(qp + (r & 1) * AP * stride + wave * 16);
             uint2 out[4];
 #pragma unroll
             for (int c = 0; c < 4; c++) {
                 const int j = c4 * 4 + c + 1;
                 const uint32_t p = ((c < 2 ? cd.x : cd.y) >> ((c & 1) * 16)) & 0xffffu;
-                const int clo = dec[2 * p], chi = dec[2 * p + 1];
-                const uint4 *plo = reinterpret_cast<const uint4 *>(prow + clo * stride);
-                const uint4 *phi = reinterpret_cast<const uint4 *>(prow + chi * stride);
+                const uint32_t rw = rows[p];
+                const uint4 *plo = reinterpret_cast<const uint4 *>(prow + (rw & 0xffffu));
+                const uint4 *phi = reinterpret_cast<const uint4 *>(prow + (rw >> 16));
                 uint32_t sc[T];
 #pragma unroll
                 for (int k = 0; k < T / 8; k++) {
