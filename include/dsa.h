@@ -58,7 +58,8 @@
 extern "C" {
 #endif
 
-#define DSA_ABI_VERSION 1
+/* raised whenever a struct layout or a signature below changes */
+#define DSA_ABI_VERSION 2
 
 typedef enum {
     DSA_OK = 0,

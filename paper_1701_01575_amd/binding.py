@@ -10,6 +10,7 @@ import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libdsa.so")
+ABI_VERSION = 2  # DSA_ABI_VERSION of the include/dsa.h the structs here mirror
 
 DSA_OK, DSA_E_INVAL, DSA_E_RANGE, DSA_E_WORKSPACE, DSA_E_CAPACITY, DSA_E_DEVICE, DSA_E_NOTSUP = range(7)
 DSA_LOCAL, DSA_GLOBAL, DSA_SEMIGLOBAL = 0, 1, 2
@@ -97,6 +98,9 @@ def lib():
         L.dsa_last_error.argtypes = []
         L.dsa_last_error.restype = ctypes.c_char_p
         L.dsa_abi_version.restype = ctypes.c_int32
+        if L.dsa_abi_version() != ABI_VERSION:  # the structs below mirror that version of dsa.h
+            raise RuntimeError(f"{LIB_PATH}: ABI version {L.dsa_abi_version()}, the binding expects "
+                               f"{ABI_VERSION}; rebuild with __graft_entry__.build()")
         for name in EXPORTS:
             if name not in ("dsa_strerror", "dsa_last_error", "dsa_abi_version"):
                 getattr(L, name).restype = ctypes.c_int

@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported(B):
     for n in names:
         assert hasattr(L, n), n
     assert sorted(B.EXPORTS) == names
-    assert B.dsa_abi_version() == 1
+    assert B.dsa_abi_version() == B.ABI_VERSION == 2
 
 
 def test_strerror(B):
