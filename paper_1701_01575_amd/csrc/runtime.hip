@@ -1163,11 +1163,12 @@ int make_search_plan(const dsa_args *a, Plan &P) {
             }
             // a strip-pipelined unit: one 4-column block of 16 rows per
             // wave and barrier step, rounds x columns / 4 steps plus the
-            // pipeline fill
+            // pipeline fill, at about 1.2x the instructions per column of an
+            // inter-sequence unit (the byte permutes of its profile)
             for (int32_t r : ks) {
                 const SearchUnit &U = rerun[r];
                 const int64_t rounds_ks = (P.qinfo[U.q].strips + wpb - 1) / wpb;
-                const double c = 1.1 * (rounds_ks * db->grp[U.g0].ncols + 4.0 * (wpb - 1)) * kTI;
+                const double c = 1.25 * (rounds_ks * db->grp[U.g0].ncols + 4.0 * (wpb - 1)) * kTI;
                 w.push_back({c, kKsBase + (int32_t)(R.inter + r)});
             }
             std::stable_sort(w.begin(), w.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
