@@ -29,6 +29,14 @@ constexpr int kLocal16GapMax = kBias16 - 1024;
 constexpr int kLocal16ExtMax = kShift16 / 4;
 
 enum Mode { LOCAL = 0, GLOBAL = 1, SEMIGLOBAL = 2 };
+
+// The value of lane - 1 of the wave (0 for lane 0): one VALU op with a
+// wave-wide DPP shift, where a shuffle would take an LDS round trip.  The
+// wavefront kernels call it at the top of each step with every lane of a
+// segment active, and a segment's first lane replaces what it receives.
+__device__ __forceinline__ int lane_above(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+}
 enum Ends { QB = 1, QE = 2, TB = 4, TE = 8 };
 
 // One group of 128 length-sorted targets.

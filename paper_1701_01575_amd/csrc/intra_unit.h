@@ -113,8 +113,8 @@ __device__ __forceinline__ void intra16_run(const IntraArgs &P, const IntraUnit 
         uint32_t cnext = (act && ncols > 0) ? codes[0] : 0;
         for (int t = 0; t < nsteps; t++) {
             // lane - 1's last row and the F leaving it, computed one step ago
-            uint32_t rH = (uint32_t)__shfl_up((int)outH, 1, kWave);
-            uint32_t rF = (uint32_t)__shfl_up((int)outF, 1, kWave);
+            uint32_t rH = (uint32_t)lane_above((int)outH);
+            uint32_t rF = (uint32_t)lane_above((int)outF);
             const int j = t - lane + 1;
             const bool colok = act && j >= 1 && j <= ncols;
             const uint32_t cc = cnext;

@@ -354,8 +354,8 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
         uint2 bnext = make_uint2(0u, 0u);
         if (lane == 0 && pass > 0 && n > 0) bnext = bnd[0];
         for (int t = 0; t < nsteps; t++) {
-            int rH = __shfl_up(outH, 1, SEG);
-            int rF = __shfl_up(outF, 1, SEG);
+            int rH = lane_above(outH);
+            int rF = lane_above(outF);
             const int j = t - lane + 1;
             const int cc = cnext;
             const uint2 bc = bnext;
