@@ -55,14 +55,22 @@ def _replay_and_check(rec, queries_seq, eager_fn, fields, tb=False):
                 assert len(a[r]) == len(b[r]) and (a[r] == b[r]).all(), f"replay {k} cigar {r}"
 
 
-@pytest.mark.parametrize("mode,top_k", [("local", 0), ("global", 0), ("semiglobal", 0), ("local", 5)])
-def test_graph_search(mode, top_k, blosum):
+@pytest.mark.parametrize("mode,top_k,route", [
+    ("local", 0, None), ("global", 0, None), ("semiglobal", 0, None), ("local", 5, None),
+    ("local", 0, "wavefront"), ("local", 0, "pipelined"), ("local", 5, "pipelined")])
+def test_graph_search(mode, top_k, route, blosum, monkeypatch):
+    """Replays of a recorded search; the routed cases send every group at
+    least 128 columns wide to the wavefront or the strip-pipelined units,
+    which then run inside the recorded persistent launch."""
     import torch
     import paper_1701_01575_amd as dsa
+    if route is not None:
+        monkeypatch.setenv("DSA_INTRA_BUDGET", "1")
+        monkeypatch.setenv("DSA_KS_BUDGET", "0" if route == "wavefront" else str(1 << 40))
     c = gen.cfg2(n_targets=3000, query_lengths=(20, 144, 700))
     Q, T = c["queries"], c["targets"]
     db = dsa.Database.from_seqset(T, blosum.shape[0])
-    log(f"graph search mode={mode} top_k={top_k}")
+    log(f"graph search mode={mode} top_k={top_k} route={route}")
 
     def eager(Qx):
         r = dsa.align(Qx, db=db, matrix=blosum, gap_open=11, gap_extend=1, mode=mode, top_k=top_k)
