@@ -18,6 +18,8 @@
 // Arithmetic, frame, end-cell rule and overflow flag are those of the
 // inter-sequence kernel.
 #pragma once
+#include <type_traits>
+
 #include "internal.h"
 #include "pk16.h"
 
@@ -86,124 +88,134 @@ __device__ __forceinline__ void ks16_unit(const SearchArgs &P, const SearchUnit 
     uint2 cd_n = pk[0];
 
     const int ticks = R * nblk + W - 1;
-    for (int t = 0; t < ticks; t++) {
-        // round r + 1's profile while round r is under way (its buffer was
-        // last read at tick (r - 1) nblk + W - 2 and is first read at tick
-        // (r + 1) nblk; nblk > W)
-        if (t >= W && (t - W) % nblk == 0) {
-            const int r1 = (t - W) / nblk + 1;
-            if (r1 < R) build(r1);
-        }
-        const int tt = t - wave;
-        const int r = tt >= 0 ? tt / nblk : 0, c4 = tt >= 0 ? tt - r * nblk : 0;
-        const int s = r * W + wave;
-        if (tt >= 0 && r < R && s < S) {
-            const int i0 = s * T;
-            if (c4 == 0) {  // a new strip: column 0 sits one e below column 1's frame
-#pragma unroll
-                for (int x = 0; x < T; x++) {
-                    H[x] = dup(kBias16 - e);
-                    E[x] = dup(kBias16);
-                }
-                Hd_top = dup(kBias16 - e);
-                B = maxs(subs(Gs, dup(1)), 0u);
-                Bj = 0;
-                Bi = 0;
-            } else if (c4 % rb == 0) {  // take the column frame back
-#pragma unroll
-                for (int x = 0; x < T; x++) {
-                    H[x] = subw(H[x], back2);
-                    E[x] = subw(E[x], back2);
-                }
-                Hd_top = subw(Hd_top, back2);
+    // the step loop, specialised by the wave's role: wave 0 reads the row
+    // above from the boundary row (or the top boundary), the others from
+    // the ring; the last wave writes its bottom row to the boundary row,
+    // the others to the ring
+    auto steps = [&](auto role) {
+        constexpr int ROLE = decltype(role)::value;  // 0: first wave, 1: middle, 2: last
+        for (int t = 0; t < ticks; t++) {
+            // round r + 1's profile while round r is under way (its buffer was
+            // last read at tick (r - 1) nblk + W - 2 and is first read at tick
+            // (r + 1) nblk; nblk > W)
+            if (t >= W && (t - W) % nblk == 0) {
+                const int r1 = (t - W) / nblk + 1;
+                if (r1 < R) build(r1);
             }
-            const int cbase = kBias16 + (c4 % rb) * 4 * e;
-            // the row above this block: the strip above's bottom row
-            uint2 hf[4];
-            if (s == 0) {
+            const int tt = t - wave;
+            const int r = tt >= 0 ? tt / nblk : 0, c4 = tt >= 0 ? tt - r * nblk : 0;
+            const int s = r * W + wave;
+            if (tt >= 0 && r < R && s < S) {
+                const int i0 = s * T;
+                if (c4 == 0) {  // a new strip: column 0 sits one e below column 1's frame
 #pragma unroll
-                for (int c = 0; c < 4; c++) hf[c] = make_uint2(dup(cbase + c * e), dup(cbase + c * e));
-            } else if (wave > 0) {
-                const uint2 *src = ring + ((wave - 1) * 2 + ((t - 1) & 1)) * 4 * kWave + lane;
+                    for (int x = 0; x < T; x++) {
+                        H[x] = dup(kBias16 - e);
+                        E[x] = dup(kBias16);
+                    }
+                    Hd_top = dup(kBias16 - e);
+                    B = maxs(subs(Gs, dup(1)), 0u);
+                    Bj = 0;
+                    Bi = 0;
+                } else if (c4 % rb == 0) {  // take the column frame back
 #pragma unroll
-                for (int c = 0; c < 4; c++) hf[c] = src[c * kWave];
-            } else {
-                if (c4 == 0) {
-#pragma unroll
-                    for (int c = 0; c < 4; c++) hf_n[c] = load_handover(bnd + (int64_t)c * 64);
+                    for (int x = 0; x < T; x++) {
+                        H[x] = subw(H[x], back2);
+                        E[x] = subw(E[x], back2);
+                    }
+                    Hd_top = subw(Hd_top, back2);
                 }
+                const int cbase = kBias16 + (c4 % rb) * 4 * e;
+                // the row above this block: the strip above's bottom row
+                uint2 hf[4];
+                if (ROLE == 0 && s == 0) {
 #pragma unroll
-                for (int c = 0; c < 4; c++) hf[c] = hf_n[c];
-                if (c4 + 1 < nblk) {
+                    for (int c = 0; c < 4; c++) hf[c] = make_uint2(dup(cbase + c * e), dup(cbase + c * e));
+                } else if (ROLE != 0) {
+                    const uint2 *src = ring + ((wave - 1) * 2 + ((t - 1) & 1)) * 4 * kWave + lane;
 #pragma unroll
-                    for (int c = 0; c < 4; c++) hf_n[c] = load_handover(bnd + (int64_t)(4 * c4 + 4 + c) * 64);
-                }
-            }
-            const uint2 cd = cd_n;
-            cd_n = pk[(int64_t)(c4 + 1 < nblk ? c4 + 1 : 0) * 64];
-            const char *prow = reinterpret_cast<const char *>(qp + (r & 1) * AP * stride + wave * 16);
-            uint2 out[4];
+                    for (int c = 0; c < 4; c++) hf[c] = src[c * kWave];
+                } else {
+                    if (c4 == 0) {
 #pragma unroll
-            for (int c = 0; c < 4; c++) {
-                const int j = c4 * 4 + c + 1;
-                const uint32_t p = ((c < 2 ? cd.x : cd.y) >> ((c & 1) * 16)) & 0xffffu;
-                const uint32_t rw = rows[p];
-                const uint4 *plo = reinterpret_cast<const uint4 *>(prow + (rw & 0xffffu));
-                const uint4 *phi = reinterpret_cast<const uint4 *>(prow + (rw >> 16));
-                uint32_t sc[T];
+                        for (int c = 0; c < 4; c++) hf_n[c] = load_handover(bnd + (int64_t)c * 64);
+                    }
 #pragma unroll
-                for (int k = 0; k < T / 8; k++) {
-                    const uint4 a = plo[k], b = phi[k];
-                    const uint32_t la[4] = {a.x, a.y, a.z, a.w}, hb[4] = {b.x, b.y, b.z, b.w};
+                    for (int c = 0; c < 4; c++) hf[c] = hf_n[c];
+                    if (c4 + 1 < nblk) {
 #pragma unroll
-                    for (int w = 0; w < 4; w++) {
-                        sc[8 * k + 2 * w] = __builtin_amdgcn_perm(hb[w], la[w], 0x05040100u);
-                        sc[8 * k + 2 * w + 1] = __builtin_amdgcn_perm(hb[w], la[w], 0x07060302u);
+                        for (int c = 0; c < 4; c++) hf_n[c] = load_handover(bnd + (int64_t)(4 * c4 + 4 + c) * 64);
                     }
                 }
-                const int cj = cbase + c * e;
-                const uint32_t Hup = hf[c].x;
-                uint32_t F = hf[c].y;
-                const uint32_t Hd = Hd_top;
-                Hd_top = Hup;
-                const uint32_t Bc = addu(B, dup(cj));
-                const uint32_t nb = column16_local_cs<T>(sc, H, E, Hd, F, o2e, e2, dup(cj + e), Bc);
-                if (nb != Bc) {
-                    const uint32_t mask = nzmask(nb ^ Bc);
-                    const uint32_t idx = first_row_of<T>(H, nb);
-                    Bi = bfi(mask, addu(idx, dup(i0 + 1)), Bi);
-                    Bj = bfi(mask, dup(j), Bj);
-                    B = maxs(B, subw(nb, dup(cj)));
+                const uint2 cd = cd_n;
+                cd_n = pk[(int64_t)(c4 + 1 < nblk ? c4 + 1 : 0) * 64];
+                const char *prow = reinterpret_cast<const char *>(qp + (r & 1) * AP * stride + wave * 16);
+                uint2 out[4];
+#pragma unroll
+                for (int c = 0; c < 4; c++) {
+                    const int j = c4 * 4 + c + 1;
+                    const uint32_t p = ((c < 2 ? cd.x : cd.y) >> ((c & 1) * 16)) & 0xffffu;
+                    const uint32_t rw = rows[p];
+                    const uint4 *plo = reinterpret_cast<const uint4 *>(prow + (rw & 0xffffu));
+                    const uint4 *phi = reinterpret_cast<const uint4 *>(prow + (rw >> 16));
+                    uint32_t sc[T];
+#pragma unroll
+                    for (int k = 0; k < T / 8; k++) {
+                        const uint4 a = plo[k], b = phi[k];
+                        const uint32_t la[4] = {a.x, a.y, a.z, a.w}, hb[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+                        for (int w = 0; w < 4; w++) {
+                            sc[8 * k + 2 * w] = __builtin_amdgcn_perm(hb[w], la[w], 0x05040100u);
+                            sc[8 * k + 2 * w + 1] = __builtin_amdgcn_perm(hb[w], la[w], 0x07060302u);
+                        }
+                    }
+                    const int cj = cbase + c * e;
+                    const uint32_t Hup = hf[c].x;
+                    uint32_t F = hf[c].y;
+                    const uint32_t Hd = Hd_top;
+                    Hd_top = Hup;
+                    const uint32_t Bc = addu(B, dup(cj));
+                    const uint32_t nb = column16_local_cs<T>(sc, H, E, Hd, F, o2e, e2, dup(cj + e), Bc);
+                    if (nb != Bc) {
+                        const uint32_t mask = nzmask(nb ^ Bc);
+                        const uint32_t idx = first_row_of<T>(H, nb);
+                        Bi = bfi(mask, addu(idx, dup(i0 + 1)), Bi);
+                        Bj = bfi(mask, dup(j), Bj);
+                        B = maxs(B, subw(nb, dup(cj)));
+                    }
+                    out[c] = make_uint2(H[T - 1], F);
                 }
-                out[c] = make_uint2(H[T - 1], F);
-            }
-            // hand the block's bottom row on
-            if (wave < W - 1) {
-                uint2 *dst = ring + (wave * 2 + (t & 1)) * 4 * kWave + lane;
+                // hand the block's bottom row on
+                if (ROLE != 2) {
+                    uint2 *dst = ring + (wave * 2 + (t & 1)) * 4 * kWave + lane;
 #pragma unroll
-                for (int c = 0; c < 4; c++) dst[c * kWave] = out[c];
-            } else if (s + 1 < S) {
+                    for (int c = 0; c < 4; c++) dst[c * kWave] = out[c];
+                } else if (s + 1 < S) {
 #pragma unroll
-                for (int c = 0; c < 4; c++) bnd[(int64_t)(4 * c4 + c) * 64] = out[c];
-            }
-            if (c4 == nblk - 1) {  // strip done: merge its best into the wave's
-                const int b2[2] = {lo16(B), hi16(B)};
-                const int bj[2] = {(int)(Bj & 0xffff), (int)(Bj >> 16)};
-                const int bi[2] = {(int)(Bi & 0xffff), (int)(Bi >> 16)};
-                uint64_t gk[2] = {end_key(lo16(Gs), (int)(Gj & 0xffff), (int)(Gi & 0xffff)),
-                                  end_key(hi16(Gs), (int)(Gj >> 16), (int)(Gi >> 16))};
-#pragma unroll
-                for (int h = 0; h < 2; h++) {
-                    const uint64_t kk = end_key(b2[h], bj[h], bi[h]);
-                    gk[h] = (b2[h] > 0) ? umax64(gk[h], kk) : gk[h];
+                    for (int c = 0; c < 4; c++) bnd[(int64_t)(4 * c4 + c) * 64] = out[c];
                 }
-                Gs = pack2(key_score(gk[0]), key_score(gk[1]));
-                Gj = pack2(key_j(gk[0]), key_j(gk[1]));
-                Gi = pack2(key_i(gk[0]), key_i(gk[1]));
+                if (c4 == nblk - 1) {  // strip done: merge its best into the wave's
+                    const int b2[2] = {lo16(B), hi16(B)};
+                    const int bj[2] = {(int)(Bj & 0xffff), (int)(Bj >> 16)};
+                    const int bi[2] = {(int)(Bi & 0xffff), (int)(Bi >> 16)};
+                    uint64_t gk[2] = {end_key(lo16(Gs), (int)(Gj & 0xffff), (int)(Gi & 0xffff)),
+                                      end_key(hi16(Gs), (int)(Gj >> 16), (int)(Gi >> 16))};
+#pragma unroll
+                    for (int h = 0; h < 2; h++) {
+                        const uint64_t kk = end_key(b2[h], bj[h], bi[h]);
+                        gk[h] = (b2[h] > 0) ? umax64(gk[h], kk) : gk[h];
+                    }
+                    Gs = pack2(key_score(gk[0]), key_score(gk[1]));
+                    Gj = pack2(key_j(gk[0]), key_j(gk[1]));
+                    Gi = pack2(key_i(gk[0]), key_i(gk[1]));
+                }
             }
+            __syncthreads();
         }
-        __syncthreads();
-    }
+    };
+    if (wave == 0) steps(std::integral_constant<int, 0>{});
+    else if (wave == W - 1) steps(std::integral_constant<int, 2>{});
+    else steps(std::integral_constant<int, 1>{});
 
     // merge the waves' bests per target: end keys through LDS
     uint64_t *keys = reinterpret_cast<uint64_t *>(lds4);  // [W][2][64]
