@@ -138,9 +138,14 @@ def cigar_string(ops) -> str:
     return "".join(f"{int(x) >> 4}{OP_CHARS[int(x) & 15]}" for x in ops)
 
 
-def top_k(scores: np.ndarray, k: int):
-    """Top-k target indices of one query by (score desc, index asc), score > 0
-    only: a full stable sort of the oracle's per-target scores."""
-    order = np.lexsort((np.arange(len(scores)), -scores.astype(np.int64)))
-    order = order[scores[order] > 0]
+def top_k(scores: np.ndarray, k: int, positive_only: bool = True):
+    """Top-k target indices of one query (Section II.B.2: the k best
+    alignments by maximum score), by (score desc, index asc): a full stable
+    sort of the oracle's per-target scores.  With positive_only (local mode)
+    scores <= 0, which mean "no alignment", are left out; in global and
+    semi-global mode every target counts."""
+    scores = np.asarray(scores).astype(np.int64)
+    order = np.lexsort((np.arange(len(scores)), -scores))
+    if positive_only:
+        order = order[scores[order] > 0]
     return order[:k]

@@ -31,10 +31,7 @@ def expected_topk(Q, T, S, o, e, K, mode, ends=None):
     sc = full["score"].reshape(nq, nt)
     hits = []
     for q in range(nq):
-        if mode == "local":
-            idx = oracle.top_k(sc[q], K)
-        else:
-            idx = np.lexsort((np.arange(nt), -sc[q].astype(np.int64)))[:K]
+        idx = oracle.top_k(sc[q], K, positive_only=(mode == "local"))
         hits.append(list(idx) + [-1] * (K - len(idx)))
     return full, np.array(hits, dtype=np.int64)
 

@@ -6,7 +6,9 @@ vs free query ends); reversal symmetry (local, global, all-ends-free
 semi-global); scores never increase with the gap open or extend penalty;
 local(a, b) >= local(a, b') for b' a substring of b; local is bounded by the
 sum of positive row maxima and of positive column maxima.  Every CIGAR the
-oracle emits rescores to its score.
+oracle emits rescores to its score.  Every prefix of a local alignment that
+ends on an =/X column scores above zero (the traceback stops at a zero
+cell before it takes any other step).
 """
 import numpy as np
 from hypothesis import given, settings, strategies as st
@@ -112,3 +114,41 @@ def test_cigar_rescores(a, b, g, mode):
         assert r["q_begin"] == 0 and r["q_end"] == len(a) - 1
     if mode == "local":
         assert runs[0][1] in "=X" and runs[-1][1] in "=X"
+
+
+dna_seq = st.lists(st.integers(0, 3), min_size=0, max_size=40).map(lambda v: np.array(v, np.uint8))
+
+
+@settings(**SETTINGS)
+@given(st.one_of(st.tuples(seq, seq, st.just("protein")), st.tuples(dna_seq, dna_seq, st.just("dna"))),
+       gaps)
+def test_local_positive_prefixes(ab, g):
+    """Scored from the definition (brute.score_columns), each prefix of the
+    reported local alignment that ends on a match or mismatch column is
+    positive: the traceback stops at a zero cell before any other step, so
+    it never passes through a cell whose best score is <= 0.  Each suffix
+    that starts on such a column is positive too: otherwise the part before
+    it would score at least as much and end at a smaller target position,
+    which the end-cell rule (smallest target end among the best) would have
+    chosen."""
+    from workloads import blosum62, dna_matrix
+    a, b, kind = ab
+    S = blosum62() if kind == "protein" else dna_matrix(2, -3)
+    o, e = g
+    r = one(a, b, S, o, e, "local", tb=True)
+    if r["score"] == 0:
+        return
+    cols = ops_to_cols([(int(x) >> 4, oracle.OP_CHARS[int(x) & 15]) for x in r["cigars"]])
+    A, B = [int(x) for x in a], [int(x) for x in b]
+    i0, j0 = int(r["q_begin"]), int(r["t_begin"])
+    for k in range(1, len(cols) + 1):
+        if cols[k - 1] == "M":
+            sc, _, _ = score_columns(A, B, S, o, e, i0, j0, cols[:k])
+            assert sc > 0, (cols, k, sc)
+    i, j = i0, j0
+    for k in range(len(cols)):
+        if cols[k] == "M":
+            sc, _, _ = score_columns(A, B, S, o, e, i, j, cols[k:])
+            assert sc > 0, (cols, k, sc)
+        i += cols[k] in "MI"
+        j += cols[k] in "MD"
