@@ -185,6 +185,29 @@ int dsa_cigar_capacity(const dsa_args *args, int64_t *entries);
 int dsa_align_batch(const dsa_args *args, const dsa_out *out);
 
 /*
+ * dsa_align_batch_noalloc - dsa_align_batch for callers that cannot
+ * allocate memory (code that must not call hipMalloc or hipHostMalloc:
+ * tight serving loops, harnesses that forbid allocation).  Same arguments,
+ * results, status codes and stream semantics as dsa_align_batch, except:
+ *   - args->workspace and args->workspace_bytes are ignored; the workspace
+ *     is a static device array of the library, DSA_NOALLOC_SCRATCH_BYTES
+ *     (64 MiB) per device, held from the library's load until the process
+ *     ends.  Boundary rows and direction-code chunks are planned to at
+ *     most a quarter of it each (more rounds of queries, more chunks).
+ *   - a call whose plan still needs more returns DSA_E_WORKSPACE before any
+ *     device work; dsa_last_error states the bytes needed.
+ *   - no device or pinned host memory is allocated: the work tables go to
+ *     the device from pageable host memory (the host heap holds the plan).
+ *     The first call on a device looks up the array's device address.
+ *   - every call on a device shares the array and finds the previous
+ *     call's contents in it: calls that overlap on one device (two streams,
+ *     two threads) race and give undefined results; calls in order on one
+ *     stream, or separated by synchronisation, are safe.
+ */
+#define DSA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int dsa_align_batch_noalloc(const dsa_args *args, const dsa_out *out);
+
+/*
  * Recorded batches: the batched form replayed from a HIP graph, for callers
  * that run the same batch shape again and again (Section II.B's map phase
  * over a fixed query set and reference).

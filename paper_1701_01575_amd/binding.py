@@ -19,7 +19,7 @@ DSA_TRACEBACK, DSA_PLAIN, DSA_FORCE_INT32 = 1, 2, 4
 DSA_ST_INT32, DSA_ST_TRUNCATED = 1, 2
 
 EXPORTS = ["dsa_db_create", "dsa_db_destroy", "dsa_db_info", "dsa_workspace_size",
-           "dsa_cigar_capacity", "dsa_align_batch", "dsa_graph_create", "dsa_graph_launch",
+           "dsa_cigar_capacity", "dsa_align_batch", "dsa_align_batch_noalloc", "dsa_graph_create", "dsa_graph_launch",
            "dsa_graph_destroy", "dsa_autotune", "dsa_tuning_get", "dsa_tuning_key",
            "dsa_timing_enable", "dsa_timing_read",
            "dsa_timing_reset",
@@ -88,6 +88,7 @@ def lib():
         L.dsa_workspace_size.argtypes = [ctypes.POINTER(dsa_args), ctypes.POINTER(ctypes.c_size_t)]
         L.dsa_cigar_capacity.argtypes = [ctypes.POINTER(dsa_args), ctypes.POINTER(ctypes.c_int64)]
         L.dsa_align_batch.argtypes = [ctypes.POINTER(dsa_args), ctypes.POINTER(dsa_out)]
+        L.dsa_align_batch_noalloc.argtypes = [ctypes.POINTER(dsa_args), ctypes.POINTER(dsa_out)]
         L.dsa_timing_enable.argtypes = [ctypes.c_int]
         L.dsa_timing_read.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int64)]
@@ -148,6 +149,19 @@ def dsa_align_batch(args: dsa_args, out: dsa_out) -> int:
     st = lib().dsa_align_batch(ctypes.byref(args), ctypes.byref(out))
     if st not in (DSA_OK, DSA_E_CAPACITY):
         check(st, "dsa_align_batch")
+    return st
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # DSA_NOALLOC_SCRATCH_BYTES
+
+
+def dsa_align_batch_noalloc(args: dsa_args, out: dsa_out) -> int:
+    """dsa_align_batch on the library's static scratch (args.workspace is
+    ignored).  Returns the status (DSA_OK or DSA_E_CAPACITY); raises on
+    other errors."""
+    st = lib().dsa_align_batch_noalloc(ctypes.byref(args), ctypes.byref(out))
+    if st not in (DSA_OK, DSA_E_CAPACITY):
+        check(st, "dsa_align_batch_noalloc")
     return st
 
 

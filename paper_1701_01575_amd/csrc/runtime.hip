@@ -41,10 +41,17 @@ struct Staging {
     std::mutex mu;
     void *buf = nullptr;
     size_t cap = 0;
+    std::vector<uint8_t> pageable;  // tables of dsa_align_batch_noalloc (no pinned allocation)
     hipEvent_t ev = nullptr;
     bool pending = false;
 };
 Staging g_staging[64];
+
+// Set while this thread runs dsa_align_batch_noalloc: tables go through
+// pageable host memory, and the boundary-row and direction-code budgets are
+// capped so that the plan fits the static scratch array.
+thread_local bool t_noalloc = false;
+thread_local int64_t t_budget_cap = 0;
 
 // Optional kernel timing (dsa_timing_enable / dsa_timing_read): event pairs
 // recorded on the stream a kernel is launched on, grouped by kind.
@@ -651,6 +658,7 @@ int64_t tb_budget_bytes() {
     if (hipGetDevice(&dev) == hipSuccess && hipDeviceTotalMem(&total, dev) == hipSuccess && total > 0)
         b = std::min<int64_t>(b, std::max<int64_t>((int64_t)(total / 16), (int64_t)1 << 28));
     if (const char *v = getenv("DSA_TB_BUDGET")) b = std::max<int64_t>(atoll(v), 1 << 20);
+    if (t_budget_cap > 0) b = std::min(b, t_budget_cap);
     return b;
 }
 
@@ -1043,6 +1051,7 @@ int make_search_plan(const dsa_args *a, Plan &P) {
             cap_bytes = std::min<int64_t>(cap_bytes, std::max<int64_t>((int64_t)(total / 16), (int64_t)1 << 30));
     }
     if (const char *v = getenv("DSA_BND_BUDGET")) cap_bytes = std::max<int64_t>(atoll(v), 1);
+    if (t_budget_cap > 0) cap_bytes = std::min(cap_bytes, t_budget_cap);
     const int64_t QS = P.persistent ? std::max<int64_t>(1, std::min<int64_t>(nq, cap_bytes / std::max<int64_t>(slot_bytes, 1))) : 1;
     // Each round is one launch with its own tail, so when the persistent form
     // needs several, the queries are dealt longest first in snake order: the
@@ -1276,17 +1285,27 @@ static int upload_tables(hipStream_t st, void *dst, size_t bytes,
         HIPCHK(hipEventSynchronize(S.ev));
         S.pending = false;
     }
-    if (S.cap < bytes) {
-        if (S.buf) HIPCHK(hipHostFree(S.buf));
-        S.buf = nullptr;
-        S.cap = 0;
-        HIPCHK(hipHostMalloc(&S.buf, bytes, hipHostMallocDefault));
-        S.cap = bytes;
-    }
     if (!S.ev) HIPCHK(hipEventCreateWithFlags(&S.ev, hipEventDisableTiming));
-    memset(S.buf, 0, bytes);
-    fill((uint8_t *)S.buf);
-    HIPCHK(hipMemcpyAsync(dst, S.buf, bytes, hipMemcpyHostToDevice, st));
+    uint8_t *h;
+    if (t_noalloc) {
+        // host heap only: the copy engine reads pageable memory through the
+        // runtime's own staging, and the event below keeps the buffer
+        // untouched until that copy is done
+        if (S.pageable.size() < bytes) S.pageable.resize(bytes);
+        h = S.pageable.data();
+    } else {
+        if (S.cap < bytes) {
+            if (S.buf) HIPCHK(hipHostFree(S.buf));
+            S.buf = nullptr;
+            S.cap = 0;
+            HIPCHK(hipHostMalloc(&S.buf, bytes, hipHostMallocDefault));
+            S.cap = bytes;
+        }
+        h = (uint8_t *)S.buf;
+    }
+    memset(h, 0, bytes);
+    fill(h);
+    HIPCHK(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, st));
     HIPCHK(hipEventRecord(S.ev, st));
     S.pending = true;
     return DSA_OK;
@@ -1520,40 +1539,24 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
         so.t_begin = nullptr;
     }
 
-    // tables -> pinned staging -> workspace
+    // tables -> staging -> workspace
     std::vector<QueryInfo> q32 = P.qinfo;
     for (auto &q : q32) q.strips = (q.len + kT32 - 1) / kT32;
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
-    Staging &S = g_staging[dev & 63];
     if (phase != RUN_KERNELS) {
-        std::lock_guard<std::mutex> lk(S.mu);
-        if (S.pending) {
-            HIPCHK(hipEventSynchronize(S.ev));
-            S.pending = false;
-        }
-        if (S.cap < P.table_bytes) {
-            if (S.buf) HIPCHK(hipHostFree(S.buf));
-            S.buf = nullptr;
-            S.cap = 0;
-            HIPCHK(hipHostMalloc(&S.buf, P.table_bytes, hipHostMallocDefault));
-            S.cap = P.table_bytes;
-        }
-        if (!S.ev) HIPCHK(hipEventCreateWithFlags(&S.ev, hipEventDisableTiming));
-        uint8_t *h = (uint8_t *)S.buf;
-        memset(h, 0, P.table_bytes);
-        if (!P.units.empty()) memcpy(h + P.off_units, P.units.data(), P.units.size() * sizeof(SearchUnit));
-        if (!P.iunits.empty())
-            memcpy(h + P.off_iunits, P.iunits.data(), P.iunits.size() * sizeof(IntraUnit));
-        if (!P.order.empty()) memcpy(h + P.off_order, P.order.data(), P.order.size() * sizeof(int32_t));
-        memcpy(h + P.off_qinfo, P.qinfo.data(), nq * sizeof(QueryInfo));
-        memcpy(h + P.off_qinfo + nq * sizeof(QueryInfo), q32.data(), nq * sizeof(QueryInfo));
-        memcpy(h + P.off_subst, a->subst, (size_t)A * A);
-        if (!P.empty_rows.empty())
-            memcpy(h + P.off_rows, P.empty_rows.data(), P.empty_rows.size() * sizeof(int32_t));
-        HIPCHK(hipMemcpyAsync(ws, h, P.table_bytes, hipMemcpyHostToDevice, st));
-        HIPCHK(hipEventRecord(S.ev, st));
-        S.pending = true;
+        const int urc = upload_tables(st, ws, P.table_bytes, [&](uint8_t *h) {
+            if (!P.units.empty()) memcpy(h + P.off_units, P.units.data(), P.units.size() * sizeof(SearchUnit));
+            if (!P.iunits.empty())
+                memcpy(h + P.off_iunits, P.iunits.data(), P.iunits.size() * sizeof(IntraUnit));
+            if (!P.order.empty()) memcpy(h + P.off_order, P.order.data(), P.order.size() * sizeof(int32_t));
+            memcpy(h + P.off_qinfo, P.qinfo.data(), nq * sizeof(QueryInfo));
+            memcpy(h + P.off_qinfo + nq * sizeof(QueryInfo), q32.data(), nq * sizeof(QueryInfo));
+            memcpy(h + P.off_subst, a->subst, (size_t)A * A);
+            if (!P.empty_rows.empty())
+                memcpy(h + P.off_rows, P.empty_rows.data(), P.empty_rows.size() * sizeof(int32_t));
+        });
+        if (urc) return urc;
     }
     if (phase == RUN_UPLOAD) return DSA_OK;
 
@@ -1879,6 +1882,68 @@ static int align_phase(const dsa_args *args, const dsa_out *out, int phase) {
 
 extern "C" int dsa_align_batch(const dsa_args *args, const dsa_out *out) {
     return align_phase(args, out, RUN_ALL);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free entry point: the workspace is a fixed device array of the
+// library, one copy per device.  In host code `scratch` names a host-side
+// stand-in; its device address comes from hipGetSymbolAddress, taken once
+// per device with that device current, and only that address reaches
+// kernels and copies.  Every call on a device shares the array (calls that
+// overlap on one device race); the kernels clear what has to start at zero.
+
+static __device__ __align__(256) uint8_t scratch[DSA_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+struct ScratchAddr {
+    std::once_flag once;
+    void *ptr = nullptr;
+    hipError_t err = hipSuccess;
+};
+ScratchAddr g_scratch[64];
+
+int scratch_get(int dev, uint8_t **out) {
+    if (dev < 0 || dev >= 64) return fail(DSA_E_DEVICE, "device index out of range for the static scratch");
+    ScratchAddr &S = g_scratch[dev];
+    std::call_once(S.once, [&] { S.err = hipGetSymbolAddress(&S.ptr, HIP_SYMBOL(scratch)); });
+    if (S.err != hipSuccess)
+        return fail(DSA_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(S.err));
+    if (!S.ptr || ((uintptr_t)S.ptr & 255)) return fail(DSA_E_DEVICE, "static scratch has no usable device address");
+    *out = (uint8_t *)S.ptr;
+    return DSA_OK;
+}
+
+struct NoallocScope {
+    NoallocScope() {
+        t_noalloc = true;
+        // boundary rows and direction-code chunks each take at most a
+        // quarter of the array, so rounds and chunks shrink to fit it
+        t_budget_cap = (int64_t)(DSA_NOALLOC_SCRATCH_BYTES / 4);
+    }
+    ~NoallocScope() {
+        t_noalloc = false;
+        t_budget_cap = 0;
+    }
+};
+}  // namespace
+
+extern "C" int dsa_align_batch_noalloc(const dsa_args *args, const dsa_out *out) {
+    if (!args) return fail(DSA_E_INVAL, "args is NULL");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    uint8_t *ws = nullptr;
+    int rc = scratch_get(dev, &ws);
+    if (rc) return rc;
+    dsa_args a = *args;
+    a.workspace = ws;
+    a.workspace_bytes = DSA_NOALLOC_SCRATCH_BYTES;
+    NoallocScope scope;
+    rc = align_phase(&a, out, RUN_ALL);
+    if (rc == DSA_E_WORKSPACE)
+        return fail(DSA_E_WORKSPACE, "dsa_align_batch_noalloc: the call needs more than the " +
+                                         std::to_string(DSA_NOALLOC_SCRATCH_BYTES) +
+                                         "-byte static scratch (" + g_err + ")");
+    return rc;
 }
 
 struct dsa_graph {
