@@ -66,6 +66,13 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
 
 
+def default_threads() -> int:
+    """Worker threads of a batch: the cores this process may run on, at most
+    DSA_ORACLE_THREADS (default 16, a one-GPU machine's share of its host)."""
+    cap = int(os.environ.get("DSA_ORACLE_THREADS", "16"))
+    return max(1, min(len(os.sched_getaffinity(0)), cap))
+
+
 def default_ends(mode: int, ends) -> int:
     if mode == SEMIGLOBAL:
         return TB | TE if not ends else int(ends)
@@ -86,7 +93,7 @@ def align_index(qi, ti, queries, targets, matrix, gap_open, gap_extend, mode="lo
     S = np.ascontiguousarray(matrix, dtype=np.int8)
     A = S.shape[0]
     if threads is None:
-        threads = len(os.sched_getaffinity(0))
+        threads = default_threads()
     score = np.zeros(n, np.int64)
     coords = np.zeros((n, 4), np.int32)
     n_ops = np.zeros(n, np.int32)

@@ -14,6 +14,7 @@ if HERE not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+    config.addinivalue_line("markers", "fullsize: full-size parity against the oracle (minutes of host time)")
 
 
 @pytest.fixture(scope="session")

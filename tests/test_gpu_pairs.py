@@ -248,44 +248,3 @@ def test_cfg4_reduced_full_parity(mode):
     got = gpu_pairs(c["queries"], c["targets"], c["matrix"], 10, 1, mode)
     exp = oracle.align_pairs(c["queries"], c["targets"], c["matrix"], 10, 1, mode=mode, traceback=True)
     compare_pairs(got, exp, True, f"cfg4 {mode}")
-
-
-def _sampled(got, c, idx, o, e, mode, label):
-    """Recompute the pairs `idx` with the oracle and compare them with the
-    GPU's results for the full batch."""
-    idx = [int(k) for k in idx]
-    exp = oracle.align_pairs(c["queries"].subset(idx), c["targets"].subset(idx), c["matrix"], o, e,
-                             mode=mode, traceback=True)
-    sub = {k: v[idx] for k, v in got.items() if isinstance(v, np.ndarray)}
-    sub["cigars"] = [got["cigars"][k] for k in idx]
-    compare_pairs(sub, exp, True, label)
-
-
-def _sample_idx(c, seed, n_random, n_largest):
-    cells = c["queries"].lengths.astype(np.int64) * c["targets"].lengths.astype(np.int64)
-    rng = np.random.default_rng([170101575, 60, seed])
-    return np.unique(np.concatenate([rng.integers(0, len(cells), size=n_random),
-                                     np.argsort(cells)[-n_largest:]]))
-
-
-def test_cfg3_full_size_sampled():
-    """All 100,000 read / window pairs (local, CIGAR) in one batched call,
-    the benchmark's launch configuration; 300 random pairs and the 5 largest
-    recomputed by the oracle."""
-    c = gen.cfg3()
-    log("cfg3 full size: 100,000 pairs, sampled")
-    got = gpu_pairs(c["queries"], c["targets"], c["matrix"], 5, 2, "local")
-    assert got["capacity_ok"]
-    _sampled(got, c, _sample_idx(c, 1, 300, 5), 5, 2, "local", "cfg3 full")
-
-
-@pytest.mark.parametrize("mode", ["global", "semiglobal"])
-def test_cfg4_full_size_sampled(mode):
-    """All 50,000 protein pairs (up to 3,000 x 3,000, CIGAR) in one batched
-    call, as the benchmark times them; 24 random pairs and the 4 largest
-    recomputed by the oracle."""
-    c = gen.cfg4()
-    log(f"cfg4 full size {mode}: 50,000 pairs, sampled")
-    got = gpu_pairs(c["queries"], c["targets"], c["matrix"], 10, 1, mode)
-    assert got["capacity_ok"]
-    _sampled(got, c, _sample_idx(c, 2, 24, 4), 10, 1, mode, f"cfg4 full {mode}")
