@@ -37,25 +37,35 @@ OP_CHARS = {OP_I: "I", OP_D: "D", OP_EQ: "=", OP_X: "X"}
 _lib = None
 
 
-def build(force: bool = False) -> str:
-    """Compile gotoh.c into liboracle.so with gcc."""
+SAN_LIB_PATH = os.path.join(HERE, "liboracle_san.so")
+
+
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile gotoh.c into liboracle.so with gcc (with sanitize: an
+    AddressSanitizer + UndefinedBehaviorSanitizer build, liboracle_san.so)."""
     src = os.path.join(HERE, "gotoh.c")
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
-        tmp = LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
+    path = SAN_LIB_PATH if sanitize else LIB_PATH
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+        tmp = path + ".tmp"
+        flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                 "-fno-sanitize-recover=undefined"] if sanitize else ["-O2"]
+        subprocess.check_call(["gcc", *flags, "-std=c11", "-fPIC", "-shared", "-pthread",
                                "-Wall", "-o", tmp, src])
-        os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+        os.replace(tmp, path)
+    return path
 
 
 def lib():
+    """The oracle library; DSA_ORACLE_SANITIZED=1 loads the sanitizer build
+    (the process must preload the sanitizer runtimes)."""
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(LIB_PATH)
+        san = os.environ.get("DSA_ORACLE_SANITIZED") == "1"
+        path = build(sanitize=san)
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         L.or_align_batch.restype = ctypes.c_int
-        L.or_align_batch.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_int32,
+        L.or_align_batch.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, P, ctypes.c_int32,
                                      ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P]
         _lib = L
@@ -80,10 +90,12 @@ def default_ends(mode: int, ends) -> int:
 
 
 def align_index(qi, ti, queries, targets, matrix, gap_open, gap_extend, mode="local",
-                ends=None, traceback=False, threads=None) -> dict:
+                ends=None, traceback=False, threads=None, pssm=None) -> dict:
     """Align pairs (queries[qi[k]], targets[ti[k]]) with the C oracle.
 
     queries/targets: objects with .codes (uint8) and .offsets (int64, n+1).
+    pssm: optional (total query residues, alphabet) int8 scores, one row per
+    query residue in the order of queries.codes, used instead of the matrix.
     Returns a dict of numpy arrays: score (int64), q_begin, q_end, t_begin,
     t_end (int32) and, with traceback, cigars (list of uint32 arrays)."""
     m = MODES[mode] if isinstance(mode, str) else int(mode)
@@ -92,6 +104,10 @@ def align_index(qi, ti, queries, targets, matrix, gap_open, gap_extend, mode="lo
     n = len(qi)
     S = np.ascontiguousarray(matrix, dtype=np.int8)
     A = S.shape[0]
+    if pssm is not None:
+        pssm = np.ascontiguousarray(pssm, dtype=np.int8)
+        if pssm.shape != (len(queries.codes), A):
+            raise ValueError("pssm must have one row of alphabet-size scores per query residue")
     if threads is None:
         threads = default_threads()
     score = np.zeros(n, np.int64)
@@ -108,7 +124,7 @@ def align_index(qi, ti, queries, targets, matrix, gap_open, gap_extend, mode="lo
             cig_off[1:] = np.cumsum(cig_cap)[:-1]
         cig = np.zeros(int(cig_cap.sum()) if n else 1, np.uint32)
     rc = lib().or_align_batch(n, _ptr(qi), _ptr(ti), _ptr(queries.codes), _ptr(queries.offsets),
-                              _ptr(targets.codes), _ptr(targets.offsets), _ptr(S), A,
+                              _ptr(targets.codes), _ptr(targets.offsets), _ptr(S), _ptr(pssm), A,
                               int(gap_open), int(gap_extend), m, default_ends(m, ends),
                               1 if traceback else 0, int(threads), _ptr(score), _ptr(coords),
                               _ptr(n_ops), _ptr(status), _ptr(cig), _ptr(cig_off), _ptr(cig_cap))
@@ -122,23 +138,23 @@ def align_index(qi, ti, queries, targets, matrix, gap_open, gap_extend, mode="lo
 
 
 def align_pairs(queries, targets, matrix, gap_open, gap_extend, mode="local", ends=None,
-                traceback=False, threads=None) -> dict:
+                traceback=False, threads=None, pssm=None) -> dict:
     """Pairwise: queries[k] vs targets[k]."""
     n = len(queries.offsets) - 1
     idx = np.arange(n, dtype=np.int64)
     return align_index(idx, idx, queries, targets, matrix, gap_open, gap_extend, mode, ends,
-                       traceback, threads)
+                       traceback, threads, pssm)
 
 
 def search(queries, targets, matrix, gap_open, gap_extend, mode="local", ends=None,
-           traceback=False, threads=None) -> dict:
+           traceback=False, threads=None, pssm=None) -> dict:
     """Every query vs every target, results query-major (n_q * n_t)."""
     nq = len(queries.offsets) - 1
     nt = len(targets.offsets) - 1
     qi = np.repeat(np.arange(nq, dtype=np.int64), nt)
     ti = np.tile(np.arange(nt, dtype=np.int64), nq)
     return align_index(qi, ti, queries, targets, matrix, gap_open, gap_extend, mode, ends,
-                       traceback, threads)
+                       traceback, threads, pssm)
 
 
 def cigar_string(ops) -> str:

@@ -14,6 +14,9 @@
  *   E[i][j] = max(E[i][j-1] - e, H[i][j-1] - o)      gap in the query (D, consumes b_j)
  *   F[i][j] = max(F[i-1][j] - e, H[i-1][j] - o)      gap in the target (I, consumes a_i)
  *   H[i][j] = max([0 if local], H[i-1][j-1] + S[a_i][b_j], E[i][j], F[i][j])
+ *   With a position-specific score profile P (one row of A scores per query
+ *   position; the extension point for user-defined scoring next to the
+ *   paper's algorithm template, Section II.C.2), S[a_i][b_j] is P[i][b_j].
  *
  *   Boundaries: H[0][0] = 0; E[i][0] = F[0][j] = -inf;
  *     local:      H[0][j] = H[i][0] = 0
@@ -85,14 +88,20 @@ typedef struct {
     int32_t status;  /* 0 ok, 1 CIGAR truncated, -1 bad arguments, -2 out of memory */
 } or_result;
 
+/* The score of query position i (1-based) against target code c. */
+static int64_t score_at(const uint8_t *a, const int8_t *S, const int8_t *P, int32_t A, int64_t i, uint8_t c) {
+    return P ? (int64_t)P[(i - 1) * A + c] : (int64_t)S[(int64_t)a[i - 1] * A + c];
+}
+
 /*
  * Align query a[0..m) with target b[0..n).
- * S is an A x A int8 matrix, row = query code, column = target code.
+ * S is an A x A int8 matrix, row = query code, column = target code; when P
+ * is not NULL it holds m rows of A scores, row i - 1 scoring query position i.
  * cigar (capacity cap, may be NULL when want_tb == 0) receives the run-length
  * encoded path, len << 4 | op, in forward order.
  */
 int or_align(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
-             const int8_t *S, int32_t A, int64_t o, int64_t e,
+             const int8_t *S, const int8_t *P, int32_t A, int64_t o, int64_t e,
              int32_t mode, int32_t ends, int32_t want_tb,
              uint32_t *cigar, int64_t cap, or_result *res)
 {
@@ -129,7 +138,7 @@ int or_align(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
             } else {
                 ev = max2(AT(E, i, j - 1) - e, AT(H, i, j - 1) - o);
                 fv = max2(AT(F, i - 1, j) - e, AT(H, i - 1, j) - o);
-                int64_t diag = AT(H, i - 1, j - 1) + (int64_t)S[(int64_t)a[i - 1] * A + b[j - 1]];
+                int64_t diag = AT(H, i - 1, j - 1) + score_at(a, S, P, A, i, b[j - 1]);
                 h = max2(diag, max2(ev, fv));
                 if (mode == OR_LOCAL) h = max2(h, 0);
             }
@@ -179,7 +188,7 @@ int or_align(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
                     while (i > 0) { rev[nrev++] = OP_I; i--; }
                     break;
                 }
-                int64_t s = S[(int64_t)a[i - 1] * A + b[j - 1]];
+                int64_t s = score_at(a, S, P, A, i, b[j - 1]);
                 if (AT(H, i, j) == AT(H, i - 1, j - 1) + s) {
                     rev[nrev++] = (a[i - 1] == b[j - 1]) ? OP_EQ : OP_X;
                     i--; j--;
@@ -226,7 +235,7 @@ typedef struct {
     const int64_t *qi, *ti;
     const uint8_t *q_codes; const int64_t *q_off;
     const uint8_t *t_codes; const int64_t *t_off;
-    const int8_t *S; int32_t A; int64_t o, e; int32_t mode, ends, want_tb;
+    const int8_t *S; const int8_t *P; int32_t A; int64_t o, e; int32_t mode, ends, want_tb;
     int64_t *score; int32_t *coords; int32_t *n_ops; int32_t *status;
     uint32_t *cigar; const int64_t *cig_off; const int64_t *cig_cap;
     int64_t next;
@@ -244,7 +253,8 @@ static void *batch_worker(void *p) {
         int64_t cap = (B->want_tb && B->cigar) ? B->cig_cap[k] : 0;
         int rc = or_align(B->q_codes + B->q_off[q], B->q_off[q + 1] - B->q_off[q],
                           B->t_codes + B->t_off[t], B->t_off[t + 1] - B->t_off[t],
-                          B->S, B->A, B->o, B->e, B->mode, B->ends, B->want_tb, cg, cap, &r);
+                          B->S, B->P ? B->P + B->q_off[q] * B->A : NULL,
+                          B->A, B->o, B->e, B->mode, B->ends, B->want_tb, cg, cap, &r);
         if (rc != 0) __atomic_store_n(&B->err, rc, __ATOMIC_RELAXED);
         B->score[k] = r.score;
         B->coords[4 * k + 0] = r.q_begin;
@@ -262,12 +272,13 @@ static void *batch_worker(void *p) {
  * k in [0, n) on n_threads threads.  Outputs per pair: score, coords (4 per
  * pair: q_begin, q_end, t_begin, t_end), and with want_tb the CIGAR runs at
  * cigar + cig_off[k] (capacity cig_cap[k]), run count n_ops[k], status[k].
- * Returns 0, or the first nonzero or_align code.
+ * pssm (NULL = score with S) holds a row of A scores per query residue, in
+ * the order of q_codes.  Returns 0, or the first nonzero or_align code.
  */
 int or_align_batch(int64_t n, const int64_t *qi, const int64_t *ti,
                    const uint8_t *q_codes, const int64_t *q_off,
                    const uint8_t *t_codes, const int64_t *t_off,
-                   const int8_t *S, int32_t A, int64_t o, int64_t e,
+                   const int8_t *S, const int8_t *pssm, int32_t A, int64_t o, int64_t e,
                    int32_t mode, int32_t ends, int32_t want_tb, int32_t n_threads,
                    int64_t *score, int32_t *coords, int32_t *n_ops, int32_t *status,
                    uint32_t *cigar, const int64_t *cig_off, const int64_t *cig_cap)
@@ -276,7 +287,7 @@ int or_align_batch(int64_t n, const int64_t *qi, const int64_t *ti,
     memset(&B, 0, sizeof(B));
     B.n = n; B.qi = qi; B.ti = ti;
     B.q_codes = q_codes; B.q_off = q_off; B.t_codes = t_codes; B.t_off = t_off;
-    B.S = S; B.A = A; B.o = o; B.e = e; B.mode = mode; B.ends = ends; B.want_tb = want_tb;
+    B.S = S; B.P = pssm; B.A = A; B.o = o; B.e = e; B.mode = mode; B.ends = ends; B.want_tb = want_tb;
     B.score = score; B.coords = coords; B.n_ops = n_ops; B.status = status;
     B.cigar = cigar; B.cig_off = cig_off; B.cig_cap = cig_cap;
     if (n_threads < 1) n_threads = 1;

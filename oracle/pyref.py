@@ -19,11 +19,19 @@ def _gap(o, e, L):
     return 0 if L == 0 else o + (L - 1) * e
 
 
-def ref_align(a, b, S, o, e, mode=LOCAL, ends=0, traceback=True):
+def ref_align(a, b, S, o, e, mode=LOCAL, ends=0, traceback=True, pssm=None):
     """Returns dict(score, q_begin, q_end, t_begin, t_end, ops) where ops is
-    a forward list of op characters ('=', 'X', 'I', 'D') or None."""
+    a forward list of op characters ('=', 'X', 'I', 'D') or None.  With pssm
+    (a row of scores per query position) residue i of a scores pssm[i][c]
+    against target code c instead of S[a[i]][c]."""
     a = [int(x) for x in a]
     b = [int(x) for x in b]
+    if pssm is None:
+        def sub(i, j):  # 1-based cell
+            return int(S[a[i - 1]][b[j - 1]])
+    else:
+        def sub(i, j):
+            return int(pssm[i - 1][b[j - 1]])
     m, n = len(a), len(b)
     if mode == SEMIGLOBAL and not ends:
         ends = TB | TE
@@ -52,7 +60,7 @@ def ref_align(a, b, S, o, e, mode=LOCAL, ends=0, traceback=True):
         for i in range(1, m + 1):
             E[i][j] = max(E[i][j - 1] - e, H[i][j - 1] - o)
             F[i][j] = max(F[i - 1][j] - e, H[i - 1][j] - o)
-            cand = [H[i - 1][j - 1] + int(S[a[i - 1]][b[j - 1]]), E[i][j], F[i][j]]
+            cand = [H[i - 1][j - 1] + sub(i, j), E[i][j], F[i][j]]
             if loc:
                 cand.append(0)
             H[i][j] = max(cand)
@@ -104,7 +112,7 @@ def ref_align(a, b, S, o, e, mode=LOCAL, ends=0, traceback=True):
                     ops.extend("I" * i)
                     i = 0
                 break
-            s = int(S[a[i - 1]][b[j - 1]])
+            s = sub(i, j)
             if h == H[i - 1][j - 1] + s:
                 ops.append("=" if a[i - 1] == b[j - 1] else "X")
                 i, j = i - 1, j - 1

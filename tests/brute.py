@@ -22,14 +22,20 @@ LOCAL, GLOBAL, SEMIGLOBAL = 0, 1, 2
 QB, QE, TB, TE = 1, 2, 4, 8
 
 
-def score_columns(a, b, S, o, e, i0, j0, cols):
+def _sub(a, b, S, pssm, i, j):
+    """Score of a[i] against b[j]: S[a[i]][b[j]], or with a position-specific
+    profile pssm[i][b[j]]."""
+    return int(pssm[i][b[j]]) if pssm is not None else int(S[a[i]][b[j]])
+
+
+def score_columns(a, b, S, o, e, i0, j0, cols, pssm=None):
     """Score of the column string `cols` starting at cell (i0, j0)."""
     i, j = i0, j0
     total = 0
     prev = None
     for c in cols:
         if c == "M":
-            total += int(S[a[i]][b[j]])
+            total += _sub(a, b, S, pssm, i, j)
             i += 1
             j += 1
         elif c == "I":
@@ -42,7 +48,7 @@ def score_columns(a, b, S, o, e, i0, j0, cols):
     return total, i, j
 
 
-def enumerate_alignments(a, b, S, o, e, mode, ends=0):
+def enumerate_alignments(a, b, S, o, e, mode, ends=0, pssm=None):
     """Yield (score, start(i0,j0), end(i1,j1), cols) for every allowed alignment.
 
     Coordinates are DP cells: the alignment consumes a[i0..i1) and b[j0..j1)."""
@@ -81,14 +87,14 @@ def enumerate_alignments(a, b, S, o, e, mode, ends=0):
             if end_ok(i, j):
                 yield sc, (i0, j0), (i, j), cols
             if i < m and j < n:
-                stack.append((i + 1, j + 1, "M", sc + int(S[a[i]][b[j]]), cols + "M"))
+                stack.append((i + 1, j + 1, "M", sc + _sub(a, b, S, pssm, i, j), cols + "M"))
             if i < m:
                 stack.append((i + 1, j, "I", sc - (e if prev == "I" else o), cols + "I"))
             if j < n:
                 stack.append((i, j + 1, "D", sc - (e if prev == "D" else o), cols + "D"))
 
 
-def brute(a, b, S, o, e, mode, ends=0):
+def brute(a, b, S, o, e, mode, ends=0, pssm=None):
     """Best score, the set of end cells attaining it, and the set of optimal
     (start, cols) paths.  Local: score 0 means no alignment (empty sets)."""
     a = [int(x) for x in a]
@@ -96,7 +102,7 @@ def brute(a, b, S, o, e, mode, ends=0):
     best = None
     ends_set = set()
     paths = set()
-    for sc, st, en, cols in enumerate_alignments(a, b, S, o, e, mode, ends):
+    for sc, st, en, cols in enumerate_alignments(a, b, S, o, e, mode, ends, pssm):
         if best is None or sc > best:
             best = sc
             ends_set = {en}
