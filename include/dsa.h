@@ -11,7 +11,8 @@
  * CIGAR; per-query top-K selection follows Section II.B.2.
  *
  * Definitions (shared by every entry point):
- *   codes        sequences are arrays of uint8 codes < alphabet_size (<= 32)
+ *   codes        sequences are arrays of uint8 codes < alphabet_size (<= 64;
+ *                searches over more than 32 letters run the exact int32 kernel)
  *   subst        alphabet_size x alphabet_size int8 matrix, row = query code,
  *                column = target code
  *   gaps         a run of L gap columns costs gap_open + (L-1) * gap_extend,
@@ -35,13 +36,17 @@
  *
  * Memory: pointers marked [dev] are device pointers on the current HIP
  * device, [host] are host pointers.  The caller owns every input and output
- * buffer.  The library owns only a dsa_db (device memory allocated by
- * dsa_db_create, released by dsa_db_destroy) and a small pinned staging
- * buffer per device for work tables.
+ * buffer.  The library owns only a dsa_db (device memory taken by
+ * dsa_db_create from the caller's allocator, or hipMalloc without one, and
+ * released by dsa_db_destroy) and a small pinned staging buffer per device
+ * for work tables.
  *
  * Streams: dsa_align_batch enqueues its copies and kernels on args->stream
  * (a hipStream_t, NULL = default stream) and returns without waiting;
- * outputs are valid once that stream has been synchronised.  It performs no
+ * outputs are valid once that stream has been synchronised.  One exception:
+ * a top-K search with DSA_TRACEBACK reads its hit list back to the host to
+ * plan the traceback of the hits, so it waits for args->stream once, in the
+ * middle of the call (and cannot be recorded into a graph).  It performs no
  * device allocation: all scratch memory is the caller's workspace.
  *
  * Errors: every entry point returns a dsa_status; no C++ exception crosses
@@ -59,7 +64,7 @@ extern "C" {
 #endif
 
 /* raised whenever a struct layout or a signature below changes */
-#define DSA_ABI_VERSION 2
+#define DSA_ABI_VERSION 4
 
 typedef enum {
     DSA_OK = 0,
@@ -86,24 +91,43 @@ enum { DSA_QB = 1, DSA_QE = 2, DSA_TB = 4, DSA_TE = 8 };
 typedef struct dsa_db dsa_db;
 
 /*
+ * Device memory supplied by the caller (for example a framework's caching
+ * allocator): alloc(bytes, ctx) returns device memory on the current device,
+ * at least 16-byte aligned, or NULL on failure; free(ptr, ctx) gives it back.
+ * Both are called on the thread that calls dsa_db_create / dsa_db_destroy.
+ */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} dsa_allocator;
+
+/*
  * dsa_db_create - pack a target database into device memory (Section II.B.1
  * "Map": the reference set is converted once into a layout suited to the
  * parallel workers and kept memory-resident, Section II.A).
  *   codes      [host] concatenated target codes, offsets[n_targets] bytes
  *   offsets    [host] n_targets + 1 int64 offsets, non-decreasing, offsets[0] = 0
  *   n_targets  >= 1
- *   alphabet_size  2..32; every code must be < alphabet_size
+ *   alphabet_size  2..64; every code must be < alphabet_size
+ *   alloc      [host] the allocator every device buffer of the database comes
+ *              from (copied; its ctx must stay valid until dsa_db_destroy),
+ *              or NULL for hipMalloc / hipFree
  *   stream     hipStream_t for the uploads (the call synchronises it)
  *   out        receives the handle
  * Targets are sorted by length into groups of 128 (two per lane of a
  * 64-wide wave), their codes interleaved so a wave reads 8 bytes per lane
- * per 4 columns.  Errors: DSA_E_INVAL, DSA_E_DEVICE.
+ * per 4 columns.  Errors: DSA_E_INVAL (also an allocator with alloc or free
+ * NULL, or memory not 16-byte aligned), DSA_E_DEVICE (also alloc returning
+ * NULL), DSA_E_NOTSUP (a target longer than 65,532 residues).  On an error
+ * every buffer already taken is given back.
  */
 int dsa_db_create(const uint8_t *codes, const int64_t *offsets, int64_t n_targets,
-                  int32_t alphabet_size, void *stream, dsa_db **out);
+                  int32_t alphabet_size, const dsa_allocator *alloc, void *stream, dsa_db **out);
 
-/* dsa_db_destroy - free a database (NULL is accepted).  Not stream-ordered:
- * the caller must make sure no enqueued work still reads it. */
+/* dsa_db_destroy - free a database (NULL is accepted), through the allocator
+ * it was created with.  Not stream-ordered: the caller must make sure no
+ * enqueued work still reads it. */
 int dsa_db_destroy(dsa_db *db);
 
 /* Number of targets, total residues and device bytes held by a database. */
@@ -119,8 +143,13 @@ typedef struct {
     const uint8_t *t_codes;    /* [dev]  pairwise: query k vs target k */
     const int64_t *t_offsets;  /* [host] n_q + 1 offsets into t_codes */
     /* scoring */
-    const int8_t *subst;       /* [host] alphabet_size^2, row = query code */
-    int32_t alphabet_size;     /* 2..32; must equal the database's */
+    const int8_t *subst;       /* [host] alphabet_size^2, row = query code (may be NULL with pssm) */
+    const int8_t *pssm;        /* [host] position-specific profile, or NULL: one row of alphabet_size
+                                  scores per query residue, rows in q_codes order; residue i of a
+                                  query then scores pssm[row][c] against target code c in place of
+                                  subst[code][c] (the scoring hook beside the paper's user-defined
+                                  algorithms, Section II.C.2); '=' and 'X' still compare codes */
+    int32_t alphabet_size;     /* 2..64; must equal the database's */
     int32_t gap_open;          /* >= gap_extend >= 0 */
     int32_t gap_extend;
     int32_t mode;              /* DSA_LOCAL | DSA_GLOBAL | DSA_SEMIGLOBAL */
@@ -173,12 +202,22 @@ int dsa_cigar_capacity(const dsa_args *args, int64_t *entries);
 
 /*
  * dsa_align_batch - align (Sections II.B.1 and II.C.2; top-K per
- * Section II.B.2).  Asynchronous on args->stream.  Scores are exact: a
- * packed int16 pass is followed by an exact int32 rerun of every result
- * that could have saturated (local search: every score above 29568, the
- * exact range of its offset int16 values; global / semi-global: every score
- * at either int16 bound), and these carry DSA_ST_INT32.  A local search with
- * gap_open above 1024 runs the int32 kernel throughout.
+ * Section II.B.2).  Asynchronous on args->stream, except that a top-K search
+ * with DSA_TRACEBACK waits once for the stream (its hit list is read back to
+ * plan the hits' traceback).  Scores are exact.  A database search runs a
+ * packed int16 pass followed by an exact int32 rerun of every result that
+ * could have saturated, and these results carry DSA_ST_INT32:
+ *   local        every score above 28,544, the exact range of the offset
+ *                int16 values the local kernels hold;
+ *   global, semi-global
+ *                every query whose host bound (3 gap_open + (m + n) gap_extend
+ *                + |min S|, or min(sum of row maxima, sum of column maxima))
+ *                leaves the int16 range goes to int32 at once, and every
+ *                score at either int16 bound is rerun.
+ * These searches run the int32 kernel throughout: DSA_FORCE_INT32; a free
+ * query end (semi-global with DSA_QE); a local search with gap_open above
+ * 1024 or gap_extend above 256.  Pairwise alignment (and the traceback of
+ * top-K hits) runs exact int32 kernels throughout.
  * Errors: DSA_E_INVAL, DSA_E_RANGE, DSA_E_WORKSPACE, DSA_E_NOTSUP,
  * DSA_E_DEVICE.
  */
@@ -301,6 +340,45 @@ int dsa_timing_reset(void);
  * search produces (must be 0; size is ignored but must be positive).
  */
 int dsa_probe(int which, int64_t size, double *rate);
+
+/*
+ * Sequence ingest (Section II.C.1: the data API reads FASTA and FASTQ files;
+ * Section II.B.1: a converter maps them into the workers' layout).  A
+ * dsa_seqset collects records streamed as text in pieces of any size and
+ * maps residues to codes; its codes and offsets go to dsa_db_create (a
+ * database) or to dsa_args (queries).  Host memory only; no device work.
+ *   alphabets  DSA_ALPHA_PROTEIN: A R N D C Q E G H I L K M F P S T W Y V B Z X *
+ *              -> 0..23 (BLOSUM62's order), other letters -> X (22);
+ *              DSA_ALPHA_DNA: A C G T -> 0..3, U -> T, other letters -> N (4).
+ *              Case-insensitive; on sequence lines every other byte (space,
+ *              tab, CR, digit, '-', '.') is skipped.
+ *   formats    decided by the first non-blank byte: '>' FASTA (header line,
+ *              then sequence lines up to the next '>' at a line start), '@'
+ *              FASTQ (header, sequence lines up to a '+' line, then quality
+ *              lines holding exactly as many bytes as residues; a quality
+ *              line may start with '@' or '+').  Qualities are not kept.
+ *   names      a record's name is its header line after '>' or '@', without
+ *              a trailing CR.
+ * dsa_seqset_feed may be called with any split of the text; dsa_seqset_finish
+ * ends the input (the last record may lack a final newline).
+ * dsa_seqset_read_file feeds a whole file in 4 MiB pieces and finishes.
+ * dsa_seqset_codes and dsa_seqset_name return pointers into the set, valid
+ * until dsa_seqset_destroy (names are not NUL-terminated).
+ * Errors: DSA_E_INVAL (bad argument, unreadable file, text before the first
+ * header, a FASTQ record without its '+' line or with a quality of another
+ * length than its sequence; dsa_last_error names the line or record).
+ */
+enum { DSA_ALPHA_PROTEIN = 1, DSA_ALPHA_DNA = 2 };
+enum { DSA_FORMAT_NONE = 0, DSA_FORMAT_FASTA = 1, DSA_FORMAT_FASTQ = 2 };
+typedef struct dsa_seqset dsa_seqset;
+int dsa_seqset_create(int32_t alphabet, dsa_seqset **out);
+int dsa_seqset_feed(dsa_seqset *set, const char *bytes, size_t len);
+int dsa_seqset_finish(dsa_seqset *set);
+int dsa_seqset_read_file(dsa_seqset *set, const char *path);
+int dsa_seqset_info(const dsa_seqset *set, int64_t *n_seqs, int64_t *n_residues, int32_t *format);
+int dsa_seqset_codes(const dsa_seqset *set, const uint8_t **codes, const int64_t **offsets);
+int dsa_seqset_name(const dsa_seqset *set, int64_t index, const char **name, int64_t *len);
+int dsa_seqset_destroy(dsa_seqset *set);
 
 const char *dsa_strerror(int status);
 const char *dsa_last_error(void);

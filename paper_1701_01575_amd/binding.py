@@ -9,14 +9,18 @@ import ctypes
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libdsa.so")
-ABI_VERSION = 2  # DSA_ABI_VERSION of the include/dsa.h the structs here mirror
+# DSA_LIBRARY names another build of the library (the host-sanitized one of
+# the CPU sanitizer tests); by default the in-tree build is loaded
+LIB_PATH = os.environ.get("DSA_LIBRARY") or os.path.join(PKG, "libdsa.so")
+ABI_VERSION = 4  # DSA_ABI_VERSION of the include/dsa.h the structs here mirror
 
 DSA_OK, DSA_E_INVAL, DSA_E_RANGE, DSA_E_WORKSPACE, DSA_E_CAPACITY, DSA_E_DEVICE, DSA_E_NOTSUP = range(7)
 DSA_LOCAL, DSA_GLOBAL, DSA_SEMIGLOBAL = 0, 1, 2
 DSA_QB, DSA_QE, DSA_TB, DSA_TE = 1, 2, 4, 8
 DSA_TRACEBACK, DSA_PLAIN, DSA_FORCE_INT32 = 1, 2, 4
 DSA_ST_INT32, DSA_ST_TRUNCATED = 1, 2
+DSA_ALPHA_PROTEIN, DSA_ALPHA_DNA = 1, 2
+DSA_FORMAT_NONE, DSA_FORMAT_FASTA, DSA_FORMAT_FASTQ = 0, 1, 2
 
 EXPORTS = ["dsa_db_create", "dsa_db_destroy", "dsa_db_info", "dsa_workspace_size",
            "dsa_cigar_capacity", "dsa_align_batch", "dsa_align_batch_noalloc", "dsa_graph_create", "dsa_graph_launch",
@@ -24,6 +28,8 @@ EXPORTS = ["dsa_db_create", "dsa_db_destroy", "dsa_db_info", "dsa_workspace_size
            "dsa_timing_enable", "dsa_timing_read",
            "dsa_timing_reset",
            "dsa_probe",
+           "dsa_seqset_create", "dsa_seqset_feed", "dsa_seqset_finish", "dsa_seqset_read_file",
+           "dsa_seqset_info", "dsa_seqset_codes", "dsa_seqset_name", "dsa_seqset_destroy",
            "dsa_strerror", "dsa_last_error", "dsa_abi_version"]
 
 
@@ -42,6 +48,7 @@ class dsa_args(ctypes.Structure):
         ("t_codes", ctypes.c_void_p),
         ("t_offsets", ctypes.c_void_p),
         ("subst", ctypes.c_void_p),
+        ("pssm", ctypes.c_void_p),
         ("alphabet_size", ctypes.c_int32),
         ("gap_open", ctypes.c_int32),
         ("gap_extend", ctypes.c_int32),
@@ -52,6 +59,18 @@ class dsa_args(ctypes.Structure):
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
+    ]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class dsa_allocator(ctypes.Structure):
+    _fields_ = [
+        ("alloc", ALLOC_FN),
+        ("free", FREE_FN),
+        ("ctx", ctypes.c_void_p),
     ]
 
 
@@ -82,7 +101,8 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.c_void_p
-        L.dsa_db_create.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_void_p)]
+        L.dsa_db_create.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(dsa_allocator), P,
+                                    ctypes.POINTER(ctypes.c_void_p)]
         L.dsa_db_destroy.argtypes = [P]
         L.dsa_db_info.argtypes = [P, P, P, P]
         L.dsa_workspace_size.argtypes = [ctypes.POINTER(dsa_args), ctypes.POINTER(ctypes.c_size_t)]
@@ -94,6 +114,15 @@ def lib():
                                       ctypes.POINTER(ctypes.c_int64)]
         L.dsa_timing_reset.argtypes = []
         L.dsa_probe.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+        L.dsa_seqset_create.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]
+        L.dsa_seqset_feed.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
+        L.dsa_seqset_finish.argtypes = [P]
+        L.dsa_seqset_read_file.argtypes = [P, ctypes.c_char_p]
+        L.dsa_seqset_info.argtypes = [P, P, P, P]
+        L.dsa_seqset_codes.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]
+        L.dsa_seqset_name.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.POINTER(ctypes.c_int64)]
+        L.dsa_seqset_destroy.argtypes = [P]
         L.dsa_strerror.argtypes = [ctypes.c_int]
         L.dsa_strerror.restype = ctypes.c_char_p
         L.dsa_last_error.argtypes = []
@@ -115,9 +144,11 @@ def check(status: int, where: str):
         raise DsaError(status, where, detail)
 
 
-def dsa_db_create(codes_ptr, offsets_ptr, n_targets, alphabet_size, stream):
+def dsa_db_create(codes_ptr, offsets_ptr, n_targets, alphabet_size, stream, allocator=None):
+    """allocator: a dsa_allocator (kept alive by the caller) or None for hipMalloc."""
     handle = ctypes.c_void_p()
-    check(lib().dsa_db_create(codes_ptr, offsets_ptr, n_targets, alphabet_size, stream,
+    check(lib().dsa_db_create(codes_ptr, offsets_ptr, n_targets, alphabet_size,
+                              ctypes.byref(allocator) if allocator is not None else None, stream,
                               ctypes.byref(handle)), "dsa_db_create")
     return handle.value
 
@@ -239,6 +270,47 @@ def dsa_probe(which: int, size: int) -> float:
     r = ctypes.c_double()
     check(lib().dsa_probe(which, size, ctypes.byref(r)), "dsa_probe")
     return r.value
+
+
+def dsa_seqset_create(alphabet: int):
+    h = ctypes.c_void_p()
+    check(lib().dsa_seqset_create(alphabet, ctypes.byref(h)), "dsa_seqset_create")
+    return h.value
+
+
+def dsa_seqset_feed(handle, data: bytes) -> None:
+    check(lib().dsa_seqset_feed(handle, data, len(data)), "dsa_seqset_feed")
+
+
+def dsa_seqset_finish(handle) -> None:
+    check(lib().dsa_seqset_finish(handle), "dsa_seqset_finish")
+
+
+def dsa_seqset_read_file(handle, path: str) -> None:
+    check(lib().dsa_seqset_read_file(handle, os.fsencode(path)), "dsa_seqset_read_file")
+
+
+def dsa_seqset_info(handle):
+    n, r, f = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+    check(lib().dsa_seqset_info(handle, ctypes.byref(n), ctypes.byref(r), ctypes.byref(f)), "dsa_seqset_info")
+    return n.value, r.value, f.value
+
+
+def dsa_seqset_codes(handle):
+    """(codes address, offsets address) borrowed from the set."""
+    c, o = ctypes.c_void_p(), ctypes.c_void_p()
+    check(lib().dsa_seqset_codes(handle, ctypes.byref(c), ctypes.byref(o)), "dsa_seqset_codes")
+    return c.value, o.value
+
+
+def dsa_seqset_name(handle, k: int) -> bytes:
+    p, n = ctypes.c_void_p(), ctypes.c_int64()
+    check(lib().dsa_seqset_name(handle, k, ctypes.byref(p), ctypes.byref(n)), "dsa_seqset_name")
+    return ctypes.string_at(p.value, n.value) if n.value else b""
+
+
+def dsa_seqset_destroy(handle) -> None:
+    check(lib().dsa_seqset_destroy(handle), "dsa_seqset_destroy")
 
 
 def dsa_strerror(status: int) -> str:

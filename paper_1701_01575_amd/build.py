@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdsa.so")
-SOURCES = ["search.hip", "intra.hip", "pair.hip", "topk.hip", "probe.hip", "runtime.hip"]
+SOURCES = ["search.hip", "intra.hip", "pair.hip", "topk.hip", "probe.hip", "runtime.hip", "ingest.cpp"]
 ARCH = os.environ.get("DSA_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -26,15 +26,19 @@ def sources():
     return [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
-    """Compile every source to an object (in parallel), then link libdsa.so."""
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+def build(verbose: bool = False, jobs: int = 4, extra_flags=(), lib_path: str = LIB) -> str:
+    """Compile every source to an object (in parallel), then link libdsa.so
+    (or lib_path, with extra_flags on every compile and the link)."""
+    hipcc = HIPCC
     objdir = tempfile.mkdtemp(prefix="dsa_build_")
     procs = []
     objs = []
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmd = [hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
+        cmd = [hipcc, *HIPCC_FLAGS, *extra_flags, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), file=sys.stderr)
         procs.append((subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT), src))
@@ -43,16 +47,17 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
             _wait(procs)
             procs = []
     _wait(procs)
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    tmp = lib_path + ".tmp"
+    cmd = [hipcc, f"--offload-arch={ARCH}", *extra_flags, "-shared", "-fPIC", "-o", tmp, *objs,
+           "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
     out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if out.returncode != 0:
         raise RuntimeError("link failed:\n" + out.stdout)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib_path)
     for o in objs:
         os.remove(o)
     os.rmdir(objdir)
-    return LIB
+    return lib_path
 
 
 def _wait(procs):

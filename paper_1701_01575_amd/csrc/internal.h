@@ -8,7 +8,8 @@ namespace dsa {
 constexpr int kWave = 64;
 constexpr int kGroup = 128;          // targets per group: 64 lanes x 2 int16 halves
 constexpr int kPadLen = 4;           // group column count is a multiple of this
-constexpr int kMaxAlphabet = 32;
+constexpr int kMaxAlphabet = 64;     // the int32 kernels' (A + 1)^2 LDS tables stay small
+constexpr int kMaxAlphabet16 = 32;   // the int16 search's pair profiles in LDS: larger alphabets run int32
 constexpr int kMaxLen16 = 65532;     // int16 kernels index rows/columns with uint16
 constexpr int kT32 = 16;             // strip height of the int32 kernels
 constexpr int32_t kKsBase = 1 << 29;  // work-list code of strip-pipelined units
@@ -38,6 +39,18 @@ __device__ __forceinline__ int lane_above(int v) {
     return __builtin_amdgcn_update_dpp(0, v, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
 }
 enum Ends { QB = 1, QE = 2, TB = 4, TE = 8 };
+
+// Score of query residue gi (an index into the query code buffer) of query
+// q against target code t: its residue's matrix row, or, when a
+// position-specific profile is given, its own profile row.  The device
+// profile holds rows of A + 1 int8 (the last column is padding), each query's
+// rows followed by one padding row, so query q's row i is row
+// q_off + q + i and its padding row is row q_off + q + m.
+__device__ __forceinline__ int qscore(const int8_t *pssm, const int8_t *subst, const uint8_t *q_codes, int A,
+                                      int64_t gi, int q, int t) {
+    return pssm ? (int)pssm[(gi + q) * (A + 1) + t] : (int)subst[min((int)q_codes[gi], A - 1) * A + t];
+}
+constexpr int kPssmPad = -128;   // score of the profile's padding row and column
 
 // One group of 128 length-sorted targets.
 struct GroupInfo {
@@ -73,6 +86,7 @@ struct SearchArgs {
     const uint8_t *q_codes;
     const QueryInfo *qinfo;
     const int8_t *subst;          // A*A
+    const int8_t *pssm;           // position-specific profile (rows of A + 1), or null
     const SearchUnit *units;
     int32_t n_units;
     int32_t A, AP, o, e, ends;
@@ -120,6 +134,7 @@ struct IntraArgs {
     const QueryInfo *qinfo;       // strips counted in rows of kTI
     const uint8_t *q_codes;
     const int8_t *subst;
+    const int8_t *pssm;           // position-specific profile (rows of A + 1), or null
     const uint8_t *inv_map;
     int32_t A, AP, o, e, ends;
     uint2 *bnd;
@@ -156,6 +171,7 @@ constexpr int kWfBlock = 16;      // steps per lane per block of wavefront direc
 struct PairInfo {
     int64_t q_off, t_off;         // into the query / target code buffers
     int64_t cig_off;              // first uint32 of this pair's CIGAR region
+    int64_t pssm_row;             // position-specific profile: the query's first row
     int32_t m, n;
     int32_t res;                  // output index (caller order)
     int32_t cig_cap;              // CIGAR region capacity (uint32 runs)
@@ -195,6 +211,7 @@ struct PairArgs {
     int32_t n_waves;
     const uint8_t *q_codes, *t_codes;
     const int8_t *subst;
+    const int8_t *pssm;           // position-specific profile (PairInfo.pssm_row), or null
     int32_t A, o, e, ends;
     int32_t traceback;
     uint32_t *tb;                 // direction codes, 4 bits per cell
@@ -241,6 +258,7 @@ struct BoundArgs {
     const QueryInfo *qinfo;
     int32_t n_q;
     const int8_t *subst;
+    const int8_t *pssm;
     int32_t A;
     const uint8_t *inv_map;
     int32_t AP;
@@ -255,6 +273,7 @@ struct ProfileArgs {
     const QueryInfo *qinfo;       // prof offsets ascending
     int32_t n_q;
     const int8_t *subst;
+    const int8_t *pssm;
     int32_t A, AP;
     const uint8_t *inv_map;
     const uint8_t *pair_dec;

@@ -75,7 +75,9 @@ __device__ __forceinline__ void intra16_run(const IntraArgs &P, const IntraUnit 
             const int i = pass * kPassRows + r;
             int v = NEG16;
             const int mc = P.inv_map[c];
-            if (i < m && mc != 0xff) v = sub[min((int)qc[i], A - 1) * A + mc] + (SHIFT ? e : 0);
+            if (i < m && mc != 0xff)
+                v = (P.pssm ? (int)P.pssm[(Q.off + U.q + i) * (A + 1) + mc] : (int)sub[min((int)qc[i], A - 1) * A + mc]) +
+                    (SHIFT ? e : 0);
             qp[c * kProfStride + r] = (int16_t)v;
         }
         __syncthreads();

@@ -63,7 +63,7 @@ __device__ __forceinline__ void ks16_unit(const SearchArgs &P, const SearchUnit 
             const int i = r * rows + rr;
             int v = NEG16;
             const int mc = P.inv_map[c];
-            if (i < m && mc != 0xff) v = P.subst[min((int)qc[i], A - 1) * A + mc] + e;
+            if (i < m && mc != 0xff) v = qscore(P.pssm, P.subst, P.q_codes, A, Q.off + i, U.q, mc) + e;
             b[c * stride + rr] = (int16_t)v;
         }
     };

@@ -61,14 +61,19 @@ hipError_t launch_pack_targets(const PairArgs &a, int64_t n_words, hipStream_t s
     return hipGetLastError();
 }
 
-template <int MODE, bool TB>
+// PS: scores from the position-specific profile (the pair's query rows, its
+// padding row for rows past the query and column A past the target), read
+// from global memory; otherwise from the (A+1) x (A+1) matrix in LDS.
+template <int MODE, bool TB, bool PS>
 __global__ void __launch_bounds__(kPairWaves * kWave) k_pair32(PairArgs P) {
     constexpr int T = kTP;
     extern __shared__ int32_t sm[];
     const int A = P.A, SS = P.A + 1;
-    for (int k = threadIdx.x; k < SS * SS; k += blockDim.x) {
-        const int r = k / SS, c = k - r * SS;
-        sm[k] = (r < A && c < A) ? (int)P.subst[r * A + c] : PAD32;
+    if (!PS) {
+        for (int k = threadIdx.x; k < SS * SS; k += blockDim.x) {
+            const int r = k / SS, c = k - r * SS;
+            sm[k] = (r < A && c < A) ? (int)P.subst[r * A + c] : PAD32;
+        }
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -83,6 +88,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pair32(PairArgs P) {
     const int m = I.m, n = I.n, S = G.strips;
     const int Sl = (m + T - 1) / T;  // this lane's own strip count (<= S)
     const uint8_t *qc = P.q_codes + I.q_off;
+    const int8_t *prow = PS ? P.pssm + I.pssm_row * SS : nullptr;
     const uint32_t *tw = P.tpk + G.tpk + lane;
     uint2 *bnd = P.bnd + G.bnd + lane;
     uint32_t *tb = P.tb + G.tb + lane;
@@ -99,7 +105,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pair32(PairArgs P) {
 #pragma unroll
         for (int r = 0; r < T; r++) {
             const int i = i0 + r;
-            rowb[r] = (i < m ? min((int)qc[i], A - 1) : A) * SS;
+            rowb[r] = PS ? min(i, m) * SS : (i < m ? min((int)qc[i], A - 1) : A) * SS;
             H[r] = left_value(MODE, ends, o, e, i + 1);
             E[r] = H[r] - o;
         }
@@ -158,7 +164,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pair32(PairArgs P) {
                 eN[1] = 0u;
 #pragma unroll
                 for (int r = 0; r < T; r++) {
-                    const int t = Hd + sm[rowb[r] + b];
+                    const int t = Hd + (PS ? (int)prow[rowb[r] + b] : sm[rowb[r] + b]);
                     Hd = H[r];
                     const int Ein = E[r], Fin = F;
                     int h = max(max(t, Ein), Fin);
@@ -245,13 +251,17 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pair32(PairArgs P) {
 hipError_t launch_pair32(const PairArgs &a, int mode, hipStream_t s) {
     if (a.n_groups <= 0) return hipSuccess;
     const int nb = (a.n_groups + kPairWaves - 1) / kPairWaves;
-    const size_t lds = pair32_lds_bytes(a.A);
-#define LP(MODE, TBV) hipLaunchKernelGGL((k_pair32<MODE, TBV>), dim3(nb), dim3(kPairWaves * kWave), lds, s, a)
-    if (a.traceback) {
-        if (mode == LOCAL) LP(LOCAL, true); else if (mode == GLOBAL) LP(GLOBAL, true); else LP(SEMIGLOBAL, true);
+    const size_t lds = a.pssm ? 16 : pair32_lds_bytes(a.A);
+#define LP(MODE, TBV, PSV) \
+    hipLaunchKernelGGL((k_pair32<MODE, TBV, PSV>), dim3(nb), dim3(kPairWaves * kWave), lds, s, a)
+#define LPM(TBV, PSV) \
+    if (mode == LOCAL) LP(LOCAL, TBV, PSV); else if (mode == GLOBAL) LP(GLOBAL, TBV, PSV); else LP(SEMIGLOBAL, TBV, PSV)
+    if (a.pssm) {
+        if (a.traceback) { LPM(true, true); } else { LPM(false, true); }
     } else {
-        if (mode == LOCAL) LP(LOCAL, false); else if (mode == GLOBAL) LP(GLOBAL, false); else LP(SEMIGLOBAL, false);
+        if (a.traceback) { LPM(true, false); } else { LPM(false, false); }
     }
+#undef LPM
 #undef LP
     return hipGetLastError();
 }
@@ -296,14 +306,16 @@ __device__ __forceinline__ int row_of(const int (&H)[T], int r) {
     return v;
 }
 
-template <int MODE, bool TB>
+template <int MODE, bool TB, bool PS>
 __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
     constexpr int T = kTP;
     extern __shared__ int32_t sm[];
     const int A = P.A, SS = P.A + 1;
-    for (int k = threadIdx.x; k < SS * SS; k += blockDim.x) {
-        const int r = k / SS, c = k - r * SS;
-        sm[k] = (r < A && c < A) ? (int)P.subst[r * A + c] : PAD32;
+    if (!PS) {
+        for (int k = threadIdx.x; k < SS * SS; k += blockDim.x) {
+            const int r = k / SS, c = k - r * SS;
+            sm[k] = (r < A && c < A) ? (int)P.subst[r * A + c] : PAD32;
+        }
     }
     __syncthreads();
     const int vw = blockIdx.x * kPairWaves + (threadIdx.x >> 6);
@@ -320,6 +332,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
     const int S = (m + T - 1) / T, passes = (S + SEG - 1) / SEG;
     const int nsteps = n + SEG - 1;
     const uint8_t *qc = P.q_codes + I.q_off, *tc = P.t_codes + I.t_off;
+    const int8_t *prow = PS ? P.pssm + I.pssm_row * SS : nullptr;
     uint2 *bnd = P.bnd + W.bnd;
     uint2 *tb = reinterpret_cast<uint2 *>(P.tb) + W.tb + lane * kWfBlock;
     const int nblk = (nsteps + kWfBlock - 1) / kWfBlock;
@@ -337,7 +350,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
 #pragma unroll
         for (int r = 0; r < T; r++) {
             const int i = i0 + r;
-            rowb[r] = (i < m ? min((int)qc[i], A - 1) : A) * SS;
+            rowb[r] = PS ? min(i, m) * SS : (i < m ? min((int)qc[i], A - 1) : A) * SS;
             H[r] = left_value(MODE, ends, o, e, i + 1);
             E[r] = H[r] - o;
         }
@@ -382,7 +395,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
                 eN[1] = 0u;
 #pragma unroll
                 for (int r = 0; r < T; r++) {
-                    const int tv = Hd + sm[rowb[r] + b];
+                    const int tv = Hd + (PS ? (int)prow[rowb[r] + b] : sm[rowb[r] + b]);
                     Hd = H[r];
                     const int Ein = E[r], Fin = F;
                     int h = max(max(tv, Ein), Fin);
@@ -492,13 +505,17 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
 hipError_t launch_pairwf(const PairArgs &a, int mode, hipStream_t s) {
     if (a.n_waves <= 0) return hipSuccess;
     const int nb = (a.n_waves + kPairWaves - 1) / kPairWaves;
-    const size_t lds = pair32_lds_bytes(a.A);
-#define LP(MODE, TBV) hipLaunchKernelGGL((k_pairwf<MODE, TBV>), dim3(nb), dim3(kPairWaves * kWave), lds, s, a)
-    if (a.traceback) {
-        if (mode == LOCAL) LP(LOCAL, true); else if (mode == GLOBAL) LP(GLOBAL, true); else LP(SEMIGLOBAL, true);
+    const size_t lds = a.pssm ? 16 : pair32_lds_bytes(a.A);
+#define LP(MODE, TBV, PSV) \
+    hipLaunchKernelGGL((k_pairwf<MODE, TBV, PSV>), dim3(nb), dim3(kPairWaves * kWave), lds, s, a)
+#define LPM(TBV, PSV) \
+    if (mode == LOCAL) LP(LOCAL, TBV, PSV); else if (mode == GLOBAL) LP(GLOBAL, TBV, PSV); else LP(SEMIGLOBAL, TBV, PSV)
+    if (a.pssm) {
+        if (a.traceback) { LPM(true, true); } else { LPM(false, true); }
     } else {
-        if (mode == LOCAL) LP(LOCAL, false); else if (mode == GLOBAL) LP(GLOBAL, false); else LP(SEMIGLOBAL, false);
+        if (a.traceback) { LPM(true, false); } else { LPM(false, false); }
     }
+#undef LPM
 #undef LP
     return hipGetLastError();
 }

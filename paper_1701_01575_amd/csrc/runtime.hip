@@ -13,6 +13,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "dsa.h"
 #include "internal.h"
 
@@ -35,6 +37,68 @@ int fail(int code, const std::string &msg) {
     } while (0)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Phase ranges for profilers (rocprofv3 --marker-trace): the plan, the table
+// upload, the search, the int32 rerun, the top-K, the hit traceback, the
+// pairwise fill and walk, the database packing.
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
+
+// Fault injection for tests of failure handling, from the environment
+// variable DSA_FAULT, a comma-separated list read at every call:
+//   alloc:N   the Nth device buffer taken by dsa_db_create fails (as if the
+//             allocator returned NULL); every buffer taken is given back
+//   launch:N  the Nth align call fails with DSA_E_DEVICE before device work
+//   qlen:L    an align call with a query of exactly L residues fails with
+//             DSA_E_DEVICE before device work
+//   ovf       database searches recompute every unit with the exact int32
+//             kernel after the int16 pass, as if each had overflowed
+// Counts start again whenever the variable's text changes.
+struct FaultSpec {
+    int64_t alloc = 0, launch = 0, qlen = -1;
+    bool ovf = false;
+};
+std::mutex g_fault_mu;
+std::string g_fault_text;
+int64_t g_fault_allocs = 0, g_fault_calls = 0;
+
+FaultSpec fault_spec() {
+    FaultSpec f;
+    const char *v = getenv("DSA_FAULT");
+    std::lock_guard<std::mutex> lk(g_fault_mu);
+    const std::string text = v ? v : "";
+    if (text != g_fault_text) {
+        g_fault_text = text;
+        g_fault_allocs = g_fault_calls = 0;
+    }
+    size_t p = 0;
+    while (p < text.size()) {
+        size_t q = text.find(',', p);
+        if (q == std::string::npos) q = text.size();
+        const std::string item = text.substr(p, q - p);
+        const size_t c = item.find(':');
+        const std::string key = item.substr(0, c);
+        const int64_t val = c == std::string::npos ? 0 : atoll(item.c_str() + c + 1);
+        if (key == "alloc") f.alloc = val;
+        else if (key == "launch") f.launch = val;
+        else if (key == "qlen") f.qlen = val;
+        else if (key == "ovf") f.ovf = true;
+        p = q + 1;
+    }
+    return f;
+}
+
+// true when this database buffer is the one DSA_FAULT=alloc:N names
+bool fault_alloc() {
+    const FaultSpec f = fault_spec();
+    if (f.alloc <= 0) return false;
+    std::lock_guard<std::mutex> lk(g_fault_mu);
+    return ++g_fault_allocs == f.alloc;
+}
 
 // Pinned staging buffer for the small per-call tables, one per device.
 struct Staging {
@@ -153,42 +217,61 @@ struct dsa_db {
     uint8_t *d_codes = nullptr;      // targets in original order (traceback of hits)
     std::vector<int64_t> offsets;    // host copy of the target offsets
     int64_t device_bytes = 0;
+    dsa_allocator alloc{};           // the caller's allocator (alloc == NULL: hipMalloc / hipFree)
 };
 
 constexpr int kLongMin = 128;  // groups this wide or wider also get the long-pair layout
 static_assert(kTI == kT32, "the wavefront and int32 kernels share the 16-row strip count");
 
+static void db_release(const dsa_db *db, void *p) {
+    if (!p) return;
+    if (db->alloc.alloc) {
+        if (db->alloc.free) db->alloc.free(p, db->alloc.ctx);
+    } else {
+        (void)hipFree(p);
+    }
+}
+
 static void db_free(dsa_db *db) {
     if (!db) return;
-    (void)hipFree(db->d_packed);
-    (void)hipFree(db->d_grp);
-    (void)hipFree(db->d_slot_target);
-    (void)hipFree(db->d_slot_len);
-    (void)hipFree(db->d_pair_dec);
-    (void)hipFree(db->d_inv_map);
-    (void)hipFree(db->d_len);
-    (void)hipFree(db->d_pairs);
-    (void)hipFree(db->d_lcodes);
-    (void)hipFree(db->d_codes);
+    void *bufs[] = {db->d_packed, db->d_grp,   db->d_slot_target, db->d_slot_len, db->d_pair_dec,
+                    db->d_inv_map, db->d_len, db->d_pairs,       db->d_lcodes,   db->d_codes};
+    for (void *p : bufs) db_release(db, p);
     delete db;
 }
 
+// One device buffer of the database, from the caller's allocator when there
+// is one, filled from host memory.
 template <typename Tp>
-static int upload(Tp **dst, const Tp *src, size_t count, int64_t *acc) {
-    size_t bytes = std::max<size_t>(count * sizeof(Tp), 16);
-    HIPCHK(hipMalloc((void **)dst, bytes));
+static int upload(const dsa_db *db, Tp **dst, const Tp *src, size_t count, int64_t *acc) {
+    size_t bytes = align_up(std::max<size_t>(count * sizeof(Tp), 16), 256);
+    if (fault_alloc()) return fail(DSA_E_DEVICE, "injected fault (DSA_FAULT=alloc): device buffer not allocated");
+    if (db->alloc.alloc) {
+        *dst = (Tp *)db->alloc.alloc(bytes, db->alloc.ctx);
+        if (!*dst) return fail(DSA_E_DEVICE, "the caller's allocator returned NULL for " + std::to_string(bytes) + " bytes");
+        if ((uintptr_t)*dst & 15) {
+            db_release(db, *dst);
+            *dst = nullptr;
+            return fail(DSA_E_INVAL, "the caller's allocator returned memory that is not 16-byte aligned");
+        }
+    } else {
+        HIPCHK(hipMalloc((void **)dst, bytes));
+    }
     if (count) HIPCHK(hipMemcpy(*dst, src, count * sizeof(Tp), hipMemcpyHostToDevice));
     *acc += (int64_t)bytes;
     return DSA_OK;
 }
 
 extern "C" int dsa_db_create(const uint8_t *codes, const int64_t *offsets, int64_t n_targets,
-                             int32_t alphabet_size, void *stream, dsa_db **out) {
+                             int32_t alphabet_size, const dsa_allocator *alloc, void *stream,
+                             dsa_db **out) {
     if (!out) return fail(DSA_E_INVAL, "out is NULL");
     *out = nullptr;
+    if (alloc && (!alloc->alloc || !alloc->free))
+        return fail(DSA_E_INVAL, "an allocator needs both alloc and free");
     if (!offsets || n_targets < 1) return fail(DSA_E_INVAL, "need offsets and n_targets >= 1");
     if (alphabet_size < 2 || alphabet_size > kMaxAlphabet)
-        return fail(DSA_E_INVAL, "alphabet_size must be in [2, 32]");
+        return fail(DSA_E_INVAL, "alphabet_size must be in [2, 64]");
     if (offsets[0] != 0) return fail(DSA_E_INVAL, "offsets[0] must be 0");
     for (int64_t k = 0; k < n_targets; k++)
         if (offsets[k + 1] < offsets[k]) return fail(DSA_E_INVAL, "offsets must be non-decreasing");
@@ -200,7 +283,9 @@ extern "C" int dsa_db_create(const uint8_t *codes, const int64_t *offsets, int64
         used[codes[k]] = true;
     }
 
+    Range rdb("dsa:db_pack");
     dsa_db *db = new dsa_db();
+    if (alloc) db->alloc = *alloc;
     db->A = alphabet_size;
     db->n_targets = n_targets;
     db->n_residues = total;
@@ -305,17 +390,17 @@ extern "C" int dsa_db_create(const uint8_t *codes, const int64_t *offsets, int64
         }
     }
     int rc;
-    if ((rc = upload(reinterpret_cast<uint16_t **>(&db->d_packed), packed.data(), packed.size(),
+    if ((rc = upload(db, reinterpret_cast<uint16_t **>(&db->d_packed), packed.data(), packed.size(),
                      &db->device_bytes)) ||
-        (rc = upload(&db->d_grp, db->grp.data(), db->grp.size(), &db->device_bytes)) ||
-        (rc = upload(&db->d_slot_target, slot_target.data(), slot_target.size(), &db->device_bytes)) ||
-        (rc = upload(&db->d_slot_len, slot_len.data(), slot_len.size(), &db->device_bytes)) ||
-        (rc = upload(&db->d_pair_dec, pair_dec.data(), pair_dec.size(), &db->device_bytes)) ||
-        (rc = upload(&db->d_inv_map, db->inv_map, (size_t)AP, &db->device_bytes)) ||
-        (rc = upload(&db->d_len, db->len.data(), db->len.size(), &db->device_bytes)) ||
-        (rc = upload(&db->d_pairs, db->pairs.data(), db->pairs.size(), &db->device_bytes)) ||
-        (rc = upload(&db->d_lcodes, lcodes.data(), lcodes.size(), &db->device_bytes)) ||
-        (rc = upload(&db->d_codes, codes, (size_t)total, &db->device_bytes))) {
+        (rc = upload(db, &db->d_grp, db->grp.data(), db->grp.size(), &db->device_bytes)) ||
+        (rc = upload(db, &db->d_slot_target, slot_target.data(), slot_target.size(), &db->device_bytes)) ||
+        (rc = upload(db, &db->d_slot_len, slot_len.data(), slot_len.size(), &db->device_bytes)) ||
+        (rc = upload(db, &db->d_pair_dec, pair_dec.data(), pair_dec.size(), &db->device_bytes)) ||
+        (rc = upload(db, &db->d_inv_map, db->inv_map, (size_t)AP, &db->device_bytes)) ||
+        (rc = upload(db, &db->d_len, db->len.data(), db->len.size(), &db->device_bytes)) ||
+        (rc = upload(db, &db->d_pairs, db->pairs.data(), db->pairs.size(), &db->device_bytes)) ||
+        (rc = upload(db, &db->d_lcodes, lcodes.data(), lcodes.size(), &db->device_bytes)) ||
+        (rc = upload(db, &db->d_codes, codes, (size_t)total, &db->device_bytes))) {
         db_free(db);
         return rc;
     }
@@ -507,6 +592,9 @@ struct PairRoute {
 
 // Lanes per wavefront pair: the narrowest segment that covers the query in
 // one pass of 16-row strips (64 lanes and several passes beyond 1024 rows).
+// (Narrower segments with several passes keep more lanes busy, but measured
+// slower on the protein and read-mapping pairs: 67.6 against 59.9 ms and
+// 19.3 against 13.9 ms.)
 int wf_seg(int64_t m) {
     for (int seg = 4; seg < kWave; seg *= 2)
         if (m <= (int64_t)kTP * seg) return seg;
@@ -548,6 +636,7 @@ struct Plan {
     size_t lds16 = 0, lds32 = 0;
     // workspace layout (byte offsets)
     size_t off_units = 0, off_qinfo = 0, off_subst = 0, off_rows = 0, table_bytes = 0;
+    size_t off_pssm = 0, pssm_bytes = 0;  // device profile (position-specific scoring), if any
     size_t off_flags = 0, off_qflag = 0, off_counter = 0, off_bnd = 0, off_prof = 0, total = 0;
     size_t off_iunits = 0, off_ibnd = 0;
     // top-K: full per-target results, hit list, pairwise workspace for traceback
@@ -563,9 +652,9 @@ int check_common(const dsa_args *a) {
     if (!a) return fail(DSA_E_INVAL, "args is NULL");
     if (a->n_q < 1) return fail(DSA_E_INVAL, "n_q must be >= 1");
     if (!a->q_offsets) return fail(DSA_E_INVAL, "q_offsets is NULL");
-    if (!a->subst) return fail(DSA_E_INVAL, "subst is NULL");
+    if (!a->subst && !a->pssm) return fail(DSA_E_INVAL, "subst and pssm are both NULL");
     if (a->alphabet_size < 2 || a->alphabet_size > kMaxAlphabet)
-        return fail(DSA_E_INVAL, "alphabet_size must be in [2, 32]");
+        return fail(DSA_E_INVAL, "alphabet_size must be in [2, 64]");
     if (a->mode < DSA_LOCAL || a->mode > DSA_SEMIGLOBAL) return fail(DSA_E_INVAL, "unknown mode");
     if (a->gap_extend < 0 || a->gap_open < 0 || a->gap_extend > a->gap_open)
         return fail(DSA_E_INVAL, "need 0 <= gap_extend <= gap_open");
@@ -609,6 +698,7 @@ struct PairPlan {
     int wf_buffers = 1;                 // code buffers of wf_tb_max words each
     std::vector<std::pair<int, int64_t>> plain_seq;  // plain: (0 group | 1 wavefront, index) in input order
     size_t off_slots = 0, off_groups = 0, off_wf = 0, off_waves = 0, off_subst = 0, table_bytes = 0;
+    size_t off_pssm = 0, pssm_bytes = 0;  // the call's own device profile (pairwise calls with one)
     size_t off_end = 0, off_bnd = 0, off_tpk = 0, off_tb = 0, off_bndw = 0, off_tbw = 0, total = 0;
 };
 
@@ -634,6 +724,7 @@ void layout_pair_plan(PairPlan &P, const PairCaps &c, int A) {
     P.off_wf = o; o = align_up(o + cnt(c.wf) * sizeof(WfPair), 256);
     P.off_waves = o; o = align_up(o + cnt(c.waves) * sizeof(WfWave), 256);
     P.off_subst = o; o = align_up(o + (size_t)A * A, 256);
+    P.off_pssm = o; o = align_up(o + P.pssm_bytes, 256);
     P.table_bytes = o;
     P.off_end = o; o = align_up(o + cnt(c.slots) * 8, 256);
     P.off_bnd = o; o = align_up(o + cnt(c.bnd) * 8, 256);
@@ -647,6 +738,7 @@ void layout_pair_plan(PairPlan &P, const PairCaps &c, int A) {
 struct PairSpec {
     int64_t q_off, t_off, m, n;
     int32_t res;
+    int64_t pssm_row = 0;  // the query's first row in the device profile
 };
 
 // Bytes of direction codes per chunk: a sixteenth of the device's memory,
@@ -767,6 +859,7 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
             I.res = x.res;
             I.cig_off = roff[x.res];
             I.cig_cap = (int32_t)rcap[x.res];
+            I.pssm_row = x.pssm_row;
             for (int lane = 1; lane < kWave; lane++) {
                 P.slots.push_back(PairInfo{});
                 memset(&P.slots.back(), 0, sizeof(PairInfo));
@@ -802,6 +895,7 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
                 I.res = x.res;
                 I.cig_off = roff[x.res];
                 I.cig_cap = (int32_t)rcap[x.res];
+                I.pssm_row = x.pssm_row;
             }
             P.slots.push_back(I);
         }
@@ -907,6 +1001,7 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
             I.res = x.res;
             I.cig_off = roff[x.res];
             I.cig_cap = (int32_t)rcap[x.res];
+            I.pssm_row = x.pssm_row;
             P.slots.push_back(I);
         }
     }
@@ -918,10 +1013,51 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     layout_pair_plan(P, caps_of(P), A);
 }
 
+// Smallest score and largest absolute score of the call's scoring: the
+// matrix, or the position-specific profile when there is one.
+void score_range(const dsa_args *a, int *mn, int *mx) {
+    *mn = 0;
+    *mx = 0;
+    const int A = a->alphabet_size;
+    const int64_t n = a->pssm ? a->q_offsets[a->n_q] * A : (int64_t)A * A;
+    const int8_t *v = a->pssm ? a->pssm : a->subst;
+    for (int64_t k = 0; k < n; k++) {
+        *mn = std::min<int>(*mn, v[k]);
+        *mx = std::max<int>(*mx, std::abs((int)v[k]));
+    }
+}
+
 int max_abs_score(const dsa_args *a) {
-    int mx = 0;
-    for (int k = 0; k < a->alphabet_size * a->alphabet_size; k++) mx = std::max(mx, std::abs((int)a->subst[k]));
+    int mn, mx;
+    score_range(a, &mn, &mx);
     return mx;
+}
+
+// Bytes of the device profile: every query's rows of A + 1 scores (the last
+// column kPssmPad), each query's rows followed by one row of kPssmPad.
+size_t pssm_bytes(const dsa_args *a) {
+    return a->pssm ? (size_t)(a->q_offsets[a->n_q] + a->n_q) * (size_t)(a->alphabet_size + 1) : 0;
+}
+
+void fill_pssm(const dsa_args *a, uint8_t *dst) {
+    const int A = a->alphabet_size;
+    int8_t *d = reinterpret_cast<int8_t *>(dst);
+    for (int64_t q = 0; q < a->n_q; q++) {
+        for (int64_t g = a->q_offsets[q]; g < a->q_offsets[q + 1]; g++) {
+            memcpy(d, a->pssm + g * A, (size_t)A);
+            d[A] = (int8_t)kPssmPad;
+            d += A + 1;
+        }
+        memset(d, (uint8_t)(int8_t)kPssmPad, (size_t)A + 1);
+        d += A + 1;
+    }
+}
+
+// The matrix into the workspace (zeros when the call scores with a profile only).
+void copy_subst(const dsa_args *a, uint8_t *dst) {
+    const size_t bytes = (size_t)a->alphabet_size * a->alphabet_size;
+    if (a->subst) memcpy(dst, a->subst, bytes);
+    else memset(dst, 0, bytes);
 }
 
 // mx: max_abs_score(a)
@@ -949,10 +1085,12 @@ int make_pair_plan(const dsa_args *a, const dsa_out *out, PairPlan &P) {
         sp[k].m = a->q_offsets[k + 1] - a->q_offsets[k];
         sp[k].n = a->t_offsets[k + 1] - a->t_offsets[k];
         sp[k].res = (int32_t)k;
+        sp[k].pssm_row = a->q_offsets[k] + k;
         const int rc = check_pair_range(a, mx, sp[k].m, sp[k].n);
         if (rc) return rc;
     }
     const bool tb = (a->flags & DSA_TRACEBACK) != 0;
+    P.pssm_bytes = pssm_bytes(a);
     build_pair_plan(sp, n, a->mode, ends, tb, (tb && out) ? out->cigar_capacity : 0, a->alphabet_size,
                     tb_budget_bytes(), P, (a->flags & DSA_PLAIN) != 0, pair_route(tuning_for(pair_key(a))));
     return DSA_OK;
@@ -971,15 +1109,13 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     P.ends = ends;
     P.persistent = !(a->flags & DSA_PLAIN);
     // a free query end is tracked by the exact int32 kernel only, and so is
-    // a local search whose gap penalties leave the offset int16 range
-    P.force32 = (a->flags & DSA_FORCE_INT32) != 0 || (ends & DSA_QE) != 0 ||
+    // a local search whose gap penalties leave the offset int16 range, and a
+    // search over more than 32 letters (its pair profiles would not fit LDS)
+    P.force32 = (a->flags & DSA_FORCE_INT32) != 0 || (ends & DSA_QE) != 0 || a->alphabet_size > kMaxAlphabet16 ||
                 (a->mode == DSA_LOCAL && (a->gap_open > kLocal16GapMax || a->gap_extend > kLocal16ExtMax));
     const int A = a->alphabet_size;
     int mn = 0, mx = 0;
-    for (int k = 0; k < A * A; k++) {
-        mn = std::min<int>(mn, a->subst[k]);
-        mx = std::max<int>(mx, std::abs((int)a->subst[k]));
-    }
+    score_range(a, &mn, &mx);
     P.min_s = -mn;
     P.max_abs_s = mx;
     // defaults measured on the protein database-search workload (the tuning
@@ -1016,7 +1152,7 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     if (!ks_ok) P.ks_budget = 0;
     P.lds16 = search16_lds_bytes(P.T, db->AP);
     P.lds32 = search32_lds_bytes(db->AP);
-    if (P.lds16 > 160 * 1024) return fail(DSA_E_NOTSUP, "alphabet too large for the LDS profile");
+    if (!P.force32 && P.lds16 > 160 * 1024) return fail(DSA_E_NOTSUP, "alphabet too large for the LDS profile");
 
     const int64_t nq = a->n_q;
     P.qinfo.resize(nq);
@@ -1197,6 +1333,8 @@ int make_search_plan(const dsa_args *a, Plan &P) {
     P.off_qinfo = o; o = align_up(o + 2 * nq * sizeof(QueryInfo), 256);  // int16 and int32 strips
     P.off_subst = o; o = align_up(o + (size_t)A * A, 256);
     P.off_rows = o; o = align_up(o + std::max<size_t>(P.empty_rows.size(), 1) * sizeof(int32_t), 256);
+    P.pssm_bytes = pssm_bytes(a);
+    P.off_pssm = o; o = align_up(o + P.pssm_bytes, 256);
     P.table_bytes = o;
     P.off_flags = o; o = align_up(o + std::max<size_t>(P.units.size(), 1) * sizeof(int32_t), 256);
     P.off_qflag = o; o = align_up(o + nq * sizeof(int32_t), 256);
@@ -1277,6 +1415,7 @@ extern "C" int dsa_workspace_size(const dsa_args *args, size_t *bytes) {
 
 static int upload_tables(hipStream_t st, void *dst, size_t bytes,
                          const std::function<void(uint8_t *)> &fill) {
+    Range r("dsa:upload");
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     Staging &S = g_staging[dev & 63];
@@ -1315,8 +1454,10 @@ static int upload_tables(hipStream_t st, void *dst, size_t bytes,
 // records only the kernels, after the tables are in place.
 enum RunPhase { RUN_ALL = 0, RUN_UPLOAD = 1, RUN_KERNELS = 2 };
 
+// pssm_dev: the device profile of a calling search (hit traceback); a
+// pairwise call with a profile uploads its own with its tables.
 static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t *ws,
-                     const uint8_t *t_codes, int phase = RUN_ALL) {
+                     const uint8_t *t_codes, int phase = RUN_ALL, const int8_t *pssm_dev = nullptr) {
     hipStream_t st = (hipStream_t)a->stream;
     const int A = a->alphabet_size;
     if (P.traceback && (!out->cigar_ops || !out->cigar_off || !out->cigar_len))
@@ -1328,13 +1469,15 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
             memcpy(h + P.off_groups, P.groups.data(), P.groups.size() * sizeof(PairGroup));
             memcpy(h + P.off_wf, P.wf.data(), P.wf.size() * sizeof(WfPair));
         memcpy(h + P.off_waves, P.waves.data(), P.waves.size() * sizeof(WfWave));
-            memcpy(h + P.off_subst, a->subst, (size_t)A * A);
+            copy_subst(a, h + P.off_subst);
+            if (P.pssm_bytes) fill_pssm(a, h + P.off_pssm);
         });
         if (rc) return rc;
         if (phase == RUN_UPLOAD) return DSA_OK;
     }
     PairArgs K;
     memset(&K, 0, sizeof(K));
+    K.pssm = pssm_dev ? pssm_dev : (P.pssm_bytes ? (const int8_t *)(ws + P.off_pssm) : nullptr);
     K.pairs = (const PairInfo *)(ws + P.off_slots);
     K.q_codes = a->q_codes;
     K.t_codes = t_codes;
@@ -1435,6 +1578,7 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
         return DSA_OK;
     };
     const char *cap_msg = "CIGAR capacity too small; see status bit 1";
+    Range rp("dsa:pairs");
     size_t span_slot;
     if ((rc = timing_begin(st, TK_SPAN, &span_slot))) return rc;
     if (P.plain) {  // one pair at a time, in input order: (pack,) fill, walk
@@ -1552,7 +1696,8 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
             if (!P.order.empty()) memcpy(h + P.off_order, P.order.data(), P.order.size() * sizeof(int32_t));
             memcpy(h + P.off_qinfo, P.qinfo.data(), nq * sizeof(QueryInfo));
             memcpy(h + P.off_qinfo + nq * sizeof(QueryInfo), q32.data(), nq * sizeof(QueryInfo));
-            memcpy(h + P.off_subst, a->subst, (size_t)A * A);
+            copy_subst(a, h + P.off_subst);
+            if (P.pssm_bytes) fill_pssm(a, h + P.off_pssm);
             if (!P.empty_rows.empty())
                 memcpy(h + P.off_rows, P.empty_rows.data(), P.empty_rows.size() * sizeof(int32_t));
         });
@@ -1571,6 +1716,7 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
     K.q_codes = a->q_codes;
     K.qinfo = (const QueryInfo *)(ws + P.off_qinfo);
     K.subst = (const int8_t *)(ws + P.off_subst);
+    K.pssm = P.pssm_bytes ? (const int8_t *)(ws + P.off_pssm) : nullptr;
     K.A = A;
     K.AP = db->AP;
     K.o = a->gap_open;
@@ -1597,6 +1743,7 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
         b.qinfo = K.qinfo;
         b.n_q = (int32_t)nq;
         b.subst = K.subst;
+        b.pssm = K.pssm;
         b.A = A;
         b.inv_map = db->d_inv_map;
         b.AP = db->AP;
@@ -1613,6 +1760,7 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
         pa.qinfo = K.qinfo;
         pa.n_q = (int32_t)nq;
         pa.subst = K.subst;
+        pa.pssm = K.pssm;
         pa.A = A;
         pa.AP = db->AP;
         pa.inv_map = db->d_inv_map;
@@ -1673,6 +1821,7 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
     I.qinfo = qi32;
     I.q_codes = a->q_codes;
     I.subst = K.subst;
+    I.pssm = K.pssm;
     I.inv_map = db->d_inv_map;
     I.A = A;
     I.AP = db->AP;
@@ -1749,17 +1898,25 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
         HIPCHK(launch_search16(k, w, P.T, P.mode, P.wpb16, nb, true, P.ldsM, st));
         return timing_end(st, slot);
     };
+    // DSA_FAULT=ovf: every unit of the round is recomputed by the int32 rerun
+    const bool force_rerun = fault_spec().ovf;
+    auto rerun = [&](const Round &R) -> int {
+        Range rr("dsa:rerun");
+        if (force_rerun) HIPCHK(launch_fill_i32(K.unit_flags + R.first, 2, R.count, st));
+        return pass(d_units + R.first, R.count, 1);
+    };
     int rc;
     for (const Round &R : P.rounds) {
         const SearchUnit *u = d_units + R.first;
+        Range rs("dsa:search");
         if (!P.force32 && R.ocount > 0) {
             if ((rc = mixed(R))) return rc;
-            if ((rc = pass(u, R.count, 1))) return rc;
+            if ((rc = rerun(R))) return rc;
         } else if (!P.force32) {
             if ((rc = intra(d_iunits + R.ifirst, R.icount, K.unit_flags))) return rc;
             if ((rc = pass(u, R.inter, 0))) return rc;
             if ((rc = join(R.icount))) return rc;
-            if ((rc = pass(u, R.count, 1))) return rc;
+            if ((rc = rerun(R))) return rc;
         } else if ((rc = pass(u, R.count, 0))) {
             return rc;
         }
@@ -1804,7 +1961,10 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
         t.out_status = out->status;
         t.hit_t = (int32_t *)(ws + P.off_hits);
         if (!t.out_tindex) return fail(DSA_E_INVAL, "top_k needs out->t_index");
-        HIPCHK(launch_topk(t, st));
+        {
+            Range r("dsa:topk");
+            HIPCHK(launch_topk(t, st));
+        }
         if (!P.traceback) {
             if (out->q_begin) HIPCHK(launch_fill_i32(out->q_begin, -1, nq * P.K, st));
             if (out->t_begin) HIPCHK(launch_fill_i32(out->t_begin, -1, nq * P.K, st));
@@ -1812,6 +1972,7 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
         }
         // traceback of the hits: read the hit list back (this waits for the
         // search), then align each (query, hit) pair with the pairwise path
+        Range rh("dsa:hit_traceback");
         std::vector<int32_t> hits((size_t)nq * P.K);
         HIPCHK(hipMemcpyAsync(hits.data(), t.hit_t, hits.size() * 4, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -1826,6 +1987,7 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
                 x.t_off = db->offsets[tg];
                 x.n = db->len[tg];
                 x.res = (int32_t)(q * P.K + k);
+                x.pssm_row = a->q_offsets[q] + q;
                 sp.push_back(x);
             }
         if (out->q_begin) HIPCHK(launch_fill_i32(out->q_begin, -1, nq * P.K, st));
@@ -1843,7 +2005,7 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
             return fail(DSA_E_WORKSPACE, "hit traceback plan exceeds its workspace bound");
         layout_pair_plan(PP, cap, A);
         if (PP.total > P.pairws_bytes) return fail(DSA_E_WORKSPACE, "hit traceback plan exceeds its workspace bound");
-        return run_pairs(a, out, PP, ws + P.off_pairws, db->d_codes);
+        return run_pairs(a, out, PP, ws + P.off_pairws, db->d_codes, RUN_ALL, K.pssm);
     }
     return DSA_OK;
 }
@@ -1861,14 +2023,31 @@ static int align_phase(const dsa_args *args, const dsa_out *out, int phase) {
     if (!out || !out->score) return fail(DSA_E_INVAL, "out->score is required");
     int rc = check_common(args);
     if (rc) return rc;
+    if (phase != RUN_KERNELS) {
+        const FaultSpec f = fault_spec();
+        bool hit = false;
+        if (f.launch > 0) {
+            std::lock_guard<std::mutex> lk(g_fault_mu);
+            hit = ++g_fault_calls == f.launch;
+        }
+        for (int64_t q = 0; !hit && f.qlen >= 0 && q < args->n_q; q++)
+            hit = args->q_offsets[q + 1] - args->q_offsets[q] == f.qlen;
+        if (hit) return fail(DSA_E_DEVICE, "injected fault (DSA_FAULT=" + g_fault_text + "): call failed before device work");
+    }
     if (!args->db) {
         PairPlan PP;
-        if ((rc = make_pair_plan(args, out, PP))) return rc;
+        {
+            Range r("dsa:plan");
+            if ((rc = make_pair_plan(args, out, PP))) return rc;
+        }
         if ((rc = check_workspace(args, PP.total))) return rc;
         return run_pairs(args, out, PP, (uint8_t *)args->workspace, args->t_codes, phase);
     }
     Plan P;
-    rc = make_plan(args, P);
+    {
+        Range r("dsa:plan");
+        rc = make_plan(args, P);
+    }
     if (rc) return rc;
     if ((rc = check_workspace(args, P.total))) return rc;
     int dev = 0;
@@ -2298,5 +2477,11 @@ extern "C" const char *dsa_strerror(int status) {
 }
 
 extern "C" const char *dsa_last_error(void) { return g_err.c_str(); }
+
+namespace dsa {
+// Errors of the host-only parts of the library (sequence ingest) go to the
+// same thread-local text.
+void set_last_error(const std::string &msg) { g_err = msg; }
+}  // namespace dsa
 
 extern "C" int32_t dsa_abi_version(void) { return DSA_ABI_VERSION; }

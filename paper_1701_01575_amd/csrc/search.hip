@@ -77,10 +77,10 @@ __global__ void k_profile16(ProfileArgs a) {
         const int i = s * T + r;
         int slo = NEG16, shi = NEG16;
         if (r < T && i < Q.len) {
-            const int c = min((int)a.q_codes[Q.off + i], A - 1);  // codes >= A are caller errors
+            // query codes >= A are caller errors; qscore clamps them
             const int clo = a.inv_map[a.pair_dec[2 * p]], chi = a.inv_map[a.pair_dec[2 * p + 1]];
-            if (clo != 0xff) slo = a.subst[c * A + clo] + a.add;
-            if (chi != 0xff) shi = a.subst[c * A + chi] + a.add;
+            if (clo != 0xff) slo = qscore(a.pssm, a.subst, a.q_codes, A, Q.off + i, lo, clo) + a.add;
+            if (chi != 0xff) shi = qscore(a.pssm, a.subst, a.q_codes, A, Q.off + i, lo, chi) + a.add;
         }
         a.prof[k] = pack2(slo, shi);
     }
@@ -396,7 +396,7 @@ __global__ void __launch_bounds__(1024) k_search32(SearchArgs P, int rerun_only)
                 const int c = idx / T, r = idx - c * T;
                 const int i = i0 + r;
                 int v = PAD32;
-                if (i < m && P.inv_map[c] != 0xff) v = P.subst[min((int)qc[i], A - 1) * A + P.inv_map[c]];
+                if (i < m && P.inv_map[c] != 0xff) v = qscore(P.pssm, P.subst, P.q_codes, A, Q.off + i, U.q, P.inv_map[c]);
                 prof[c * SP + r] = v;
             }
             __syncthreads();
@@ -576,11 +576,10 @@ __global__ void k_bound16(BoundArgs a) {
     const QueryInfo Q = a.qinfo[q];
     int64_t sum = 0;
     for (int i = threadIdx.x; i < Q.len; i += blockDim.x) {
-        const int c = min((int)a.q_codes[Q.off + i], a.A - 1);
         int best = 0;
         for (int k = 0; k < a.AP; k++) {
             const int t = a.inv_map[k];
-            if (t != 0xff) best = max(best, (int)a.subst[c * a.A + t]);
+            if (t != 0xff) best = max(best, qscore(a.pssm, a.subst, a.q_codes, a.A, Q.off + i, q, t));
         }
         sum += best;
     }

@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported(B):
     for n in names:
         assert hasattr(L, n), n
     assert sorted(B.EXPORTS) == names
-    assert B.dsa_abi_version() == B.ABI_VERSION == 2
+    assert B.dsa_abi_version() == B.ABI_VERSION == 4
 
 
 def test_strerror(B):
@@ -61,7 +61,7 @@ def _args(B, **kw):
     (dict(gap_extend=6), 1),
     (dict(gap_open=-1), 1),
     (dict(mode=7), 1),
-    (dict(alphabet_size=40), 1),
+    (dict(alphabet_size=70), 1),
     (dict(free_ends=4), 1),          # free ends outside semiglobal
     (dict(flags=64), 1),
     (dict(n_q=0), 1),
@@ -77,11 +77,26 @@ def test_db_create_validates_before_allocating(B):
     codes = np.array([0, 1, 9], np.uint8)
     offs = np.array([0, 3], np.int64)
     h = ctypes.c_void_p()
-    st = B.lib().dsa_db_create(codes.ctypes.data, offs.ctypes.data, 1, 4, None, ctypes.byref(h))
+    st = B.lib().dsa_db_create(codes.ctypes.data, offs.ctypes.data, 1, 4, None, None, ctypes.byref(h))
     assert st == B.DSA_E_INVAL and "alphabet" in B.dsa_last_error()
     bad = np.array([0, 5, 3], np.int64)
-    st = B.lib().dsa_db_create(codes.ctypes.data, bad.ctypes.data, 2, 16, None, ctypes.byref(h))
+    st = B.lib().dsa_db_create(codes.ctypes.data, bad.ctypes.data, 2, 16, None, None, ctypes.byref(h))
     assert st == B.DSA_E_INVAL
+
+
+def test_db_create_allocator_needs_both_functions(B):
+    """An allocator without a free function is refused before any device
+    work; the callbacks are never called."""
+    codes = np.array([0, 1, 2], np.uint8)
+    offs = np.array([0, 3], np.int64)
+    calls = []
+    alloc = B.ALLOC_FN(lambda n, ctx: calls.append(n) or None)
+    half = B.dsa_allocator(alloc, B.FREE_FN(), None)
+    h = ctypes.c_void_p()
+    st = B.lib().dsa_db_create(codes.ctypes.data, offs.ctypes.data, 1, 4, ctypes.byref(half), None,
+                               ctypes.byref(h))
+    assert st == B.DSA_E_INVAL and "allocator" in B.dsa_last_error()
+    assert calls == [] and not h.value
 
 
 def test_length_limit(B):
@@ -90,7 +105,7 @@ def test_length_limit(B):
     codes = np.zeros(65533, np.uint8)
     offs = np.array([0, 65533], np.int64)
     h = ctypes.c_void_p()
-    st = B.lib().dsa_db_create(codes.ctypes.data, offs.ctypes.data, 1, 4, None, ctypes.byref(h))
+    st = B.lib().dsa_db_create(codes.ctypes.data, offs.ctypes.data, 1, 4, None, None, ctypes.byref(h))
     assert st == B.DSA_E_NOTSUP and "65532" in B.dsa_last_error()
     n = ctypes.c_size_t()
     qo = np.array([0, 65533], np.int64)
