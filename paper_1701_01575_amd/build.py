@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdsa.so")
-SOURCES = ["search.hip", "intra.hip", "pair.hip", "topk.hip", "probe.hip", "runtime.hip", "ingest.cpp"]
+SOURCES = ["search.hip", "intra.hip", "pair.hip", "pair16.hip", "topk.hip", "probe.hip", "runtime.hip", "ingest.cpp"]
 ARCH = os.environ.get("DSA_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -22,7 +22,9 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "pair16.h"
 #include "pk16.h"
+#include "walk.h"
 
 namespace dsa {
 
@@ -306,8 +308,9 @@ __device__ __forceinline__ int row_of(const int (&H)[T], int r) {
     return v;
 }
 
+// only: when set, the segments of the pairs k with only[k] == 0 do nothing.
 template <int MODE, bool TB, bool PS>
-__global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
+__global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P, const int32_t *only) {
     constexpr int T = kTP;
     extern __shared__ int32_t sm[];
     const int A = P.A, SS = P.A + 1;
@@ -325,6 +328,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
     const int lane = threadIdx.x & (SEG - 1);
     const int k_seg = (threadIdx.x & 63) / SEG;
     if (k_seg >= V.np) return;
+    if (only && !only[V.p0 + k_seg]) return;
     const WfPair W = P.wf[V.p0 + k_seg];
     const PairInfo I = P.pairs[W.slot];
     const int o = P.o, e = P.e, ends = P.ends;
@@ -502,12 +506,12 @@ __global__ void __launch_bounds__(kPairWaves * kWave) k_pairwf(PairArgs P) {
     }
 }
 
-hipError_t launch_pairwf(const PairArgs &a, int mode, hipStream_t s) {
+hipError_t launch_pairwf_only(const PairArgs &a, int mode, const int32_t *only, hipStream_t s) {
     if (a.n_waves <= 0) return hipSuccess;
     const int nb = (a.n_waves + kPairWaves - 1) / kPairWaves;
     const size_t lds = a.pssm ? 16 : pair32_lds_bytes(a.A);
 #define LP(MODE, TBV, PSV) \
-    hipLaunchKernelGGL((k_pairwf<MODE, TBV, PSV>), dim3(nb), dim3(kPairWaves * kWave), lds, s, a)
+    hipLaunchKernelGGL((k_pairwf<MODE, TBV, PSV>), dim3(nb), dim3(kPairWaves * kWave), lds, s, a, only)
 #define LPM(TBV, PSV) \
     if (mode == LOCAL) LP(LOCAL, TBV, PSV); else if (mode == GLOBAL) LP(GLOBAL, TBV, PSV); else LP(SEMIGLOBAL, TBV, PSV)
     if (a.pssm) {
@@ -520,28 +524,13 @@ hipError_t launch_pairwf(const PairArgs &a, int mode, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_pairwf(const PairArgs &a, int mode, hipStream_t s) {
+    return launch_pairwf_only(a, mode, nullptr, s);
+}
+
 // ---------------------------------------------------------------------------
 // Traceback walk: one thread per pair slot.
 
-struct RunWriter {
-    uint32_t *out;
-    int64_t lo, pos;  // region [lo, hi); runs are written downwards from hi
-    uint32_t op = 0, len = 0;
-    bool truncated = false;
-    __device__ void flush() {
-        if (len == 0) return;
-        if (pos > lo) out[--pos] = (len << 4) | op;
-        else truncated = true;
-        len = 0;
-    }
-    __device__ void emit(uint32_t o, uint32_t count) {
-        if (count == 0) return;
-        if (o != op) { flush(); op = o; }
-        len += count;
-    }
-};
-
-constexpr uint32_t OP_I = 1, OP_D = 2, OP_EQ = 7, OP_X = 8;
 
 // Walk one pair back from its end cell (1-based i, j; i < 0 = nothing to
 // trace) through the direction codes that code(i, j) returns.
@@ -598,23 +587,6 @@ __device__ void walk_pair(const PairArgs &P, const PairInfo &I, int i, int j, Co
     P.cig_off_out[I.res] = W.pos;
     P.cig_len_out[I.res] = (int32_t)(I.cig_off + I.cig_cap - W.pos);
     if (W.truncated && P.out_status) P.out_status[I.res] |= 2;  // DSA_ST_TRUNCATED
-}
-
-// Residue k (0..15) of a 16-residue window held as four uint32.
-__device__ __forceinline__ int byte_of(const uint32_t (&w)[4], int k) {
-    const uint32_t x = (k < 8) ? ((k < 4) ? w[0] : w[1]) : ((k < 12) ? w[2] : w[3]);
-    return (int)((x >> (8 * (k & 3))) & 0xffu);
-}
-
-// Residues [base, base + 16) of a sequence of `len` (zero past its end),
-// as 16 independent byte loads.
-__device__ __forceinline__ void load_window(const uint8_t *seq, int len, int base, uint32_t (&w)[4]) {
-    uint32_t v[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-    for (int k = 0; k < 16; k++)
-        if (base + k < len) v[k >> 2] |= (uint32_t)seq[base + k] << (8 * (k & 3));
-#pragma unroll
-    for (int k = 0; k < 4; k++) w[k] = v[k];
 }
 
 // Walk of the lane-per-pair kernel's pairs: one thread per pair slot.  Like
@@ -680,11 +652,13 @@ __global__ void __launch_bounds__(kLaneWalkThreads) k_walk(PairArgs P, int64_t s
 // into registers.  The 16 steps then read only LDS and registers.
 constexpr int kWalkThreads = 64;
 
+// only: when set, the pairs k with only[k] == 0 are left alone.
 template <int MODE>
-__global__ void __launch_bounds__(kWalkThreads) k_walk_wf(PairArgs P) {
+__global__ void __launch_bounds__(kWalkThreads) k_walk_wf(PairArgs P, const int32_t *only) {
     __shared__ uint4 cache[kWalkThreads * 4 * 8];  // per thread: 4 blocks x 128 bytes
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= P.n_wf) return;
+    if (only && !only[k]) return;
     const WfPair W = P.wf[k];
     const PairInfo I = P.pairs[W.slot];
     const uint2 *tb = reinterpret_cast<const uint2 *>(P.tb) + W.tb;
@@ -742,14 +716,18 @@ __global__ void __launch_bounds__(kWalkThreads) k_walk_wf(PairArgs P) {
         refill);
 }
 
-hipError_t launch_walk_wf(const PairArgs &a, int mode, hipStream_t s) {
+hipError_t launch_walk_wf_only(const PairArgs &a, int mode, const int32_t *only, hipStream_t s) {
     if (a.n_wf <= 0) return hipSuccess;
     const int bs = kWalkThreads;
     const unsigned nb = (unsigned)((a.n_wf + bs - 1) / bs);
-    if (mode == LOCAL) hipLaunchKernelGGL(k_walk_wf<LOCAL>, dim3(nb), dim3(bs), 0, s, a);
-    else if (mode == GLOBAL) hipLaunchKernelGGL(k_walk_wf<GLOBAL>, dim3(nb), dim3(bs), 0, s, a);
-    else hipLaunchKernelGGL(k_walk_wf<SEMIGLOBAL>, dim3(nb), dim3(bs), 0, s, a);
+    if (mode == LOCAL) hipLaunchKernelGGL(k_walk_wf<LOCAL>, dim3(nb), dim3(bs), 0, s, a, only);
+    else if (mode == GLOBAL) hipLaunchKernelGGL(k_walk_wf<GLOBAL>, dim3(nb), dim3(bs), 0, s, a, only);
+    else hipLaunchKernelGGL(k_walk_wf<SEMIGLOBAL>, dim3(nb), dim3(bs), 0, s, a, only);
     return hipGetLastError();
+}
+
+hipError_t launch_walk_wf(const PairArgs &a, int mode, hipStream_t s) {
+    return launch_walk_wf_only(a, mode, nullptr, s);
 }
 
 hipError_t launch_walk(const PairArgs &a, int mode, int64_t slot0, int64_t n_slots, hipStream_t s) {

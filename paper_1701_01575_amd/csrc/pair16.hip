@@ -1,0 +1,647 @@
+// Pairwise alignment, packed int16 (Sections II.B.1 and II.C.2: global,
+// semi-global and local alignment of query k against target k).
+//
+// Fill (k_pairpk): the wavefront layout of the int32 kernel (a segment of w
+// lanes per unit, lane l owning the 16-row strips l, l + w, ... and computing
+// column t - l + 1 at step t), with two pairs per segment: pair a in the low
+// half of every packed register, pair b in the high half.  A segment has as
+// many lanes as strips (passes of equal width beyond 64 strips) and sits at
+// any lane of its wave beside the others.  Values
+// are held as value + bias, with the bias chosen per pair so that every
+// value the recurrence can reach is a positive normal binary16 pattern
+// (pk16_bias in the runtime): one v_pk_maximum3_f16 then takes the three-way
+// maximum of H for both pairs.  Scores come from an int16 copy of the matrix
+// in LDS (code A pads rows past a query and columns past a target with 0,
+// which keeps padding cells within the range of the real ones).
+//
+// Instead of direction codes the fill stores checkpoints, 0.5 byte per cell
+// like the codes: the bottom row of each strip (H and the F entering the next
+// strip, per step) and, every kCkCols steps, the strip's column (H and the E
+// of the next column for its 16 rows).  The walk (k_walk_ck) recomputes from
+// them, exactly, the direction codes of the 16 x 16 tile it stands in and
+// follows them to the tile's edge.  The stored columns are staggered (strip s
+// on lane l stores at columns c with c + l a multiple of kCkCols), so that
+// all lanes of a wave store in the same step.
+//
+// Range: global and semi-global pairs whose H could exceed the limit (the
+// query's sum of row maxima above hlim) and local pairs whose best score
+// exceeds it are flagged; the exact int32 kernels then redo them (fill with
+// direction codes in the same region, and their own walk).
+#include "pair16.h"
+#include "pk16.h"
+#include "walk.h"
+
+namespace dsa {
+
+namespace {
+
+// low halves of a and b as (a, b); high halves likewise (v_perm_b32)
+__device__ __forceinline__ uint32_t lo_lo(uint32_t a, uint32_t b) { return __builtin_amdgcn_perm(b, a, 0x05040100u); }
+__device__ __forceinline__ uint32_t hi_hi(uint32_t a, uint32_t b) { return __builtin_amdgcn_perm(b, a, 0x07060302u); }
+
+// H[r] for a per-lane row r, by a uniform branch per distinct r (the
+// registers stay registers).
+__device__ __forceinline__ uint32_t row_of16(const uint32_t (&H)[kTP], int r) {
+    uint32_t v = 0;
+    for (;;) {
+        int u = __builtin_amdgcn_readfirstlane(r);
+        asm volatile("" : "+s"(u));
+        uint32_t c;
+#define DSA_ROW(k) case k: c = H[k]; asm volatile("" : "+v"(c)); break;
+        switch (u) {
+            DSA_ROW(0) DSA_ROW(1) DSA_ROW(2) DSA_ROW(3) DSA_ROW(4) DSA_ROW(5) DSA_ROW(6) DSA_ROW(7)
+            DSA_ROW(8) DSA_ROW(9) DSA_ROW(10) DSA_ROW(11) DSA_ROW(12) DSA_ROW(13) DSA_ROW(14)
+            default: c = H[15]; asm volatile("" : "+v"(c)); break;
+        }
+#undef DSA_ROW
+        if (r == u) {
+            v = c;
+            break;
+        }
+    }
+    return v;
+}
+
+// Reductions over a segment of w lanes starting at wave lane lane0 (lane =
+// the segment lane): a tree towards the segment's first lane, whose result
+// every lane of the segment then reads.
+__device__ __forceinline__ uint64_t seg_max64(uint64_t k, int lane, int w, int lane0) {
+    const int wl = lane0 + lane;
+    for (int d = 1; d < w; d <<= 1) {
+        const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)k, wl + d);
+        const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(k >> 32), wl + d);
+        if (lane + d < w) k = umax64(k, ((uint64_t)hi << 32) | lo);
+    }
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)k, lane0), hi = (uint32_t)__shfl((int)(uint32_t)(k >> 32), lane0);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int seg_sum(int v, int lane, int w, int lane0) {
+    const int wl = lane0 + lane;
+    for (int d = 1; d < w; d <<= 1) {
+        const int x = __shfl(v, wl + d);
+        if (lane + d < w) v += x;
+    }
+    return __shfl(v, lane0);
+}
+
+// the H of 1-based row i at column 0 (0 past the query: padding rows)
+__device__ __forceinline__ int left_or_pad(int mode, int ends, int o, int e, int i, int m) {
+    return i <= m ? left_value(mode, ends, o, e, i) : 0;
+}
+
+}  // namespace
+
+size_t pk16_lds_bytes(int A) { return (size_t)((A + 1) * (A + 1) + (A + 1)) * 2 + 16; }
+
+template <int MODE, bool TB>
+__global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_waves_per_eu(3))) k_pairpk(PairArgs P, Pk16Args X) {
+    constexpr int T = kTP;
+    extern __shared__ uint16_t sm16[];
+    const int A = P.A, SS = P.A + 1;
+    uint16_t *rmx = sm16 + SS * SS;
+    for (int k = threadIdx.x; k < SS * SS; k += blockDim.x) {
+        const int r = k / SS, c = k - r * SS;
+        sm16[k] = (uint16_t)(int16_t)((r < A && c < A) ? (int)P.subst[r * A + c] : 0);
+    }
+    for (int q = threadIdx.x; q < SS; q += blockDim.x) {
+        int mx = 0;
+        if (q < A)
+            for (int c = 0; c < A; c++) mx = max(mx, (int)P.subst[q * A + c]);
+        rmx[q] = (uint16_t)mx;
+    }
+    __syncthreads();
+    const int vw = blockIdx.x * kPairWaves + (threadIdx.x >> 6);
+    if (vw >= X.n_waves) return;  // no block barrier below; segments never read another segment's lanes
+    const Pk16Wave V = X.waves[vw];
+    const int k_seg = X.lanemap[(int64_t)vw * kWave + (threadIdx.x & 63)];
+    if (k_seg < 0) return;
+    const Pk16Unit U = X.units[V.u0 + k_seg];
+    const int SEG = U.w, lane0 = U.lane0;
+    const int lane = (int)(threadIdx.x & 63) - lane0;
+    const bool hasB = U.b >= 0;
+    const int ub = hasB ? U.b : U.a;
+    const WfPair WA = P.wf[U.a], WB = P.wf[ub];
+    const PairInfo IA = P.pairs[WA.slot], IB = P.pairs[WB.slot];
+    const Pk16Pair KA = X.pk[U.a], KB = X.pk[ub];
+    const int o = P.o, e = P.e, ends = P.ends;
+    const int mA = IA.m, nA = IA.n;
+    const int mB = hasB ? IB.m : 0, nB = hasB ? IB.n : 0;
+    const int SA = (mA + T - 1) / T, SB = (mB + T - 1) / T;
+    const int S = max(SA, SB), passes = (S + SEG - 1) / SEG;
+    const int nmax = max(nA, nB);
+    const int NST = U.nst, Q = NST / kCkCols;
+    const int nsteps = nmax + SEG - 1;
+    const uint8_t *qA = P.q_codes + IA.q_off, *qB = P.q_codes + IB.q_off;
+    const uint8_t *tA = P.t_codes + IA.t_off, *tB = P.t_codes + IB.t_off;
+    uint32_t *ckA = P.tb + 2 * WA.tb, *ckB = P.tb + 2 * WB.tb;
+    uint32_t *bdA = reinterpret_cast<uint32_t *>(P.bnd + WA.bnd), *bdB = reinterpret_cast<uint32_t *>(P.bnd + WB.bnd);
+    const int RS = SS * 2;  // bytes per LDS matrix row
+    const uint32_t bias2 = pack2(KA.bias, KB.bias);
+    const uint32_t o2 = dup(o), e2 = dup(e);
+    const char *smb = reinterpret_cast<const char *>(sm16);
+
+    // global and semi-global: H never exceeds the query's sum of positive row
+    // maxima; a pair whose sum exceeds its limit goes to int32 at once
+    int flagA = 0, flagB = 0;
+    if (MODE != LOCAL) {
+        int uA = 0, uB = 0;
+        for (int i = lane; i < mA; i += SEG) uA += rmx[min((int)qA[i], A - 1)];
+        for (int i = lane; i < mB; i += SEG) uB += rmx[min((int)qB[i], A - 1)];
+        uA = seg_sum(uA, lane, SEG, lane0);
+        uB = seg_sum(uB, lane, SEG, lane0);
+        flagA = uA > KA.hlim;
+        flagB = uB > KB.hlim;
+    }
+    const bool skip = flagA && (flagB || !hasB);
+
+    uint64_t gkA = end_key(0, 0, 0), gkB = gkA;  // local: the lane's best over its strips
+    int gsA = 0, gjA = 0, gsB = 0, gjB = 0;      // global / semi: held by the lane of the last strip
+    const bool qe_free = (MODE == SEMIGLOBAL) && (ends & QE);
+    int QsA = PAD32, QiA = 0, QsB = PAD32, QiB = 0;
+    for (int pass = 0; pass < passes && !skip; pass++) {
+        const int s = pass * SEG + lane;
+        const int i0 = s * T;
+        const bool act = s < S;
+        const bool lastA = (s == SA - 1), lastB = (s == SB - 1);
+        const int rlastA = mA - 1 - i0, rlastB = mB - 1 - i0;
+        uint32_t rowAB[T], H[T], E[T];
+#pragma unroll
+        for (int r = 0; r < T; r++) {
+            const int i = i0 + r;
+            const int cA = i < mA ? min((int)qA[i], A - 1) : A;
+            const int cB = i < mB ? min((int)qB[i], A - 1) : A;
+            rowAB[r] = pack2(cA * RS, cB * RS);
+            H[r] = addu(pack2(left_or_pad(MODE, ends, o, e, i + 1, mA), left_or_pad(MODE, ends, o, e, i + 1, mB)),
+                        bias2);
+            E[r] = (MODE == LOCAL) ? bias2 : subw(H[r], o2);
+        }
+        uint32_t Hd_top = addu(pack2(left_or_pad(MODE, ends, o, e, i0, mA), left_or_pad(MODE, ends, o, e, i0, mB)),
+                               bias2);
+        uint32_t Bv = bias2, Bi2 = 0, Bj2 = 0;  // local: best of this strip, its row and column
+        int resA = 0, LsA = 0, LjA = 0, resB = 0, LsB = 0, LjB = 0;
+        if (MODE != LOCAL) {
+            if (lastA) { resA = left_value(MODE, ends, o, e, mA); LsA = resA; }
+            if (lastB) { resB = left_value(MODE, ends, o, e, mB); LsB = resB; }
+        }
+        uint32_t outH = 0, outF = 0;
+        // this lane's checkpoint words: step t of the bottom row at
+        // bot + t * nsp, the q-th stored column at left + q * nsp * 16
+        const int nspA = min(SEG, SA - pass * SEG), nspB = min(SEG, SB - pass * SEG);
+        const int64_t botA = (int64_t)pass * NST * SEG + lane, botB = botA;
+        const int64_t lftA = (int64_t)SA * NST + ((int64_t)pass * Q * SEG + lane) * T;
+        const int64_t lftB = (int64_t)SB * NST + ((int64_t)pass * Q * SEG + lane) * T;
+        // the previous pass's last strip (lane 0 reads it): column j of its
+        // bottom row at prv + (j + SEG - 2) * SEG (with checkpoints), or bd[j - 1]
+        const int prv = (pass - 1) * NST * SEG + (SEG - 1);
+        const bool rdA = lane == 0 && pass > 0 && s < SA, rdB = lane == 0 && pass > 0 && s < SB;
+        // one step ahead: the raw target codes of the lane's next column (256
+        // past a target) and lane 0's next boundary words; a load is first
+        // used one step after it is issued
+        // A half with no such strip or column gets H = 0 and F = -o there,
+        // which keeps its padding cells within range
+        const uint32_t w0A = pack2(KA.bias, KA.bias - o), w0B = pack2(KB.bias, KB.bias - o);
+        uint32_t ca = 256u, cb = 256u, wa = w0A, wb = w0B;
+        auto fetch_col = [&](int j) {
+            ca = 256u;
+            cb = 256u;
+            if (act && j >= 1 && j <= nA) ca = tA[j - 1];
+            if (act && j >= 1 && j <= nB) cb = tB[j - 1];
+            wa = w0A;
+            wb = w0B;
+            if (TB) {
+                if (rdA && j >= 1 && j <= nA) wa = ckA[prv + (j + SEG - 2) * SEG];
+                if (rdB && j >= 1 && j <= nB) wb = ckB[prv + (j + SEG - 2) * SEG];
+            } else {
+                if (rdA && j >= 1 && j <= nA) wa = bdA[j - 1];
+                if (rdB && j >= 1 && j <= nB) wb = bdB[j - 1];
+            }
+        };
+        fetch_col(1 - lane);
+        for (int t = 0; t < nsteps; t++) {
+#pragma unroll
+            for (int r = 0; r < T; r++) asm volatile("" : "+v"(rowAB[r]));  // the two row offsets stay one register
+            uint32_t rH = (uint32_t)lane_above((int)outH);
+            uint32_t rF = (uint32_t)lane_above((int)outF);
+            const int j = t - lane + 1;
+            const uint32_t ca0 = ca, cb0 = cb, wa0 = wa, wb0 = wb;
+            fetch_col(j + 1);
+            if (act && j >= 1 && j <= nmax) {
+                if (lane == 0) {
+                    if (pass == 0) {  // the top boundary row (0 past a target)
+                        const int tv = top_value(MODE, ends, o, e, j);
+                        rH = addu(pack2(j <= nA ? tv : 0, j <= nB ? tv : 0), bias2);
+                        rF = subw(rH, o2);
+                    } else {
+                        rH = lo_lo(wa0, wb0);
+                        rF = hi_hi(wa0, wb0);
+                    }
+                }
+                // column codes clamped to the alphabet, A (scores 0) past a target
+                const int bA2 = 2 * (ca0 > 255u ? A : min((int)ca0, A - 1));
+                const int bB2 = 2 * (cb0 > 255u ? A : min((int)cb0, A - 1));
+                uint32_t Hd = Hd_top;
+                Hd_top = rH;
+                uint32_t F = rF;
+                uint32_t cm = Bv, held = 0;
+                // scores four rows ahead: the LDS reads of the next group of
+                // four rows are in flight while the current group computes
+                uint32_t na[4], nb[4], cur[4];
+                auto fetch = [&](int g) {
+#pragma unroll
+                    for (int x = 0; x < 4; x++) {
+                        const uint32_t ra = rowAB[4 * g + x];
+                        na[x] = *reinterpret_cast<const uint16_t *>(smb + (ra & 0xffffu) + bA2);
+                        nb[x] = *reinterpret_cast<const uint16_t *>(smb + (ra >> 16) + bB2);
+                    }
+                };
+                fetch(0);
+#pragma unroll
+                for (int r = 0; r < T; r++) {
+                    if ((r & 3) == 0) {
+#pragma unroll
+                        for (int x = 0; x < 4; x++) cur[x] = na[x] | (nb[x] << 16);
+                        if (r + 4 < T) fetch((r >> 2) + 1);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    const uint32_t t2 = addu(Hd, cur[r & 3]);
+                    Hd = H[r];
+                    const uint32_t h = max3h(t2, E[r], F);
+                    if (MODE == LOCAL) {
+                        if (r & 1) cm = max3h(cm, held, h);
+                        else held = h;
+                    }
+                    const uint32_t ho = subw(h, o2);
+                    if (MODE == LOCAL) {
+                        E[r] = max3h(subw(E[r], e2), ho, bias2);
+                        F = max3h(subw(F, e2), ho, bias2);
+                    } else {
+                        E[r] = maxu(subw(E[r], e2), ho);
+                        F = maxu(subw(F, e2), ho);
+                    }
+                    H[r] = h;
+                }
+                // keep the E updates in the column's block, between the F
+                // chain's steps, rather than sunk past the end-cell branches
+#pragma unroll
+                for (int r = 0; r < T; r++) asm volatile("" : "+v"(E[r]));
+                if (MODE == LOCAL) {
+                    const uint32_t d = cm ^ Bv;  // nonzero in a half whose best grew
+                    if (d) {
+                        const uint32_t mk = nzmask(d);
+                        const uint32_t row = first_row_of(H, cm);
+                        Bi2 = bfi(mk, addu(row, dup(i0 + 1)), Bi2);
+                        Bj2 = bfi(mk, dup(j), Bj2);
+                        Bv = cm;
+                    }
+                } else {
+                    if (lastA && j <= nA && ((ends & TE) || j == nA)) {
+                        const int v = (int)(row_of16(H, rlastA) & 0xffffu) - KA.bias;
+                        if (!(ends & TE)) resA = v;
+                        else if (v > LsA) { LsA = v; LjA = j; }
+                    }
+                    if (lastB && j <= nB && ((ends & TE) || j == nB)) {
+                        const int v = (int)(row_of16(H, rlastB) >> 16) - KB.bias;
+                        if (!(ends & TE)) resB = v;
+                        else if (v > LsB) { LsB = v; LjB = j; }
+                    }
+                    if (qe_free) {
+                        if (j == nA && s < SA) {
+#pragma unroll
+                            for (int r = 0; r < T; r++) {
+                                const int v = (int)(H[r] & 0xffffu) - KA.bias;
+                                if (i0 + r < mA && v > QsA) { QsA = v; QiA = i0 + r + 1; }
+                            }
+                        }
+                        if (j == nB && s < SB) {
+#pragma unroll
+                            for (int r = 0; r < T; r++) {
+                                const int v = (int)(H[r] >> 16) - KB.bias;
+                                if (i0 + r < mB && v > QsB) { QsB = v; QiB = i0 + r + 1; }
+                            }
+                        }
+                    }
+                }
+                outH = H[T - 1];
+                outF = F;
+                if (TB) {
+                    // this step's bottom row, and every kCkCols steps the strip's column
+                    if (s < SA) ckA[botA + (int64_t)t * nspA] = lo_lo(outH, outF);
+                    if (s < SB) ckB[botB + (int64_t)t * nspB] = hi_hi(outH, outF);
+                } else if (lane == SEG - 1 && pass + 1 < passes) {
+                    if (j <= nA) bdA[j - 1] = lo_lo(outH, outF);
+                    if (j <= nB) bdB[j - 1] = hi_hi(outH, outF);
+                }
+            }
+            if (TB && ((t + 1) & (kCkCols - 1)) == 0) {
+                const int q = (t + 1) / kCkCols - 1;
+                if (s < SA) {
+                    uint4 *d = reinterpret_cast<uint4 *>(ckA + lftA + (int64_t)q * nspA * T);
+#pragma unroll
+                    for (int x = 0; x < T / 4; x++)
+                        d[x] = make_uint4(lo_lo(H[4 * x], E[4 * x]), lo_lo(H[4 * x + 1], E[4 * x + 1]),
+                                          lo_lo(H[4 * x + 2], E[4 * x + 2]), lo_lo(H[4 * x + 3], E[4 * x + 3]));
+                }
+                if (s < SB) {
+                    uint4 *d = reinterpret_cast<uint4 *>(ckB + lftB + (int64_t)q * nspB * T);
+#pragma unroll
+                    for (int x = 0; x < T / 4; x++)
+                        d[x] = make_uint4(hi_hi(H[4 * x], E[4 * x]), hi_hi(H[4 * x + 1], E[4 * x + 1]),
+                                          hi_hi(H[4 * x + 2], E[4 * x + 2]), hi_hi(H[4 * x + 3], E[4 * x + 3]));
+                }
+            }
+        }
+        if (act) {
+            if (MODE == LOCAL) {
+                const int bA = (int)(Bv & 0xffffu), bB = (int)(Bv >> 16);
+                if (bA > KA.bias + KA.hlim) flagA = 1;
+                if (bB > KB.bias + KB.hlim) flagB = 1;
+                if (bA > KA.bias) gkA = umax64(gkA, end_key(bA - KA.bias, (int)(Bj2 & 0xffffu), (int)(Bi2 & 0xffffu)));
+                if (bB > KB.bias) gkB = umax64(gkB, end_key(bB - KB.bias, (int)(Bj2 >> 16), (int)(Bi2 >> 16)));
+            } else {
+                if (lastA) {
+                    if (ends & TE) { gsA = LsA; gjA = LjA; }
+                    else { gsA = resA; gjA = nA; }
+                }
+                if (lastB) {
+                    if (ends & TE) { gsB = LsB; gjB = LjB; }
+                    else { gsB = resB; gjB = nB; }
+                }
+            }
+        }
+    }
+
+    // per pair: the end cell over the segment's lanes
+    int GsA, GjA, GiA, GsB, GjB, GiB;
+    if (MODE == LOCAL) {
+        flagA = seg_sum(flagA, lane, SEG, lane0) > 0;
+        flagB = seg_sum(flagB, lane, SEG, lane0) > 0;
+        gkA = seg_max64(gkA, lane, SEG, lane0);
+        gkB = seg_max64(gkB, lane, SEG, lane0);
+        GsA = key_score(gkA); GjA = key_j(gkA); GiA = key_i(gkA);
+        GsB = key_score(gkB); GjB = key_j(gkB); GiB = key_i(gkB);
+    } else {
+        GsA = __shfl(gsA, lane0 + (SA > 0 ? (SA - 1) % SEG : 0));
+        GjA = __shfl(gjA, lane0 + (SA > 0 ? (SA - 1) % SEG : 0));
+        GsB = __shfl(gsB, lane0 + (SB > 0 ? (SB - 1) % SEG : 0));
+        GjB = __shfl(gjB, lane0 + (SB > 0 ? (SB - 1) % SEG : 0));
+        GiA = mA;
+        GiB = mB;
+        if (qe_free) {
+            // the last column's best over the lanes (row 0 included), then
+            // against the last row's candidate
+            uint64_t qa = (lane == 0) ? end_key(top_value(MODE, ends, o, e, nA), nA, 0) : end_key(PAD32, nA, 0);
+            uint64_t qb = (lane == 0) ? end_key(top_value(MODE, ends, o, e, nB), nB, 0) : end_key(PAD32, nB, 0);
+            if (QsA > PAD32) qa = umax64(qa, end_key(QsA, nA, QiA));
+            if (QsB > PAD32) qb = umax64(qb, end_key(QsB, nB, QiB));
+            qa = seg_max64(qa, lane, SEG, lane0);
+            qb = seg_max64(qb, lane, SEG, lane0);
+            const uint64_t ka = umax64(end_key(GsA, GjA, GiA), qa), kb = umax64(end_key(GsB, GjB, GiB), qb);
+            GsA = key_score(ka); GjA = key_j(ka); GiA = key_i(ka);
+            GsB = key_score(kb); GjB = key_j(kb); GiB = key_i(kb);
+        }
+    }
+    if (lane != 0) return;
+    // the unit's records again, from memory: an opaque index keeps the
+    // compiler from holding them in registers through the step loop
+    int ui = V.u0 + k_seg;
+    asm volatile("" : "+v"(ui));
+    const Pk16Unit U2 = X.units[ui];
+    for (int h = 0; h < (hasB ? 2 : 1); h++) {
+        const int fl = h ? flagB : flagA;
+        const int wk = h ? U2.b : U2.a;
+        X.flag[wk] = fl;
+        if (fl) continue;  // the int32 kernel writes this pair's results
+        const int slot = P.wf[wk].slot;
+        const PairInfo I = P.pairs[slot];
+        int Gs = h ? GsB : GsA, Gj = h ? GjB : GjA, Gi = h ? GiB : GiA;
+        const int m = I.m, n = I.n;
+        if (m == 0) {  // empty query: the last row is the top boundary row
+            if (MODE == LOCAL) { Gs = 0; }
+            else if (MODE == SEMIGLOBAL && (ends & TE)) { Gs = 0; Gj = 0; }
+            else { Gs = top_value(MODE, ends, o, e, n); Gj = n; }
+            Gi = 0;
+        }
+        int qe, te;
+        if (MODE == LOCAL) { qe = Gs > 0 ? Gi - 1 : -1; te = Gs > 0 ? Gj - 1 : -1; }
+        else { qe = Gi - 1; te = Gj - 1; }
+        P.out_score[I.res] = Gs;
+        if (P.out_qend) P.out_qend[I.res] = qe;
+        if (P.out_tend) P.out_tend[I.res] = te;
+        if (P.out_status) P.out_status[I.res] = 0;  // exact in int16
+        if (TB) {
+            P.end_i[slot] = (MODE == LOCAL && Gs == 0) ? -1 : Gi;
+            P.end_j[slot] = Gj;
+        } else {
+            if (P.out_qbeg) P.out_qbeg[I.res] = -1;
+            if (P.out_tbeg) P.out_tbeg[I.res] = -1;
+        }
+    }
+}
+
+hipError_t launch_pairpk(const PairArgs &a, const Pk16Args &x, int mode, hipStream_t s) {
+    if (x.n_waves <= 0) return hipSuccess;
+    const int nb = (x.n_waves + kPairWaves - 1) / kPairWaves;
+    const size_t lds = pk16_lds_bytes(a.A);
+#define LP(MODE, TBV) hipLaunchKernelGGL((k_pairpk<MODE, TBV>), dim3(nb), dim3(kPairWaves * kWave), lds, s, a, x)
+    if (a.traceback) {
+        if (mode == LOCAL) LP(LOCAL, true); else if (mode == GLOBAL) LP(GLOBAL, true); else LP(SEMIGLOBAL, true);
+    } else {
+        if (mode == LOCAL) LP(LOCAL, false); else if (mode == GLOBAL) LP(GLOBAL, false); else LP(SEMIGLOBAL, false);
+    }
+#undef LP
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Walk from checkpoints: 16 lanes per pair, four pairs per block.  At each
+// step the pair stands in the tile of strip s = (i - 1) / 16 between the
+// stored column c0 < j (or column 0) and column j.  The group recomputes the
+// tile's rows (16 s, i] and columns (c0, j] as a wavefront over its lanes
+// (lane r owns row 16 s + r + 1 and takes the row above from lane r - 1 by a
+// DPP row shift), starting from the stored left column, the bottom row of
+// strip s - 1 (or the top boundary) and the matrix; every lane keeps its
+// row's 4-bit direction codes (those of the int32 kernels: bits 0-1 where H
+// came from, 0 zero, 1 diagonal, 2 E, 3 F; bit 2 E extends; bit 3 F extends)
+// and puts them in LDS.  All 16 lanes then follow the same codes out of the
+// tile (one of them stores the CIGAR runs).
+constexpr int kCkWalkThreads = 64;
+constexpr int kCkGroup = 16;
+
+__device__ __forceinline__ int row_above(int v) {  // lane r - 1 of the 16-lane row (0 for lane 0)
+    return __builtin_amdgcn_update_dpp(0, v, 0x111 /* row_shr:1 */, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int row_next(int v) {   // lane r + 1 of the 16-lane row (0 for lane 15)
+    return __builtin_amdgcn_update_dpp(0, v, 0x101 /* row_shl:1 */, 0xf, 0xf, false);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args X) {
+    // per lane: its row's 16 cells, one byte each (the 4-bit code, bit 4 = residues equal)
+    __shared__ uint32_t tile[kCkWalkThreads * kCkCols / 4];
+    __shared__ int16_t sm[(kMaxAlphabet16 + 1) * (kMaxAlphabet16 + 1)];
+    const int A = P.A;
+    for (int k = threadIdx.x; k < A * A; k += blockDim.x) sm[k] = (int16_t)P.subst[k];
+    __syncthreads();
+    const int r = threadIdx.x & (kCkGroup - 1);
+    const int gbase = threadIdx.x & ~(kCkGroup - 1);  // the group's first thread
+    const int k = blockIdx.x * (kCkWalkThreads / kCkGroup) + (threadIdx.x / kCkGroup);
+    if (k >= P.n_wf) return;  // no block barrier below; groups never read another group's lanes
+    if (X.flag[k]) return;    // walked by the int32 path
+    const WfPair W = P.wf[k];
+    const PairInfo I = P.pairs[W.slot];
+    const Pk16Pair KP = X.pk[k];
+    const int o = P.o, e = P.e, ends = P.ends;
+    const int m = I.m, n = I.n, S = (m + kTP - 1) / kTP;
+    const int seg = KP.w, NST = KP.nst, bias = KP.bias;
+    const uint32_t *ck = P.tb + 2 * W.tb;
+    const uint8_t *qc = P.q_codes + I.q_off, *tc = P.t_codes + I.t_off;
+    RunWriter Wr{P.cigar, I.cig_off, I.cig_off + I.cig_cap};
+    Wr.store = (r == 0);
+    int i = P.end_i[W.slot], j = P.end_j[W.slot];
+    if (i < 0) {  // local alignment of score 0: nothing to trace
+        if (r == 0) {
+            if (P.out_qbeg) P.out_qbeg[I.res] = -1;
+            if (P.out_tbeg) P.out_tbeg[I.res] = -1;
+            P.cig_off_out[I.res] = I.cig_off;
+            P.cig_len_out[I.res] = 0;
+        }
+        return;
+    }
+    uint8_t *mine = reinterpret_cast<uint8_t *>(tile) + kCkCols * threadIdx.x;
+    const uint8_t *grp = reinterpret_cast<const uint8_t *>(tile) + kCkCols * gbase;
+    int state = 0;  // 0 = H, 1 = E, 2 = F
+    int budget = 2 * (m + n) + 4;
+    for (;;) {
+        if (i == 0 || j == 0) {  // on the boundary, in state H
+            if (MODE != LOCAL) {
+                if (i == 0 && j > 0 && !(ends & TB)) { Wr.emit(OP_D, (uint32_t)j); j = 0; }
+                else if (j == 0 && i > 0 && !(ends & QB)) { Wr.emit(OP_I, (uint32_t)i); i = 0; }
+            }
+            break;
+        }
+        if (--budget < 0) break;
+        const int s = (i - 1) / kTP, i0 = s * kTP, l = s % seg;
+        int c0 = j - 1 - ((j - 1 + l) & (kCkCols - 1));
+        if (c0 < 1) c0 = 0;
+        const int nr = i - i0, nc = j - c0;  // 1 .. 16 each
+        // lane r: row i0 + r + 1, its residue and left-column H and E;
+        // lane x: column c0 + 1 + x, its residue and top-row H and F (the
+        // bottom row of strip s - 1, or the top boundary)
+        const int ri = i0 + r + 1;
+        const int qcode = (r < nr) ? (int)qc[ri - 1] : 0;
+        const int qrow = min(qcode, A - 1) * A;
+        int Hl, El;
+        if (c0 >= 1) {
+            const uint32_t w = ck[pk16_left_at(s, (c0 + l) / kCkCols - 1, S, seg, NST) + r];
+            Hl = (int)(w & 0xffffu) - bias;
+            El = (int)(w >> 16) - bias;
+        } else {
+            Hl = left_value(MODE, ends, o, e, ri);
+            El = (MODE == LOCAL) ? 0 : Hl - o;
+        }
+        const int lp = (s + seg - 1) % seg;  // lane of strip s - 1 in the fill
+        int colH = 0, colF = 0, colT = 0;
+        if (r < nc) {
+            const int c = c0 + 1 + r;
+            colT = (int)tc[c - 1];
+            if (s == 0) {
+                colH = top_value(MODE, ends, o, e, c);
+                colF = colH - o;
+            } else {
+                const uint32_t w = ck[pk16_bot_at(s - 1, c + lp - 1, S, seg, NST)];
+                colH = (int)(w & 0xffffu) - bias;
+                colF = (int)(w >> 16) - bias;
+            }
+        }
+        int corner;  // H(i0, c0), the diagonal of row i0 + 1 in column c0 + 1
+        if (s == 0) corner = top_value(MODE, ends, o, e, c0);
+        else if (c0 == 0) corner = left_value(MODE, ends, o, e, i0);
+        else corner = (int)(ck[pk16_bot_at(s - 1, c0 + lp - 1, S, seg, NST)] & 0xffffu) - bias;
+        // wavefront: at step u lane r computes column x = u - r of its row;
+        // lane 0 takes column u from the top arrays, which shift one lane
+        // towards lane 0 every step, and each lane hands H, F and the
+        // column's residue to the lane below
+        int Hd_top = row_above(Hl);
+        if (r == 0) Hd_top = corner;
+        int outH = 0, outF = 0, outT = 0;
+        const int nsteps = nc + nr - 1;
+        for (int u = 0; u < nsteps; u++) {
+            int rH = row_above(outH), rF = row_above(outF), rT = row_above(outT);
+            if (r == 0) { rH = colH; rF = colF; rT = colT; }
+            colH = row_next(colH);
+            colF = row_next(colF);
+            colT = row_next(colT);
+            const int x = u - r;
+            if (x >= 0 && x < nc && r < nr) {
+                const int hd = Hd_top;
+                Hd_top = rH;
+                const int t = hd + (int)sm[qrow + min(rT, A - 1)];
+                const int Ein = El, Fin = rF;
+                int h = max(max(t, Ein), Fin);
+                if (MODE == LOCAL) h = max(h, 0);
+                const int ho = h - o;
+                uint32_t code = (h == t) ? 1u : ((h == Ein) ? 2u : 3u);
+                if (MODE == LOCAL && h == 0) code = 0u;
+                code |= (Ein > Hl - o) ? 4u : 0u;  // E(i, c) extends E(i, c - 1)
+                code |= (Fin > rH - o) ? 8u : 0u;  // F(i, c) extends F(i - 1, c)
+                code |= (qcode == rT) ? 16u : 0u;  // residues equal (= or X on the diagonal)
+                int En = max(Ein - e, ho), Fn = max(Fin - e, ho);
+                if (MODE == LOCAL) { En = max(En, 0); Fn = max(Fn, 0); }
+                El = En;
+                Hl = h;
+                outH = h;
+                outF = Fn;
+                outT = rT;
+                mine[x] = (uint8_t)code;
+            }
+        }
+        asm volatile("" ::: "memory");  // the codes are in LDS before any lane reads them
+        // follow the codes out of the tile (every lane the same walk)
+        bool stop = false;
+        while (i > i0 && j > c0) {
+            if (--budget < 0) { stop = true; break; }
+            const uint32_t code = grp[kCkCols * (i - i0 - 1) + (j - c0 - 1)];
+            if (state == 0) {
+                const uint32_t src = code & 3u;
+                if (src == 0u) { stop = true; break; }
+                if (src == 1u) {
+                    Wr.emit((code & 16u) ? OP_EQ : OP_X, 1);
+                    i--;
+                    j--;
+                } else {
+                    state = (src == 2u) ? 1 : 2;
+                }
+            } else if (state == 1) {
+                Wr.emit(OP_D, 1);
+                j--;
+                if (!((code >> 2) & 1u)) state = 0;
+            } else {
+                Wr.emit(OP_I, 1);
+                i--;
+                if (!((code >> 3) & 1u)) state = 0;
+            }
+        }
+        asm volatile("" ::: "memory");  // the next tile's codes are written after these reads
+        if (stop) break;
+    }
+    Wr.flush();
+    if (r != 0) return;
+    if (P.out_qbeg) P.out_qbeg[I.res] = i;
+    if (P.out_tbeg) P.out_tbeg[I.res] = j;
+    P.cig_off_out[I.res] = Wr.pos;
+    P.cig_len_out[I.res] = (int32_t)(I.cig_off + I.cig_cap - Wr.pos);
+    if (Wr.truncated && P.out_status) P.out_status[I.res] |= 2;  // DSA_ST_TRUNCATED
+}
+
+hipError_t launch_walk_ck(const PairArgs &a, const Pk16Args &x, int mode, hipStream_t s) {
+    if (a.n_wf <= 0) return hipSuccess;
+    const int bs = kCkWalkThreads, per = kCkWalkThreads / kCkGroup;
+    const unsigned nb = (unsigned)((a.n_wf + per - 1) / per);
+    if (mode == LOCAL) hipLaunchKernelGGL(k_walk_ck<LOCAL>, dim3(nb), dim3(bs), 0, s, a, x);
+    else if (mode == GLOBAL) hipLaunchKernelGGL(k_walk_ck<GLOBAL>, dim3(nb), dim3(bs), 0, s, a, x);
+    else hipLaunchKernelGGL(k_walk_ck<SEMIGLOBAL>, dim3(nb), dim3(bs), 0, s, a, x);
+    return hipGetLastError();
+}
+
+}  // namespace dsa

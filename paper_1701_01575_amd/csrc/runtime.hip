@@ -17,6 +17,7 @@
 
 #include "dsa.h"
 #include "internal.h"
+#include "pair16.h"
 
 using namespace dsa;
 
@@ -612,6 +613,7 @@ PairRoute pair_route(const Tuning &t) {
 // (the hit traceback lays out its plan in a workspace sized for the worst case).
 struct PairCaps {
     int64_t slots = 0, groups = 0, wf = 0, bnd = 0, tpk = 0, tb = 0, bndw = 0, tbw = 0, waves = 0;
+    int64_t units = 0, pkwaves = 0;  // the packed int16 fill's units and waves
 };
 
 struct Plan {
@@ -696,9 +698,20 @@ struct PairPlan {
     std::vector<int64_t> wf_chunk_pair;   // first pair of each chunk (+ end)
     int64_t wf_tb_max = 0, wf_tb_total = 0, wf_bnd_total = 0;  // uint32 / uint32 / uint2
     int wf_buffers = 1;                 // code buffers of wf_tb_max words each
+    // packed int16 fill of the wavefront pairs (pk): units of two pairs, their
+    // waves per chunk, per pair its bias and limit, and per pair a flag (host
+    // value 1 for pairs it cannot hold; the fill sets the rest)
+    bool pk = false;
+    std::vector<Pk16Unit> units;
+    std::vector<Pk16Wave> pkwaves;
+    std::vector<Pk16Pair> pkpairs;
+    std::vector<int32_t> pkflags;
+    std::vector<int8_t> lanemap;          // per packed wave, 64 lanes: the lane's unit in the wave
+    std::vector<int64_t> pk_chunk_first;  // first packed wave of each chunk (+ end)
     std::vector<std::pair<int, int64_t>> plain_seq;  // plain: (0 group | 1 wavefront, index) in input order
     size_t off_slots = 0, off_groups = 0, off_wf = 0, off_waves = 0, off_subst = 0, table_bytes = 0;
     size_t off_pssm = 0, pssm_bytes = 0;  // the call's own device profile (pairwise calls with one)
+    size_t off_units = 0, off_pkwaves = 0, off_pkpairs = 0, off_flags = 0, off_lanemap = 0;
     size_t off_end = 0, off_bnd = 0, off_tpk = 0, off_tb = 0, off_bndw = 0, off_tbw = 0, total = 0;
 };
 
@@ -713,6 +726,8 @@ PairCaps caps_of(const PairPlan &P) {
     c.tb = P.tb_max;
     c.bndw = P.wf_bnd_total;
     c.tbw = P.wf_tb_max * P.wf_buffers;
+    c.units = (int64_t)P.units.size();
+    c.pkwaves = (int64_t)P.pkwaves.size();
     return c;
 }
 
@@ -725,6 +740,11 @@ void layout_pair_plan(PairPlan &P, const PairCaps &c, int A) {
     P.off_waves = o; o = align_up(o + cnt(c.waves) * sizeof(WfWave), 256);
     P.off_subst = o; o = align_up(o + (size_t)A * A, 256);
     P.off_pssm = o; o = align_up(o + P.pssm_bytes, 256);
+    P.off_units = o; o = align_up(o + (size_t)c.units * sizeof(Pk16Unit), 256);
+    P.off_pkwaves = o; o = align_up(o + (size_t)c.pkwaves * sizeof(Pk16Wave), 256);
+    P.off_pkpairs = o; o = align_up(o + (size_t)(c.units ? cnt(c.wf) : 0) * sizeof(Pk16Pair), 256);
+    P.off_flags = o; o = align_up(o + (size_t)(c.units ? cnt(c.wf) : 0) * sizeof(int32_t), 256);
+    P.off_lanemap = o; o = align_up(o + (size_t)c.pkwaves * kWave, 256);
     P.table_bytes = o;
     P.off_end = o; o = align_up(o + cnt(c.slots) * 8, 256);
     P.off_bnd = o; o = align_up(o + cnt(c.bnd) * 8, 256);
@@ -741,17 +761,25 @@ struct PairSpec {
     int64_t pssm_row = 0;  // the query's first row in the device profile
 };
 
-// Bytes of direction codes per chunk: a sixteenth of the device's memory,
-// at most 16 GiB (the wavefront kind keeps two chunks when it has several).
+// Bytes of direction codes (or checkpoints) per chunk: a sixth of the
+// device's memory, at most 48 GiB (the int32 wavefront kind keeps two chunks
+// when it has several).
 int64_t tb_budget_bytes() {
-    int64_t b = (int64_t)16 << 30;
+    int64_t b = (int64_t)48 << 30;
     int dev = 0;
     size_t total = 0;
     if (hipGetDevice(&dev) == hipSuccess && hipDeviceTotalMem(&total, dev) == hipSuccess && total > 0)
-        b = std::min<int64_t>(b, std::max<int64_t>((int64_t)(total / 16), (int64_t)1 << 28));
+        b = std::min<int64_t>(b, std::max<int64_t>((int64_t)(total / 6), (int64_t)1 << 28));
     if (const char *v = getenv("DSA_TB_BUDGET")) b = std::max<int64_t>(atoll(v), 1 << 20);
     if (t_budget_cap > 0) b = std::min(b, t_budget_cap);
     return b;
+}
+
+// DSA_PAIR_INT32=1: every wavefront pair through the exact int32 kernel (the
+// packed int16 fill off), for comparisons.
+bool pk16_disabled() {
+    const char *v = getenv("DSA_PAIR_INT32");
+    return v && atoi(v) != 0;
 }
 
 // Reorder idx by key(idx) descending, equal keys keeping their order (the
@@ -780,11 +808,37 @@ static void sort_desc_stable(std::vector<int64_t> &idx, Key key) {
     for (size_t p = 0; p < n; p++) idx[p] = rec[p].v;
 }
 
+// The packed int16 fill: whether a call may use it, its gap penalties and
+// the extremes of its scores (smin = -(most negative score), smax = the
+// largest, both at least 0).
+struct PkSpec {
+    bool on = false;
+    int o = 0, e = 0, smin = 0, smax = 0;
+};
+// Pairs whose H limit is below this run int32 from the start.
+constexpr int kPk16MinLimit = 256;
+
+// Bias and H limit of a pair in the packed fill.  The lowest value the
+// recurrence reaches is above -(G(m) + G(n) + o + e + smin) in global and
+// semi-global mode, G(L) = o + (L - 1) e the cost of a gap of length L (every
+// H is at least the score of the path of one vertical and one horizontal
+// gap; E, F and the diagonal sum go one step lower), and above -(o + e + smin)
+// in local mode (E and F are floored at 0).  Held as value + bias with bias =
+// 1024 + that depth, every value is a positive normal binary16 pattern while
+// H stays at most hlim, which keeps H + s within 0x7bff, the largest finite
+// one.
+void pk16_bias(const PkSpec &k, int mode, int64_t m, int64_t n, int32_t *bias, int32_t *hlim) {
+    auto G = [&](int64_t L) -> int64_t { return L > 0 ? k.o + (L - 1) * (int64_t)k.e : 0; };
+    const int64_t depth = (mode == DSA_LOCAL ? 0 : G(m) + G(n)) + k.o + k.e + k.smin;
+    *bias = (int32_t)std::min<int64_t>(0x0400 + depth, 0x7fff);
+    *hlim = (int32_t)std::max<int64_t>(0x7bff - (0x0400 + depth) - k.smax, -1);
+}
+
 // Group and lay out a list of pairs.  n_results sizes the CIGAR regions (one
 // per result index, in result order); tb_cap caps the codes of one chunk.
 void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mode, int ends,
                      bool traceback, int64_t cigar_capacity, int A, int64_t tb_cap, PairPlan &P,
-                     bool plain, const PairRoute &route) {
+                     bool plain, const PairRoute &route, const PkSpec &pk = PkSpec()) {
     P.mode = mode;
     P.ends = ends;
     P.traceback = traceback;
@@ -907,31 +961,96 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     // pairs of a width largest first), then the waves longest first across
     // widths; codes chunked at wave boundaries.  Plain: one pair per wave, in
     // input order.  Pairs are stored in wave order; their slots follow the
-    // groups'.
+    // groups'.  With the packed fill, the pairs it can hold go two to a
+    // segment (waves of 64 / seg units), the others to waves of the int32
+    // kernel, and every packed wave also gets the int32 waves of its pairs
+    // (they run only the pairs the packed fill flags).
     std::vector<int> segk(sp.size(), 0);
     for (int64_t k : worder) segk[k] = wf_seg(sp[k].m);
-    auto seg_of = [&](int64_t k) { return segk[k]; };
     if (!plain)  // segment width, then cells (m, n < 2^16: cells < 2^32)
         sort_desc_stable(worder, [&](int64_t k) {
             return ((uint64_t)segk[k] << 33) | (uint64_t)(sp[k].m * sp[k].n);
         });
+    const bool use_pk = pk.on && !plain;
+    std::vector<int32_t> pbias(sp.size(), 0), phlim(sp.size(), 0);
+    std::vector<char> pkok(sp.size(), 0);
+    if (use_pk)
+        for (int64_t k : worder) {
+            pk16_bias(pk, mode, sp[k].m, sp[k].n, &pbias[k], &phlim[k]);
+            pkok[k] = phlim[k] >= kPk16MinLimit;
+        }
+    auto strips_of = [&](int64_t k) { return (sp[k].m + kTP - 1) / kTP; };
+    // A wave to plan: packed (units [u_first, +u_count) of `units`) or int32
+    // (pairs [first, +count) of `wo`, one segment width).
     struct WaveSpec {
-        int64_t first = 0, count = 0;  // into worder
+        bool packed = false;
+        int64_t first = 0, count = 0;    // int32 kind: into wo
+        int64_t u_first = 0, u_count = 0;
         int seg = 0;
-        int64_t cost = 0;              // steps: passes x (longest target + seg - 1)
+        int64_t cost = 0;                // steps: passes x (longest target + lanes - 1)
     };
+    struct UnitSpec {
+        int64_t a = -1, b = -1;          // into sp
+        int w = 0;
+        int64_t nst = 0, cost = 0;
+    };
+    std::vector<int64_t> wo;             // pairs of the int32 kind in wave order
+    std::vector<UnitSpec> us;
     std::vector<WaveSpec> wv;
-    for (size_t k = 0; k < worder.size(); k++) {
-        const int seg = seg_of(worder[k]);
-        if (plain || wv.empty() || wv.back().seg != seg || wv.back().count == kWave / seg) {
+    if (use_pk) {
+        // units of two pairs with equal or neighbouring strip counts, as many
+        // lanes as strips (passes of equal width beyond 64 strips)
+        std::vector<int64_t> el;
+        for (int64_t k : worder)
+            if (pkok[k]) el.push_back(k);
+        sort_desc_stable(el, [&](int64_t k) { return ((uint64_t)strips_of(k) << 17) | (uint64_t)sp[k].n; });
+        for (size_t q = 0; q < el.size(); q += 2) {
+            UnitSpec u;
+            u.a = el[q];
+            u.b = q + 1 < el.size() ? el[q + 1] : -1;
+            const int64_t S = std::max(strips_of(u.a), u.b >= 0 ? strips_of(u.b) : 0);
+            const int64_t nmax = std::max(sp[u.a].n, u.b >= 0 ? sp[u.b].n : 0);
+            const int64_t passes = std::max<int64_t>((S + kWave - 1) / kWave, 1);
+            u.w = (int)std::max<int64_t>((S + passes - 1) / passes, 1);
+            u.nst = (int64_t)align_up((size_t)(nmax + u.w - 1), kCkCols);
+            u.cost = passes * (nmax + u.w - 1);
+            us.push_back(u);
+        }
+        std::vector<int64_t> ui(us.size());
+        for (size_t v = 0; v < us.size(); v++) ui[v] = (int64_t)v;
+        sort_desc_stable(ui, [&](int64_t v) { return (uint64_t)us[v].cost; });
+        std::vector<UnitSpec> sorted(us.size());
+        for (size_t v = 0; v < us.size(); v++) sorted[v] = us[ui[v]];
+        us.swap(sorted);
+        // waves of consecutive units while their lanes fit in 64
+        for (size_t v = 0; v < us.size();) {
             WaveSpec x;
-            x.first = (int64_t)k;
+            x.packed = true;
+            x.u_first = (int64_t)v;
+            int lanes = 0;
+            while (v < us.size() && lanes + us[v].w <= kWave) {
+                lanes += us[v].w;
+                x.cost = std::max(x.cost, us[v].cost);
+                v++;
+                x.u_count++;
+            }
+            wv.push_back(x);
+        }
+    }
+    for (size_t q = 0; q < worder.size(); q++) {  // the int32 kind
+        const int64_t k = worder[q];
+        if (use_pk && pkok[k]) continue;
+        const int seg = segk[k];
+        if (plain || wv.empty() || wv.back().packed || wv.back().seg != seg || wv.back().count == kWave / seg) {
+            WaveSpec x;
+            x.first = (int64_t)wo.size();
             x.seg = seg;
             wv.push_back(x);
         }
         WaveSpec &w = wv.back();
         w.count++;
-        const PairSpec &x = sp[worder[k]];
+        wo.push_back(k);
+        const PairSpec &x = sp[k];
         const int64_t passes = ((x.m + kTP - 1) / kTP + seg - 1) / seg;
         w.cost = std::max(w.cost, passes * (x.n + seg - 1));
     }
@@ -943,43 +1062,106 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
         for (size_t v = 0; v < wv.size(); v++) sorted[v] = wv[wi[v]];
         wv.swap(sorted);
     }
+    // the pairs of a wave, and per pair its unit (packed kind) or -1
+    auto wave_pairs = [&](const WaveSpec &w, std::vector<std::pair<int64_t, int64_t>> &out) {
+        out.clear();
+        if (w.packed) {
+            for (int64_t u = w.u_first; u < w.u_first + w.u_count; u++) {
+                out.push_back({us[u].a, u});
+                if (us[u].b >= 0) out.push_back({us[u].b, u});
+            }
+        } else {
+            for (int64_t q = 0; q < w.count; q++) out.push_back({wo[w.first + q], -1});
+        }
+    };
+    // a pair's region holds its int32 direction codes or its checkpoints
+    auto region_words = [&](int64_t k, int64_t u) -> int64_t {
+        if (!traceback) return 0;
+        const PairSpec &x = sp[k];
+        const int seg = segk[k];
+        const int64_t strips = (x.m + kTP - 1) / kTP;
+        const int64_t passes = (strips + seg - 1) / seg;
+        const int64_t nblk = (x.n + seg - 1 + kWfBlock - 1) / kWfBlock;
+        int64_t words = passes * nblk * kWfBlock * seg * 2;
+        if (u >= 0) words = std::max(words, pk16_words(strips, us[u].nst));
+        return (int64_t)align_up((size_t)words, 4);
+    };
     P.waves.reserve(P.waves.size() + wv.size());
     P.wf.reserve(P.wf.size() + worder.size());
     P.slots.reserve(P.slots.size() + worder.size());
+    P.pk = use_pk;
     int64_t wchunk = 0;
+    std::vector<std::pair<int64_t, int64_t>> wp;
     for (size_t v = 0; v < wv.size(); v++) {
+        const WaveSpec &w = wv[v];
+        wave_pairs(w, wp);
         int64_t wave_words = 0;
-        for (int64_t q = 0; q < wv[v].count; q++) {
-            const PairSpec &x = sp[worder[wv[v].first + q]];
-            const int seg = wv[v].seg;
-            const int64_t passes = ((x.m + kTP - 1) / kTP + seg - 1) / seg;
-            const int64_t nblk = (x.n + seg - 1 + kWfBlock - 1) / kWfBlock;
-            wave_words += traceback ? passes * nblk * kWfBlock * seg * 2 : 0;
-        }
+        for (const auto &x : wp) wave_words += region_words(x.first, x.second);
         if (plain) {
-            if (v == 0) { P.wf_chunk_first.push_back(0); P.wf_chunk_pair.push_back(0); }
+            if (v == 0) { P.wf_chunk_first.push_back(0); P.wf_chunk_pair.push_back(0); P.pk_chunk_first.push_back(0); }
             wchunk = 0;
         } else if (v == 0 || (wchunk > 0 && (wchunk + wave_words) * 4 > tb_cap)) {
-            P.wf_chunk_first.push_back((int64_t)v);
+            P.wf_chunk_first.push_back((int64_t)P.waves.size());
             P.wf_chunk_pair.push_back((int64_t)P.wf.size());
+            P.pk_chunk_first.push_back((int64_t)P.pkwaves.size());
             wchunk = 0;
         }
-        WfWave V;
-        V.p0 = (int32_t)P.wf.size();
-        V.np = (int32_t)wv[v].count;
-        V.seg = wv[v].seg;
-        V.pad = 0;
-        P.waves.push_back(V);
-        for (int64_t q = 0; q < wv[v].count; q++) {
-            const PairSpec &x = sp[worder[wv[v].first + q]];
-            const int seg = wv[v].seg;
-            const int64_t passes = ((x.m + kTP - 1) / kTP + seg - 1) / seg;
-            const int64_t nblk = (x.n + seg - 1 + kWfBlock - 1) / kWfBlock;
-            const int64_t words = traceback ? passes * nblk * kWfBlock * seg * 2 : 0;
+        const int64_t p0 = (int64_t)P.wf.size();
+        // int32 waves over these pairs: one segment width each, 64 / seg pairs
+        {
+            std::vector<std::pair<int, int64_t>> bys;  // (seg, wave-relative pair)
+            for (size_t q = 0; q < wp.size(); q++) bys.push_back({segk[wp[q].first], (int64_t)q});
+            std::stable_sort(bys.begin(), bys.end(), [](const std::pair<int, int64_t> &x,
+                                                         const std::pair<int, int64_t> &y) { return x.first > y.first; });
+            // pairs are stored in this order so that an int32 wave's pairs are contiguous
+            std::vector<std::pair<int64_t, int64_t>> reordered;
+            for (const auto &x : bys) reordered.push_back(wp[x.second]);
+            wp.swap(reordered);
+            for (size_t q0 = 0; q0 < wp.size();) {
+                const int seg = segk[wp[q0].first];
+                size_t q1 = q0;
+                while (q1 < wp.size() && segk[wp[q1].first] == seg && (int64_t)(q1 - q0) < kWave / seg) q1++;
+                WfWave V;
+                V.p0 = (int32_t)(p0 + (int64_t)q0);
+                V.np = (int32_t)(q1 - q0);
+                V.seg = seg;
+                V.pad = 0;
+                P.waves.push_back(V);
+                q0 = q1;
+            }
+        }
+        if (w.packed) {
+            Pk16Wave K;
+            K.u0 = (int32_t)P.units.size();
+            K.nu = (int32_t)w.u_count;
+            P.pkwaves.push_back(K);
+            std::vector<int8_t> map(kWave, -1);
+            int lane = 0;
+            for (int64_t u = w.u_first; u < w.u_first + w.u_count; u++) {
+                Pk16Unit U;
+                U.a = U.b = -1;
+                for (size_t q = 0; q < wp.size(); q++) {
+                    if (wp[q].second != u) continue;
+                    if (wp[q].first == us[u].a) U.a = (int32_t)(p0 + (int64_t)q);
+                    else U.b = (int32_t)(p0 + (int64_t)q);
+                }
+                U.nst = (int32_t)us[u].nst;
+                U.lane0 = (int16_t)lane;
+                U.w = (int16_t)us[u].w;
+                for (int x = 0; x < us[u].w; x++) map[lane + x] = (int8_t)(u - w.u_first);
+                lane += us[u].w;
+                P.units.push_back(U);
+            }
+            P.lanemap.insert(P.lanemap.end(), map.begin(), map.end());
+        }
+        for (const auto &pq : wp) {
+            const int64_t k = pq.first, u = pq.second;
+            const PairSpec &x = sp[k];
+            const int64_t words = region_words(k, u);
             WfPair W;
             memset(&W, 0, sizeof(W));
             W.slot = (int32_t)P.slots.size();
-            W.seg = seg;
+            W.seg = segk[k];
             W.tb = wchunk / 2;  // plain: every pair starts at 0 (one at a time)
             wchunk += words;
             if (plain) {
@@ -992,6 +1174,16 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
             P.wf_tb_max = std::max(P.wf_tb_max, wchunk);
             P.wf_tb_total += words;
             P.wf.push_back(W);
+            Pk16Pair K;
+            memset(&K, 0, sizeof(K));
+            if (u >= 0) {
+                K.nst = (int32_t)us[u].nst;
+                K.bias = pbias[k];
+                K.hlim = phlim[k];
+                K.w = us[u].w;
+            }
+            P.pkpairs.push_back(K);
+            P.pkflags.push_back(u >= 0 ? 0 : 1);
             PairInfo I;
             memset(&I, 0, sizeof(I));
             I.q_off = x.q_off;
@@ -1007,9 +1199,16 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     }
     P.wf_chunk_first.push_back((int64_t)P.waves.size());
     P.wf_chunk_pair.push_back((int64_t)P.wf.size());
-    // with several chunks, fills and walks alternate between two code buffers
-    // so that a chunk's walk overlaps the next chunk's fill
-    if (traceback && !plain && P.wf_chunk_first.size() > 2) P.wf_buffers = 2;
+    P.pk_chunk_first.push_back((int64_t)P.pkwaves.size());
+    if (P.units.empty()) {
+        P.pk = false;
+        P.pkpairs.clear();
+        P.pkflags.clear();
+    }
+    // with several chunks, fills and walks of the int32 kind alternate
+    // between two code buffers so that a chunk's walk overlaps the next
+    // chunk's fill (the packed kind's walk is short: its chunks run in order)
+    if (traceback && !plain && !P.pk && P.wf_chunk_first.size() > 2) P.wf_buffers = 2;
     layout_pair_plan(P, caps_of(P), A);
 }
 
@@ -1091,8 +1290,21 @@ int make_pair_plan(const dsa_args *a, const dsa_out *out, PairPlan &P) {
     }
     const bool tb = (a->flags & DSA_TRACEBACK) != 0;
     P.pssm_bytes = pssm_bytes(a);
+    // the packed int16 fill scores from an int16 copy of the matrix: not with
+    // a position-specific profile, alphabets above 32 letters or DSA_FORCE_INT32
+    PkSpec pk;
+    pk.on = !a->pssm && a->alphabet_size <= kMaxAlphabet16 && !(a->flags & DSA_FORCE_INT32) && !pk16_disabled();
+    if (pk.on) {
+        const int A = a->alphabet_size;
+        for (int k = 0; k < A * A; k++) {
+            pk.smin = std::max(pk.smin, -(int)a->subst[k]);
+            pk.smax = std::max(pk.smax, (int)a->subst[k]);
+        }
+        pk.o = a->gap_open;
+        pk.e = a->gap_extend;
+    }
     build_pair_plan(sp, n, a->mode, ends, tb, (tb && out) ? out->cigar_capacity : 0, a->alphabet_size,
-                    tb_budget_bytes(), P, (a->flags & DSA_PLAIN) != 0, pair_route(tuning_for(pair_key(a))));
+                    tb_budget_bytes(), P, (a->flags & DSA_PLAIN) != 0, pair_route(tuning_for(pair_key(a))), pk);
     return DSA_OK;
 }
 
@@ -1468,7 +1680,14 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
             memcpy(h + P.off_slots, P.slots.data(), P.slots.size() * sizeof(PairInfo));
             memcpy(h + P.off_groups, P.groups.data(), P.groups.size() * sizeof(PairGroup));
             memcpy(h + P.off_wf, P.wf.data(), P.wf.size() * sizeof(WfPair));
-        memcpy(h + P.off_waves, P.waves.data(), P.waves.size() * sizeof(WfWave));
+            memcpy(h + P.off_waves, P.waves.data(), P.waves.size() * sizeof(WfWave));
+            if (P.pk) {
+                memcpy(h + P.off_units, P.units.data(), P.units.size() * sizeof(Pk16Unit));
+                memcpy(h + P.off_pkwaves, P.pkwaves.data(), P.pkwaves.size() * sizeof(Pk16Wave));
+                memcpy(h + P.off_pkpairs, P.pkpairs.data(), P.pkpairs.size() * sizeof(Pk16Pair));
+                memcpy(h + P.off_flags, P.pkflags.data(), P.pkflags.size() * sizeof(int32_t));
+                memcpy(h + P.off_lanemap, P.lanemap.data(), P.lanemap.size());
+            }
             copy_subst(a, h + P.off_subst);
             if (P.pssm_bytes) fill_pssm(a, h + P.off_pssm);
         });
@@ -1535,10 +1754,37 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
         }
         return DSA_OK;
     };
+    // the packed int16 fill: its waves per chunk, per pair its bias and flag
+    Pk16Args X;
+    memset(&X, 0, sizeof(X));
+    X.units = (const Pk16Unit *)(ws + P.off_units);
+    X.waves = (const Pk16Wave *)(ws + P.off_pkwaves);
+    X.pk = (const Pk16Pair *)(ws + P.off_pkpairs);
+    X.flag = (int32_t *)(ws + P.off_flags);
+    X.lanemap = (const int8_t *)(ws + P.off_lanemap);
     auto wf_launch = [&](size_t c, hipStream_t s) -> int {
         const PairArgs k = wf_args(c, 0);
-        HIPCHK(launch_pairwf(k, P.mode, s));
-        if (P.traceback) HIPCHK(launch_walk_wf(walk_args(k, c), P.mode, s));
+        if (!P.pk) {
+            HIPCHK(launch_pairwf(k, P.mode, s));
+            if (P.traceback) HIPCHK(launch_walk_wf(walk_args(k, c), P.mode, s));
+            return DSA_OK;
+        }
+        // packed fill of the chunk's units, then the int32 fill of the pairs
+        // it flags (and of those it cannot hold), then the two walks
+        Pk16Args x = X;
+        x.waves = X.waves + P.pk_chunk_first[c];
+        x.lanemap = X.lanemap + P.pk_chunk_first[c] * kWave;
+        x.n_waves = (int32_t)(P.pk_chunk_first[c + 1] - P.pk_chunk_first[c]);
+        HIPCHK(launch_pairpk(k, x, P.mode, s));
+        HIPCHK(launch_pairwf_only(k, P.mode, X.flag, s));
+        if (P.traceback) {
+            const PairArgs kw = walk_args(k, c);
+            Pk16Args xw = X;
+            xw.pk = X.pk + P.wf_chunk_pair[c];
+            xw.flag = X.flag + P.wf_chunk_pair[c];
+            HIPCHK(launch_walk_ck(kw, xw, P.mode, s));
+            HIPCHK(launch_walk_wf_only(kw, P.mode, xw.flag, s));
+        }
         return DSA_OK;
     };
     // chunks of wavefront pairs with two code buffers: fills on `sf`, walks on
