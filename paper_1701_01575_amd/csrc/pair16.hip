@@ -92,18 +92,37 @@ __device__ __forceinline__ int left_or_pad(int mode, int ends, int o, int e, int
 
 }  // namespace
 
-size_t pk16_lds_bytes(int A) { return (size_t)((A + 1) * (A + 1) + (A + 1)) * 2 + 16; }
+// The fill's score table in LDS: the matrix as int8 with row and column A
+// scoring 0, rows of kPkRow(A) entries (a multiple of 4), in kPkCopies
+// copies interleaved by bank: entry e of copy c is byte e % 4 of dword
+// (e / 4) * kPkCopies + c.  Lane L reads copy L % kPkCopies, so the 32 lanes
+// the LDS serves at once read 32 different banks whatever their entries
+// (random lookups into one copy collide several ways per read).  Then the
+// row maxima of the matrix (int16).
+constexpr int kPkCopies = 32;
+__host__ __device__ inline int kPkRow(int A) { return (A + 1 + 3) & ~3; }
+size_t pk16_lds_bytes(int A) {
+    return (size_t)kPkCopies * (A + 1) * kPkRow(A) + (size_t)(A + 1) * 2 + 16;
+}
 
 template <int MODE, bool TB>
 __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_waves_per_eu(3))) k_pairpk(PairArgs P, Pk16Args X) {
     constexpr int T = kTP;
-    extern __shared__ uint16_t sm16[];
-    const int A = P.A, SS = P.A + 1;
-    uint16_t *rmx = sm16 + SS * SS;
-    for (int k = threadIdx.x; k < SS * SS; k += blockDim.x) {
-        const int r = k / SS, c = k - r * SS;
-        sm16[k] = (uint16_t)(int16_t)((r < A && c < A) ? (int)P.subst[r * A + c] : 0);
+    extern __shared__ uint32_t smw[];
+    const int A = P.A, SS = P.A + 1, RW = kPkRow(A);
+    const int nd = SS * RW / 4;  // dwords of one copy
+    for (int k = threadIdx.x; k < nd * kPkCopies; k += blockDim.x) {
+        const int d = k / kPkCopies;
+        uint32_t v = 0;
+#pragma unroll
+        for (int x = 0; x < 4; x++) {
+            const int en = 4 * d + x, r = en / RW, c = en - r * RW;
+            const int sc = (r < A && c < A) ? (int)P.subst[r * A + c] : 0;
+            v |= (uint32_t)(uint8_t)(int8_t)sc << (8 * x);
+        }
+        smw[k] = v;
     }
+    uint16_t *rmx = reinterpret_cast<uint16_t *>(smw + nd * kPkCopies);
     for (int q = threadIdx.x; q < SS; q += blockDim.x) {
         int mx = 0;
         if (q < A)
@@ -136,10 +155,12 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
     const uint8_t *tA = P.t_codes + IA.t_off, *tB = P.t_codes + IB.t_off;
     uint32_t *ckA = P.tb + 2 * WA.tb, *ckB = P.tb + 2 * WB.tb;
     uint32_t *bdA = reinterpret_cast<uint32_t *>(P.bnd + WA.bnd), *bdB = reinterpret_cast<uint32_t *>(P.bnd + WB.bnd);
-    const int RS = SS * 2;  // bytes per LDS matrix row
+    // byte offsets into the score table: row q of this lane's copy at
+    // q * RB + LB, column b at (b / 4) * 4 * kPkCopies + b % 4
+    const int RB = RW / 4 * 4 * kPkCopies, LB = 4 * (int)(threadIdx.x % kPkCopies);
     const uint32_t bias2 = pack2(KA.bias, KB.bias);
     const uint32_t o2 = dup(o), e2 = dup(e);
-    const char *smb = reinterpret_cast<const char *>(sm16);
+    const char *smb = reinterpret_cast<const char *>(smw);
 
     // global and semi-global: H never exceeds the query's sum of positive row
     // maxima; a pair whose sum exceeds its limit goes to int32 at once
@@ -171,7 +192,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
             const int i = i0 + r;
             const int cA = i < mA ? min((int)qA[i], A - 1) : A;
             const int cB = i < mB ? min((int)qB[i], A - 1) : A;
-            rowAB[r] = pack2(cA * RS, cB * RS);
+            rowAB[r] = pack2(cA * RB + LB, cB * RB + LB);
             H[r] = addu(pack2(left_or_pad(MODE, ends, o, e, i + 1, mA), left_or_pad(MODE, ends, o, e, i + 1, mB)),
                         bias2);
             E[r] = (MODE == LOCAL) ? bias2 : subw(H[r], o2);
@@ -238,8 +259,10 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
                     }
                 }
                 // column codes clamped to the alphabet, A (scores 0) past a target
-                const int bA2 = 2 * (ca0 > 255u ? A : min((int)ca0, A - 1));
-                const int bB2 = 2 * (cb0 > 255u ? A : min((int)cb0, A - 1));
+                const int bA = ca0 > 255u ? A : min((int)ca0, A - 1);
+                const int bB = cb0 > 255u ? A : min((int)cb0, A - 1);
+                const int bA2 = (bA >> 2) * (4 * kPkCopies) + (bA & 3);
+                const int bB2 = (bB >> 2) * (4 * kPkCopies) + (bB & 3);
                 uint32_t Hd = Hd_top;
                 Hd_top = rH;
                 uint32_t F = rF;
@@ -251,8 +274,8 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
 #pragma unroll
                     for (int x = 0; x < 4; x++) {
                         const uint32_t ra = rowAB[4 * g + x];
-                        na[x] = *reinterpret_cast<const uint16_t *>(smb + (ra & 0xffffu) + bA2);
-                        nb[x] = *reinterpret_cast<const uint16_t *>(smb + (ra >> 16) + bB2);
+                        na[x] = (uint32_t)(int)*reinterpret_cast<const int8_t *>(smb + (ra & 0xffffu) + bA2);
+                        nb[x] = (uint32_t)(int)*reinterpret_cast<const int8_t *>(smb + (ra >> 16) + bB2);
                     }
                 };
                 fetch(0);
@@ -260,7 +283,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
                 for (int r = 0; r < T; r++) {
                     if ((r & 3) == 0) {
 #pragma unroll
-                        for (int x = 0; x < 4; x++) cur[x] = na[x] | (nb[x] << 16);
+                        for (int x = 0; x < 4; x++) cur[x] = lo_lo(na[x], nb[x]);
                         if (r + 4 < T) fetch((r >> 2) + 1);
                         __builtin_amdgcn_sched_barrier(0);
                     }

@@ -967,18 +967,23 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     // (they run only the pairs the packed fill flags).
     std::vector<int> segk(sp.size(), 0);
     for (int64_t k : worder) segk[k] = wf_seg(sp[k].m);
+    const bool use_pk = pk.on && !plain;
+    std::vector<int32_t> pbias(sp.size(), 0), phlim(sp.size(), 0);
+    std::vector<char> pkok(sp.size(), 0);
+    std::vector<int64_t> el;  // the pairs of the packed kind
+    if (use_pk) {
+        std::vector<int64_t> rest;
+        for (int64_t k : worder) {
+            pk16_bias(pk, mode, sp[k].m, sp[k].n, &pbias[k], &phlim[k]);
+            pkok[k] = phlim[k] >= kPk16MinLimit;
+            (pkok[k] ? el : rest).push_back(k);
+        }
+        worder.swap(rest);
+    }
     if (!plain)  // segment width, then cells (m, n < 2^16: cells < 2^32)
         sort_desc_stable(worder, [&](int64_t k) {
             return ((uint64_t)segk[k] << 33) | (uint64_t)(sp[k].m * sp[k].n);
         });
-    const bool use_pk = pk.on && !plain;
-    std::vector<int32_t> pbias(sp.size(), 0), phlim(sp.size(), 0);
-    std::vector<char> pkok(sp.size(), 0);
-    if (use_pk)
-        for (int64_t k : worder) {
-            pk16_bias(pk, mode, sp[k].m, sp[k].n, &pbias[k], &phlim[k]);
-            pkok[k] = phlim[k] >= kPk16MinLimit;
-        }
     auto strips_of = [&](int64_t k) { return (sp[k].m + kTP - 1) / kTP; };
     // A wave to plan: packed (units [u_first, +u_count) of `units`) or int32
     // (pairs [first, +count) of `wo`, one segment width).
@@ -1000,9 +1005,6 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     if (use_pk) {
         // units of two pairs with equal or neighbouring strip counts, as many
         // lanes as strips (passes of equal width beyond 64 strips)
-        std::vector<int64_t> el;
-        for (int64_t k : worder)
-            if (pkok[k]) el.push_back(k);
         sort_desc_stable(el, [&](int64_t k) { return ((uint64_t)strips_of(k) << 17) | (uint64_t)sp[k].n; });
         for (size_t q = 0; q < el.size(); q += 2) {
             UnitSpec u;
@@ -1010,6 +1012,9 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
             u.b = q + 1 < el.size() ? el[q + 1] : -1;
             const int64_t S = std::max(strips_of(u.a), u.b >= 0 ? strips_of(u.b) : 0);
             const int64_t nmax = std::max(sp[u.a].n, u.b >= 0 ? sp[u.b].n : 0);
+            // the fewest passes that fit 64 lanes (more passes of narrower
+            // segments pack waves fuller but measured slower: the fill is
+            // bound by each wave's issue, and fewer, longer waves hide less)
             const int64_t passes = std::max<int64_t>((S + kWave - 1) / kWave, 1);
             u.w = (int)std::max<int64_t>((S + passes - 1) / passes, 1);
             u.nst = (int64_t)align_up((size_t)(nmax + u.w - 1), kCkCols);
@@ -1022,7 +1027,9 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
         std::vector<UnitSpec> sorted(us.size());
         for (size_t v = 0; v < us.size(); v++) sorted[v] = us[ui[v]];
         us.swap(sorted);
-        // waves of consecutive units while their lanes fit in 64
+        // waves of consecutive units while their lanes fit in 64 (filling the
+        // gaps best-fit with later, shorter units measured slower: fewer
+        // waves hide less of each wave's latency)
         for (size_t v = 0; v < us.size();) {
             WaveSpec x;
             x.packed = true;
@@ -1039,7 +1046,6 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     }
     for (size_t q = 0; q < worder.size(); q++) {  // the int32 kind
         const int64_t k = worder[q];
-        if (use_pk && pkok[k]) continue;
         const int seg = segk[k];
         if (plain || wv.empty() || wv.back().packed || wv.back().seg != seg || wv.back().count == kWave / seg) {
             WaveSpec x;
@@ -1062,16 +1068,21 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
         for (size_t v = 0; v < wv.size(); v++) sorted[v] = wv[wi[v]];
         wv.swap(sorted);
     }
-    // the pairs of a wave, and per pair its unit (packed kind) or -1
-    auto wave_pairs = [&](const WaveSpec &w, std::vector<std::pair<int64_t, int64_t>> &out) {
+    // the pairs of a wave (k, its unit or -1, 0 for a unit's pair a, 1 for b),
+    // segment widths of the int32 kernel from the widest, so that each of
+    // its waves takes consecutive pairs
+    struct WP { int64_t k, u; int role; };
+    auto wave_pairs = [&](const WaveSpec &w, std::vector<WP> &out) {
         out.clear();
-        if (w.packed) {
-            for (int64_t u = w.u_first; u < w.u_first + w.u_count; u++) {
-                out.push_back({us[u].a, u});
-                if (us[u].b >= 0) out.push_back({us[u].b, u});
+        for (int seg = kWave; seg >= 4; seg >>= 1) {
+            if (w.packed) {
+                for (int64_t u = w.u_first; u < w.u_first + w.u_count; u++) {
+                    if (segk[us[u].a] == seg) out.push_back({us[u].a, u, 0});
+                    if (us[u].b >= 0 && segk[us[u].b] == seg) out.push_back({us[u].b, u, 1});
+                }
+            } else if (w.seg == seg) {
+                for (int64_t q = 0; q < w.count; q++) out.push_back({wo[w.first + q], -1, 0});
             }
-        } else {
-            for (int64_t q = 0; q < w.count; q++) out.push_back({wo[w.first + q], -1});
         }
     };
     // a pair's region holds its int32 direction codes or its checkpoints
@@ -1086,17 +1097,21 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
         if (u >= 0) words = std::max(words, pk16_words(strips, us[u].nst));
         return (int64_t)align_up((size_t)words, 4);
     };
-    P.waves.reserve(P.waves.size() + wv.size());
-    P.wf.reserve(P.wf.size() + worder.size());
-    P.slots.reserve(P.slots.size() + worder.size());
+    const size_t n_wf = worder.size() + el.size();
+    P.waves.reserve(P.waves.size() + 2 * wv.size());
+    P.wf.reserve(P.wf.size() + n_wf);
+    P.slots.reserve(P.slots.size() + n_wf);
+    P.pkpairs.reserve(n_wf);
+    P.pkflags.reserve(n_wf);
     P.pk = use_pk;
     int64_t wchunk = 0;
-    std::vector<std::pair<int64_t, int64_t>> wp;
+    std::vector<WP> wp;
+    wp.reserve(2 * kWave);
     for (size_t v = 0; v < wv.size(); v++) {
         const WaveSpec &w = wv[v];
         wave_pairs(w, wp);
         int64_t wave_words = 0;
-        for (const auto &x : wp) wave_words += region_words(x.first, x.second);
+        for (const auto &x : wp) wave_words += region_words(x.k, x.u);
         if (plain) {
             if (v == 0) { P.wf_chunk_first.push_back(0); P.wf_chunk_pair.push_back(0); P.pk_chunk_first.push_back(0); }
             wchunk = 0;
@@ -1109,18 +1124,10 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
         const int64_t p0 = (int64_t)P.wf.size();
         // int32 waves over these pairs: one segment width each, 64 / seg pairs
         {
-            std::vector<std::pair<int, int64_t>> bys;  // (seg, wave-relative pair)
-            for (size_t q = 0; q < wp.size(); q++) bys.push_back({segk[wp[q].first], (int64_t)q});
-            std::stable_sort(bys.begin(), bys.end(), [](const std::pair<int, int64_t> &x,
-                                                         const std::pair<int, int64_t> &y) { return x.first > y.first; });
-            // pairs are stored in this order so that an int32 wave's pairs are contiguous
-            std::vector<std::pair<int64_t, int64_t>> reordered;
-            for (const auto &x : bys) reordered.push_back(wp[x.second]);
-            wp.swap(reordered);
             for (size_t q0 = 0; q0 < wp.size();) {
-                const int seg = segk[wp[q0].first];
+                const int seg = segk[wp[q0].k];
                 size_t q1 = q0;
-                while (q1 < wp.size() && segk[wp[q1].first] == seg && (int64_t)(q1 - q0) < kWave / seg) q1++;
+                while (q1 < wp.size() && segk[wp[q1].k] == seg && (int64_t)(q1 - q0) < kWave / seg) q1++;
                 WfWave V;
                 V.p0 = (int32_t)(p0 + (int64_t)q0);
                 V.np = (int32_t)(q1 - q0);
@@ -1135,27 +1142,27 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
             K.u0 = (int32_t)P.units.size();
             K.nu = (int32_t)w.u_count;
             P.pkwaves.push_back(K);
-            std::vector<int8_t> map(kWave, -1);
+            const size_t ub = P.units.size();
+            const size_t mb = P.lanemap.size();
+            P.lanemap.resize(mb + kWave, (int8_t)-1);
             int lane = 0;
             for (int64_t u = w.u_first; u < w.u_first + w.u_count; u++) {
                 Pk16Unit U;
                 U.a = U.b = -1;
-                for (size_t q = 0; q < wp.size(); q++) {
-                    if (wp[q].second != u) continue;
-                    if (wp[q].first == us[u].a) U.a = (int32_t)(p0 + (int64_t)q);
-                    else U.b = (int32_t)(p0 + (int64_t)q);
-                }
                 U.nst = (int32_t)us[u].nst;
                 U.lane0 = (int16_t)lane;
                 U.w = (int16_t)us[u].w;
-                for (int x = 0; x < us[u].w; x++) map[lane + x] = (int8_t)(u - w.u_first);
+                for (int x = 0; x < us[u].w; x++) P.lanemap[mb + lane + x] = (int8_t)(u - w.u_first);
                 lane += us[u].w;
                 P.units.push_back(U);
             }
-            P.lanemap.insert(P.lanemap.end(), map.begin(), map.end());
+            for (size_t q = 0; q < wp.size(); q++) {
+                Pk16Unit &U = P.units[ub + (size_t)(wp[q].u - w.u_first)];
+                (wp[q].role ? U.b : U.a) = (int32_t)(p0 + (int64_t)q);
+            }
         }
         for (const auto &pq : wp) {
-            const int64_t k = pq.first, u = pq.second;
+            const int64_t k = pq.k, u = pq.u;
             const PairSpec &x = sp[k];
             const int64_t words = region_words(k, u);
             WfPair W;
