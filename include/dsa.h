@@ -85,7 +85,7 @@ enum { DSA_QB = 1, DSA_QE = 2, DSA_TB = 4, DSA_TE = 8 };
 #define DSA_FORCE_INT32 4u  /* skip the packed int16 pass */
 
 /* per-result status bits */
-#define DSA_ST_INT32     1u  /* the result came from the int32 rerun */
+#define DSA_ST_INT32     1u  /* computed by an int32 kernel (a rerun, or a path that is int32 throughout) */
 #define DSA_ST_TRUNCATED 2u  /* the CIGAR did not fit in its slot */
 
 typedef struct dsa_db dsa_db;
@@ -216,8 +216,19 @@ int dsa_cigar_capacity(const dsa_args *args, int64_t *entries);
  *                score at either int16 bound is rerun.
  * These searches run the int32 kernel throughout: DSA_FORCE_INT32; a free
  * query end (semi-global with DSA_QE); a local search with gap_open above
- * 1024 or gap_extend above 256.  Pairwise alignment (and the traceback of
- * top-K hits) runs exact int32 kernels throughout.
+ * 1024 or gap_extend above 256.
+ * Pairwise alignment: large pairs (by default 48 query rows and 32,768 cells
+ * or more) run a packed int16 fill, two pairs per wavefront segment, each
+ * pair's values offset by a bias that covers the lowest value its recurrence
+ * can reach (gap_open + gap_extend + |min S|, plus the two boundary gaps in
+ * global and semi-global mode).  A pair whose values could pass the int16
+ * range is redone by the exact int32 kernels and carries DSA_ST_INT32: in
+ * global and semi-global mode when its query's sum of positive row maxima
+ * exceeds the limit the bias leaves (31,743 - bias - max S, with bias =
+ * 1,024 + that depth), in local mode when its best score does.  These run int32 throughout: a
+ * position-specific profile, more than 32 letters, DSA_FORCE_INT32,
+ * DSA_PLAIN.  Smaller pairs, and the traceback of top-K hits, run exact
+ * int32 kernels.
  * Errors: DSA_E_INVAL, DSA_E_RANGE, DSA_E_WORKSPACE, DSA_E_NOTSUP,
  * DSA_E_DEVICE.
  */
