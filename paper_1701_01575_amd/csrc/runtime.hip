@@ -163,9 +163,8 @@ int timing_end(hipStream_t st, size_t slot) {
 // default priority).  One per calling thread and device, so concurrent
 // calls from different threads never share fork / join events.
 struct Aux {
-    hipStream_t s = nullptr, s2 = nullptr;
+    hipStream_t s = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
-    std::vector<hipEvent_t> ev;  // ordering events of pipelined chunks
 };
 thread_local Aux t_aux[64];
 
@@ -173,7 +172,6 @@ int aux_get(int dev, Aux **out) {
     Aux &A = t_aux[dev & 63];
     if (!A.s) {
         HIPCHK(hipStreamCreateWithFlags(&A.s, hipStreamNonBlocking));
-        HIPCHK(hipStreamCreateWithFlags(&A.s2, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&A.fork, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&A.join, hipEventDisableTiming));
     }
@@ -697,7 +695,6 @@ struct PairPlan {
     std::vector<int64_t> wf_chunk_first;  // first wave of each chunk (+ end)
     std::vector<int64_t> wf_chunk_pair;   // first pair of each chunk (+ end)
     int64_t wf_tb_max = 0, wf_tb_total = 0, wf_bnd_total = 0;  // uint32 / uint32 / uint2
-    int wf_buffers = 1;                 // code buffers of wf_tb_max words each
     // packed int16 fill of the wavefront pairs (pk): units of two pairs, their
     // waves per chunk, per pair its bias and limit, and per pair a flag (host
     // value 1 for pairs it cannot hold; the fill sets the rest)
@@ -725,7 +722,7 @@ PairCaps caps_of(const PairPlan &P) {
     c.tpk = P.tpk_total;
     c.tb = P.tb_max;
     c.bndw = P.wf_bnd_total;
-    c.tbw = P.wf_tb_max * P.wf_buffers;
+    c.tbw = P.wf_tb_max;
     c.units = (int64_t)P.units.size();
     c.pkwaves = (int64_t)P.pkwaves.size();
     return c;
@@ -1212,10 +1209,6 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
         P.pkpairs.clear();
         P.pkflags.clear();
     }
-    // with several chunks, fills and walks of the int32 kind alternate
-    // between two code buffers so that a chunk's walk overlaps the next
-    // chunk's fill (the packed kind's walk is short: its chunks run in order)
-    if (traceback && !plain && !P.pk && P.wf_chunk_first.size() > 2) P.wf_buffers = 2;
     layout_pair_plan(P, caps_of(P), A);
 }
 
@@ -1597,7 +1590,7 @@ int make_search_plan(const dsa_args *a, Plan &P) {
         c.waves = (int64_t)B2.wf.size();  // at least one pair per wave
         c.tb = std::max(B1.tb_max, std::min(tb_budget_bytes() / 4, B1.tb_total));
         c.bndw = B2.wf_bnd_total;
-        c.tbw = 2 * std::max(B2.wf_tb_max, std::min(tb_budget_bytes() / 4, B2.wf_tb_total));
+        c.tbw = std::max(B2.wf_tb_max, std::min(tb_budget_bytes() / 4, B2.wf_tb_total));
         P.pair_caps = c;
         PairPlan L;
         layout_pair_plan(L, c, A);
@@ -1734,12 +1727,11 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
     KW.tb = (uint32_t *)(ws + P.off_tbw);
     KW.bnd = (uint2 *)(ws + P.off_bndw);
     // chunk c: waves [wf_chunk_first[c], +1) fill, pairs [wf_chunk_pair[c], +1) walk
-    auto wf_args = [&](size_t c, int buffer) {
+    auto wf_args = [&](size_t c) {
         PairArgs k = KW;
         k.waves = dv + P.wf_chunk_first[c];
         k.n_waves = (int32_t)(P.wf_chunk_first[c + 1] - P.wf_chunk_first[c]);
         k.wf = dw;  // waves index pairs absolutely
-        k.tb = KW.tb + buffer * P.wf_tb_max;
         return k;
     };
     auto walk_args = [&](PairArgs k, size_t c) {
@@ -1770,7 +1762,7 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
     X.flag = (int32_t *)(ws + P.off_flags);
     X.lanemap = (const int8_t *)(ws + P.off_lanemap);
     auto wf_launch = [&](size_t c, hipStream_t s) -> int {
-        const PairArgs k = wf_args(c, 0);
+        const PairArgs k = wf_args(c);
         if (!P.pk) {
             HIPCHK(launch_pairwf(k, P.mode, s));
             if (P.traceback) HIPCHK(launch_walk_wf(walk_args(k, c), P.mode, s));
@@ -1792,30 +1784,6 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
             HIPCHK(launch_walk_ck(kw, xw, P.mode, s));
             HIPCHK(launch_walk_wf_only(kw, P.mode, xw.flag, s));
         }
-        return DSA_OK;
-    };
-    // chunks of wavefront pairs with two code buffers: fills on `sf`, walks on
-    // `sw`; a fill waits for the walk that last used its buffer
-    auto wf_pipelined = [&](Aux *ax, hipStream_t sf) -> int {
-        hipStream_t sw = ax->s2;
-        const size_t nch = P.wf_chunk_first.size() - 1;
-        if (ax->ev.size() < 2 * nch + 1) {
-            const size_t old = ax->ev.size();
-            ax->ev.resize(2 * nch + 1);
-            for (size_t k = old; k < ax->ev.size(); k++)
-                HIPCHK(hipEventCreateWithFlags(&ax->ev[k], hipEventDisableTiming));
-        }
-        for (size_t c = 0; c < nch; c++) {
-            const PairArgs k = wf_args(c, (int)(c & 1));
-            if (c >= 2) HIPCHK(hipStreamWaitEvent(sf, ax->ev[2 * (c - 2) + 1], 0));
-            HIPCHK(launch_pairwf(k, P.mode, sf));
-            HIPCHK(hipEventRecord(ax->ev[2 * c], sf));
-            HIPCHK(hipStreamWaitEvent(sw, ax->ev[2 * c], 0));
-            HIPCHK(launch_walk_wf(walk_args(k, c), P.mode, sw));
-            HIPCHK(hipEventRecord(ax->ev[2 * c + 1], sw));
-        }
-        HIPCHK(hipEventRecord(ax->ev[2 * nch], sw));
-        HIPCHK(hipStreamWaitEvent(sf, ax->ev[2 * nch], 0));
         return DSA_OK;
     };
     auto lane_launch = [&](int64_t g0, int64_t g1, hipStream_t s) -> int {
@@ -1864,20 +1832,9 @@ static int run_pairs(const dsa_args *a, const dsa_out *out, PairPlan &P, uint8_t
     if (!P.wf.empty()) {
         size_t slot;
         if ((rc = timing_begin(ws_st, TK_PAIR_WF, &slot))) return rc;
-        // pipelined chunks are not recorded into graphs: recording them (a
-        // second auxiliary stream joined through the first) crashed inside
-        // dsa_graph_create; a graph replays the chunks in order instead
-        if (P.wf_buffers == 2 && !t_capturing) {
-            if (!aux) {
-                int dev = 0;
-                HIPCHK(hipGetDevice(&dev));
-                if ((rc = aux_get(dev, &aux))) return rc;
-            }
-            if ((rc = wf_pipelined(aux, ws_st))) return rc;
-        } else {
-            for (size_t c = 0; c + 1 < P.wf_chunk_first.size(); c++)
-                if ((rc = wf_launch(c, ws_st))) return rc;
-        }
+        // chunk by chunk: fill, then walk (eager calls and graphs alike)
+        for (size_t c = 0; c + 1 < P.wf_chunk_first.size(); c++)
+            if ((rc = wf_launch(c, ws_st))) return rc;
         if ((rc = timing_end(ws_st, slot))) return rc;
     }
     if (!P.groups.empty()) {
