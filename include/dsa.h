@@ -348,7 +348,12 @@ int dsa_timing_reset(void);
  * iterations; 5 -> HBM copy of `size` bytes, *rate = bytes read + written
  * per second; 7 -> *rate = the number of wrong results of the packed
  * binary16 three-way maximum over every operand pattern the local-mode int16
- * search produces (must be 0; size is ignored but must be positive).
+ * search produces (must be 0; size is ignored but must be positive);
+ * 8, 9 -> *rate = local-mode cells per second of a bare 16-row column
+ * recurrence (scores from an LDS profile, no boundary or end-cell work),
+ * 8 in packed int16 (two targets per lane), 9 in 8-bit lanes of 32-bit
+ * words (four targets per lane), size = columns per lane; 10 -> *rate = the
+ * number of wrong results of the byte sign spread that 9 uses (must be 0).
  */
 int dsa_probe(int which, int64_t size, double *rate);
 

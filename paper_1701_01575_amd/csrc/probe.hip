@@ -10,6 +10,7 @@
 #include "dsa.h"
 #include "internal.h"
 #include "pk16.h"
+#include "swar8.h"
 
 namespace dsa {
 
@@ -67,6 +68,86 @@ __global__ void k_max3_order(unsigned long long *bad) {
     if (nbad) atomicAdd(bad, nbad);
 }
 
+// Cell-rate probes: the local recurrence of one 16-row strip column after
+// column, scores from a profile in LDS (a random profile row per column),
+// nothing else (no boundary rows, no end-cell bookkeeping).  k_cells16: two
+// targets per lane, packed int16, the search kernel's column (offset
+// binary16 three-way maxima in the column-shifted frame); k_cells8: four
+// targets per lane, 8-bit lanes in 32-bit ALU operations (swar8.h), the two
+// 8-bit pairs of a row's scores from two profile reads, as an int8 first
+// pass over the same database layout would fetch them.  Values are not kept
+// in range (the profile favours matches); only the instruction stream
+// matters here.
+__global__ void __launch_bounds__(256) k_cells16(uint32_t *out, int cols, uint32_t seed) {
+    __shared__ uint32_t prof[64 * 16];
+    for (int k = threadIdx.x; k < 64 * 16; k += blockDim.x) prof[k] = dup((int)((k * 2654435761u) >> 28) - 3);
+    __syncthreads();
+    uint32_t H[16], E[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        H[r] = dup(kBias16);
+        E[r] = dup(kBias16);
+    }
+    uint32_t B = dup(kBias16), code = seed * (threadIdx.x + 1u);
+    const uint32_t oe2 = dup(10), e2 = dup(1), phi = dup(kBias16);
+    for (int c = 0; c < cols; c++) {
+        code = code * 1664525u + 1013904223u;
+        const uint32_t *pr = prof + ((code >> 26) << 4);
+        uint32_t sc[16];
+#pragma unroll
+        for (int r = 0; r < 16; r++) sc[r] = pr[r];
+        uint32_t F = dup(kBias16);
+        B = column16_local_cs<16>(sc, H, E, dup(kBias16), F, oe2, e2, phi, B);
+    }
+    out[blockIdx.x * blockDim.x + threadIdx.x] = B ^ H[15] ^ E[15];
+}
+
+struct SpreadPerm {  // bit 7 of each byte over the byte: one v_perm_b32 (see swar8.h)
+    __device__ uint32_t operator()(uint32_t d) const { return __builtin_amdgcn_perm(d << 8, d, 0x090B080Au); }
+};
+
+__global__ void __launch_bounds__(256) k_cells8(uint32_t *out, int cols, uint32_t seed) {
+    __shared__ uint16_t prof[64 * 16];  // two targets' scores + p per entry
+    for (int k = threadIdx.x; k < 64 * 16; k += blockDim.x)
+        prof[k] = (uint16_t)(((k * 2654435761u) >> 28) | (((k * 40503u) >> 12) & 15u) << 8);
+    __syncthreads();
+    Swar8Gaps g;
+    g.o4 = 0x0a0a0a0au;
+    g.e4 = 0x01010101u;
+    g.z4 = 0x0b0b0b0bu;
+    g.np4 = 0u - 0x04040404u;
+    uint32_t H[16], E[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        H[r] = g.z4;
+        E[r] = g.z4 - g.o4 + g.e4;
+    }
+    uint32_t B = g.z4, ovf = 0, code = seed * (threadIdx.x + 1u);
+    for (int c = 0; c < cols; c++) {
+        code = code * 1664525u + 1013904223u;
+        const uint16_t *pa = prof + ((code >> 26) << 4), *pb = prof + (((code >> 20) & 63u) << 4);
+        uint32_t sc[16];
+#pragma unroll
+        for (int r = 0; r < 16; r++) sc[r] = (uint32_t)pa[r] | ((uint32_t)pb[r] << 16);
+        uint32_t F = g.z4 - g.o4 + g.e4;
+        B = column8_local(sc, H, E, g.z4, F, g, B, ovf, SpreadPerm());
+    }
+    out[blockIdx.x * blockDim.x + threadIdx.x] = B ^ H[15] ^ E[15] ^ ovf;
+}
+
+// SpreadPerm against its definition on 2^26 hashed words (every pattern of
+// the four sign bits with varied low bits).  Counts the failures.
+__global__ void k_spread_check(unsigned long long *bad) {
+    unsigned long long nbad = 0;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < (1u << 26); k += gridDim.x * blockDim.x) {
+        const uint32_t d = (k * 2654435761u) ^ (k << 7) ^ (k >> 11);
+        uint32_t want = 0;
+        for (int i = 0; i < 4; i++) want |= ((d >> (8 * i + 7)) & 1u) ? 0xffu << (8 * i) : 0u;
+        nbad += SpreadPerm()(d) != want;
+    }
+    if (nbad) atomicAdd(bad, nbad);
+}
+
 __global__ void k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -81,9 +162,12 @@ using namespace dsa;
 // 3 = v_add_u32, 4 = v_max_i32, 6 = v_pk_maximum3_f16 (result: instructions
 // per second summed over lanes); 5 = HBM copy of `bytes` (result: bytes read
 // + written per second); 7 = the three-way maximum order check (result: the
-// number of wrong results).
+// number of wrong results); 8 = local cells per second, packed int16 (two
+// targets per lane), 9 = the same with four 8-bit targets per lane, each
+// over `size` columns; 10 = the byte sign-spread check of the 8-bit probe
+// (result: the number of wrong results).
 extern "C" int dsa_probe(int which, int64_t size, double *rate) {
-    if (!rate || which < 0 || which > 7 || size <= 0) return DSA_E_INVAL;
+    if (!rate || which < 0 || which > 10 || size <= 0) return DSA_E_INVAL;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) != hipSuccess) return DSA_E_DEVICE;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
@@ -96,10 +180,25 @@ extern "C" int dsa_probe(int which, int64_t size, double *rate) {
     };
     if (ok(hipEventCreate(&a)) && ok(hipEventCreate(&b))) {
         float ms = 0.f;
-        if (which == 7) {
+        if (which == 8 || which == 9) {
+            const int blocks = cus * 8;
+            const int cols = (int)std::min<int64_t>(size, 1 << 24);
+            if (ok(hipMalloc(&p0, (size_t)blocks * 256 * sizeof(uint32_t)))) {
+                uint32_t *out = (uint32_t *)p0;
+                auto launch = [&]() {
+                    if (which == 8) hipLaunchKernelGGL(k_cells16, dim3(blocks), dim3(256), 0, 0, out, cols, 7u);
+                    else hipLaunchKernelGGL(k_cells8, dim3(blocks), dim3(256), 0, 0, out, cols, 7u);
+                    return hipGetLastError();
+                };
+                if (ok(launch()) && ok(hipEventRecord(a, 0)) && ok(launch()) && ok(hipEventRecord(b, 0)) &&
+                    ok(hipEventSynchronize(b)) && ok(hipEventElapsedTime(&ms, a, b)))
+                    *rate = (double)blocks * 256.0 * (which == 8 ? 2.0 : 4.0) * 16.0 * cols / (ms * 1e-3);
+            }
+        } else if (which == 7 || which == 10) {
             unsigned long long bad = 0;
             if (ok(hipMalloc(&p0, sizeof(bad))) && ok(hipMemset(p0, 0, sizeof(bad)))) {
-                hipLaunchKernelGGL(k_max3_order, dim3(cus * 8), dim3(256), 0, 0, (unsigned long long *)p0);
+                if (which == 7) hipLaunchKernelGGL(k_max3_order, dim3(cus * 8), dim3(256), 0, 0, (unsigned long long *)p0);
+                else hipLaunchKernelGGL(k_spread_check, dim3(cus * 8), dim3(256), 0, 0, (unsigned long long *)p0);
                 if (ok(hipGetLastError()) && ok(hipMemcpy(&bad, p0, sizeof(bad), hipMemcpyDeviceToHost)))
                     *rate = (double)bad;
             }

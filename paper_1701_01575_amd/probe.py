@@ -1,9 +1,12 @@
 """Measured ceilings on the current GPU (dsa_probe): VALU issue rate of the
-instructions the alignment kernels use, and an HBM copy of known size (also
-the reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE).
+instructions the alignment kernels use, an HBM copy of known size (also
+the reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE), and the
+local-mode cell rate of a bare 16-row column in packed int16 against 8-bit
+lanes of 32-bit words.
 
     python paper_1701_01575_amd/probe.py            # all probes
     python paper_1701_01575_amd/probe.py copy BYTES # one copy of BYTES
+    python paper_1701_01575_amd/probe.py cells      # the two cell rates only
 """
 import os
 import sys
@@ -24,6 +27,9 @@ def main(argv):
         r = B.dsa_probe(5, int(argv[1]))
         print(f"copy of {int(argv[1])} bytes x 6 launches: {r / 1e9:.0f} GB/s (read + write)")
         return
+    if len(argv) >= 1 and argv[0] == "cells":
+        cells()
+        return
     for w, (n, per) in NAMES.items():
         r = B.dsa_probe(w, 20000)
         print(f"{n:22s} {r / 1e12:7.2f} T lane-instructions/s  ({r * per / 1e12:.2f} T 16-bit ops/s)")
@@ -31,6 +37,16 @@ def main(argv):
     print(f"HBM copy of 4 GiB: {r / 1e9:.0f} GB/s (read + write)")
     bad = B.dsa_probe(7, 1)
     print(f"v_pk_maximum3_f16 order check (offset local-mode operands): {int(bad)} wrong results")
+    cells()
+
+
+def cells():
+    bad = B.dsa_probe(10, 1)
+    print(f"byte sign spread check (8-bit probe): {int(bad)} wrong results")
+    r16, r8 = B.dsa_probe(8, 65536), B.dsa_probe(9, 65536)
+    print(f"local cells, packed int16 (2 targets per lane):  {r16 / 1e12:6.2f} T cells/s")
+    print(f"local cells, 8-bit lanes (4 targets per lane):   {r8 / 1e12:6.2f} T cells/s")
+    print(f"int16 / 8-bit: {r16 / r8:.2f}")
 
 
 if __name__ == "__main__":

@@ -13,3 +13,13 @@ def test_max3_order_exhaustive():
     import torch
     torch.cuda.init()
     assert B.dsa_probe(7, 1) == 0.0
+
+
+def test_spread_and_cell_rates():
+    """The byte sign spread of the 8-bit probe is exact on the device, and
+    both cell-rate probes run (their rates are recorded with the profiles)."""
+    import torch
+    torch.cuda.init()
+    assert B.dsa_probe(10, 1) == 0.0
+    r16, r8 = B.dsa_probe(8, 4096), B.dsa_probe(9, 4096)
+    assert r16 > 0 and r8 > 0
