@@ -150,12 +150,16 @@ __device__ __forceinline__ void ks16_unit(const SearchArgs &P, const SearchUnit 
                 const uint2 cd = cd_n;
                 cd_n = pk[(int64_t)(c4 + 1 < nblk ? c4 + 1 : 0) * 64];
                 const char *prow = reinterpret_cast<const char *>(qp + (r & 1) * AP * stride + wave * 16);
+                // the four columns' letter-row offsets up front, so that a
+                // column's profile reads wait for one LDS round trip, not two
+                uint32_t rw4[4];
+#pragma unroll
+                for (int c = 0; c < 4; c++) rw4[c] = rows[((c < 2 ? cd.x : cd.y) >> ((c & 1) * 16)) & 0xffffu];
                 uint2 out[4];
 #pragma unroll
                 for (int c = 0; c < 4; c++) {
                     const int j = c4 * 4 + c + 1;
-                    const uint32_t p = ((c < 2 ? cd.x : cd.y) >> ((c & 1) * 16)) & 0xffffu;
-                    const uint32_t rw = rows[p];
+                    const uint32_t rw = rw4[c];
                     const uint4 *plo = reinterpret_cast<const uint4 *>(prow + (rw & 0xffffu));
                     const uint4 *phi = reinterpret_cast<const uint4 *>(prow + (rw >> 16));
                     uint32_t sc[T];
