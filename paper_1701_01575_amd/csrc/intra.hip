@@ -8,7 +8,7 @@
 // [16 s, 16 s + 16) for strip s = 64 * pass + l.  The lanes sweep the target
 // columns on an anti-diagonal: at step t lane l computes column t - l + 1, so
 // the row above it (lane l - 1's last row, one step earlier) arrives through
-// a lane shuffle together with the F leaving it.  Between passes lane 63's
+// a DPP row shift (wave_shr:1) together with the F leaving it.  Between passes lane 63's
 // last row goes through a boundary buffer in HBM.  Same recurrence, modes,
 // saturation rules and end-cell rule as the inter-sequence kernel; strips
 // track their own strictly-greater best, merged lexicographically (score

@@ -1,6 +1,12 @@
-// Pairwise alignment with traceback: query k against target k.
+// Pairwise alignment with traceback: query k against target k, the exact
+// int32 kernels.  Pairs with short queries or few cells run here one pair per
+// lane (k_pair32, k_walk); longer pairs take the packed int16 wavefront fill
+// and checkpoint walk of pair16.hip, and the pairs that leave its exact int16
+// range come back to the int32 wavefront kernels below (k_pairwf, k_walk_wf),
+// which also serve every longer pair when int16 is not used (DSA_FORCE_INT32,
+// position-specific profiles, alphabets above 32 letters).
 //
-// Fill (k_pair32): one pair per lane, exact int32, the same recurrence, modes,
+// Lane-per-pair fill (k_pair32): one pair per lane, exact int32, the same recurrence, modes,
 // boundaries and end-cell rule as the database kernels.  Pairs are sorted by
 // strip count and target length into groups of 64 so that a wave's lanes
 // share the strip count; the query is cut into 16-row strips held in VGPRs,
@@ -273,8 +279,8 @@ hipError_t launch_pair32(const PairArgs &a, int mode, hipStream_t s) {
 // mix segment widths, longest first).  Segment lane l owns rows
 // [16 s, 16 s + 16) of strip s = SEG * pass + l and at step t computes
 // column t - l + 1, so the row above (lane l - 1's last row one step
-// earlier) and the F leaving it arrive by a lane shuffle inside the
-// segment; between passes the segment's last lane hands its last row over
+// earlier) and the F leaving it arrive by a DPP wave shift (a segment's
+// first lane takes the boundary instead); between passes the segment's last lane hands its last row over
 // through the pair's boundary row in HBM.  Exact int32, the same
 // recurrence, direction codes and end-cell rule as k_pair32.  A lane's 16
 // codes of one step are 64 bits, stored in blocks of kWfBlock steps per lane

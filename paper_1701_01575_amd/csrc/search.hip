@@ -18,11 +18,22 @@
 // database stores for each lane and column, so one 4-byte LDS word feeds a
 // packed add.  All waves of a workgroup share the strip's profile.
 //
-// Local mode uses unsigned saturating subtractions for E and F, which
-// clamps them at 0 and makes the explicit 0 in the H maximum redundant:
-// 9 packed instructions per two cells.  An int16 result that reached 32767
-// may have saturated; its unit is flagged and the exact int32 kernel
-// recomputes it (the int32 kernel also serves DSA_FORCE_INT32).
+// Local mode holds each value as value + kBias16 in a column-shifted frame
+// (column j adds (j - 1) e, taken back every few column blocks), where the
+// E decrement disappears and E and F share one subtraction.  The bias keeps
+// every reachable pattern a positive normal binary16 number, on which
+// v_pk_maximum3_f16 is the integer maximum, so the H maximum, the zero
+// floors and the running best are three-way maxima: 6.5 packed
+// instructions per two cells (pk16.h).  Global and semi-global use signed
+// saturating int16.  A unit whose int16 best passes the exact range is
+// flagged, and the exact int32 kernel recomputes it (the int32 kernel also
+// serves DSA_FORCE_INT32).
+//
+// Persistent form: one launch pulls units from a longest-first work list on
+// an atomic counter.  Besides the inter-sequence units it runs, with the
+// whole block, the wavefront units of long targets (intra_unit.h) and the
+// strip-pipelined units that share one group's strips among the block's
+// waves (ks_unit.h).
 //
 // End cell (smallest target end j, then smallest query end i, among cells
 // reaching the best score): each strip scans its columns in order and keeps
