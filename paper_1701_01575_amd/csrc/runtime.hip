@@ -780,29 +780,46 @@ bool pk16_disabled() {
 }
 
 // Reorder idx by key(idx) descending, equal keys keeping their order (the
-// result of a stable sort).  Keys below 2^40 and fewer than 2^24 entries pack
-// (key, position) into one 64-bit word, so the sort compares plain integers;
-// otherwise (key, position) records are sorted.
+// result of a stable sort).  Short lists take a comparison sort; longer ones
+// a least-significant-digit radix sort on 11-bit digits (stable by
+// construction, digits complemented for the descending order), as many
+// passes as the largest key has digits: the planning of 100,000 pairs sorts
+// several lists of that length per call.
 template <class Key>
 static void sort_desc_stable(std::vector<int64_t> &idx, Key key) {
     const size_t n = idx.size();
+    if (n < 2) return;
     uint64_t kmax = 0;
     std::vector<uint64_t> keys(n);
     for (size_t p = 0; p < n; p++) kmax = std::max(kmax, keys[p] = key(idx[p]));
-    if (kmax < ((uint64_t)1 << 40) && n < ((size_t)1 << 24)) {
-        std::vector<uint64_t> w(n);
-        for (size_t p = 0; p < n; p++) w[p] = (keys[p] << 24) | (uint64_t)(((size_t)1 << 24) - 1 - p);
-        std::sort(w.begin(), w.end(), std::greater<uint64_t>());
+    if (n < 2048) {
+        std::vector<size_t> ord(n);
+        std::iota(ord.begin(), ord.end(), (size_t)0);
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return keys[a] > keys[b]; });
         std::vector<int64_t> out(n);
-        for (size_t p = 0; p < n; p++) out[p] = idx[((size_t)1 << 24) - 1 - (size_t)(w[p] & 0xffffff)];
+        for (size_t p = 0; p < n; p++) out[p] = idx[ord[p]];
         idx.swap(out);
         return;
     }
-    struct R { uint64_t k; int64_t pos, v; };
-    std::vector<R> rec(n);
-    for (size_t p = 0; p < n; p++) rec[p] = R{keys[p], (int64_t)p, idx[p]};
-    std::sort(rec.begin(), rec.end(), [](const R &a, const R &b) { return a.k != b.k ? a.k > b.k : a.pos < b.pos; });
-    for (size_t p = 0; p < n; p++) idx[p] = rec[p].v;
+    constexpr int kBits = 11;
+    constexpr uint64_t kMask = (1u << kBits) - 1;
+    int bits = 0;
+    while (bits < 64 && (kmax >> bits) != 0) bits++;
+    std::vector<uint64_t> k2(n);
+    std::vector<int64_t> i2(n);
+    std::vector<size_t> cnt(kMask + 2);
+    for (int shift = 0; shift < bits; shift += kBits) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (size_t p = 0; p < n; p++) cnt[kMask - ((keys[p] >> shift) & kMask) + 1]++;
+        for (size_t d = 1; d < cnt.size(); d++) cnt[d] += cnt[d - 1];
+        for (size_t p = 0; p < n; p++) {
+            const size_t at = cnt[kMask - ((keys[p] >> shift) & kMask)]++;
+            k2[at] = keys[p];
+            i2[at] = idx[p];
+        }
+        keys.swap(k2);
+        idx.swap(i2);
+    }
 }
 
 // The packed int16 fill: whether a call may use it, its gap penalties and
@@ -1104,11 +1121,17 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     int64_t wchunk = 0;
     std::vector<WP> wp;
     wp.reserve(2 * kWave);
+    std::vector<int64_t> wwords;  // region words of the wave's pairs, in wp order
+    wwords.reserve(2 * kWave);
     for (size_t v = 0; v < wv.size(); v++) {
         const WaveSpec &w = wv[v];
         wave_pairs(w, wp);
         int64_t wave_words = 0;
-        for (const auto &x : wp) wave_words += region_words(x.k, x.u);
+        wwords.clear();
+        for (const auto &x : wp) {
+            wwords.push_back(region_words(x.k, x.u));
+            wave_words += wwords.back();
+        }
         if (plain) {
             if (v == 0) { P.wf_chunk_first.push_back(0); P.wf_chunk_pair.push_back(0); P.pk_chunk_first.push_back(0); }
             wchunk = 0;
@@ -1158,10 +1181,10 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
                 (wp[q].role ? U.b : U.a) = (int32_t)(p0 + (int64_t)q);
             }
         }
-        for (const auto &pq : wp) {
-            const int64_t k = pq.k, u = pq.u;
+        for (size_t q = 0; q < wp.size(); q++) {
+            const int64_t k = wp[q].k, u = wp[q].u;
             const PairSpec &x = sp[k];
-            const int64_t words = region_words(k, u);
+            const int64_t words = wwords[q];
             WfPair W;
             memset(&W, 0, sizeof(W));
             W.slot = (int32_t)P.slots.size();
