@@ -27,6 +27,9 @@
 // query's sum of row maxima above hlim) and local pairs whose best score
 // exceeds it are flagged; the exact int32 kernels then redo them (fill with
 // direction codes in the same region, and their own walk).
+#include <type_traits>
+#include <utility>
+
 #include "pair16.h"
 #include "pk16.h"
 #include "walk.h"
@@ -497,6 +500,25 @@ __device__ __forceinline__ int row_above(int v) {  // lane r - 1 of the 16-lane 
 __device__ __forceinline__ int row_next(int v) {   // lane r + 1 of the 16-lane row (0 for lane 15)
     return __builtin_amdgcn_update_dpp(0, v, 0x101 /* row_shl:1 */, 0xf, 0xf, false);
 }
+// lane r - 1's v in the 16-lane row, `first` in lane 0
+__device__ __forceinline__ int row_shr1(int first, int v) {
+    return __builtin_amdgcn_update_dpp(first, v, 0x111 /* row_shr:1 */, 0xf, 0xf, false);
+}
+// lane r - K's v, v itself in lanes r < K (a step of a prefix maximum)
+template <int K>
+__device__ __forceinline__ int row_shr_keep(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, 0x110 + K /* row_shr:K */, 0xf, 0xf, false);
+}
+// f(integral_constant<int, X>) for X in the sequence, in order
+template <int... X, class Fn>
+__device__ __forceinline__ void for_cols(std::integer_sequence<int, X...>, Fn &&f) {
+    (f(std::integral_constant<int, X>{}), ...);
+}
+// lane X's v in every lane of the 16-lane row
+template <int X>
+__device__ __forceinline__ int bcast16(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x150 + X /* row_newbcast:X */, 0xf, 0xf, false);
+}
 
 template <int MODE>
 __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args X) {
@@ -581,44 +603,47 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
         if (s == 0) corner = top_value(MODE, ends, o, e, c0);
         else if (c0 == 0) corner = left_value(MODE, ends, o, e, i0);
         else corner = (int)(ck[pk16_bot_at(s - 1, c0 + lp - 1, S, seg, NST)] & 0xffffu) - bias;
-        // wavefront: at step u lane r computes column x = u - r of its row;
-        // lane 0 takes column u from the top arrays, which shift one lane
-        // towards lane 0 every step, and each lane hands H, F and the
-        // column's residue to the lane below
-        int Hd_top = row_above(Hl);
-        if (r == 0) Hd_top = corner;
-        int outH = 0, outF = 0, outT = 0;
-        const int nsteps = nc + nr - 1;
-        for (int u = 0; u < nsteps; u++) {
-            int rH = row_above(outH), rF = row_above(outF), rT = row_above(outT);
-            if (r == 0) { rH = colH; rF = colF; rT = colT; }
-            colH = row_next(colH);
-            colF = row_next(colF);
-            colT = row_next(colT);
-            const int x = u - r;
-            if (x >= 0 && x < nc && r < nr) {
-                const int hd = Hd_top;
-                Hd_top = rH;
-                const int t = hd + (int)sm[qrow + min(rT, A - 1)];
-                const int Ein = El, Fin = rF;
-                int h = max(max(t, Ein), Fin);
-                if (MODE == LOCAL) h = max(h, 0);
-                const int ho = h - o;
-                uint32_t code = (h == t) ? 1u : ((h == Ein) ? 2u : 3u);
-                if (MODE == LOCAL && h == 0) code = 0u;
-                code |= (Ein > Hl - o) ? 4u : 0u;  // E(i, c) extends E(i, c - 1)
-                code |= (Fin > rH - o) ? 8u : 0u;  // F(i, c) extends F(i - 1, c)
-                code |= (qcode == rT) ? 16u : 0u;  // residues equal (= or X on the diagonal)
-                int En = max(Ein - e, ho), Fn = max(Fin - e, ho);
-                if (MODE == LOCAL) { En = max(En, 0); Fn = max(Fn, 0); }
-                El = En;
-                Hl = h;
-                outH = h;
-                outF = Fn;
-                outT = rT;
-                mine[x] = (uint8_t)code;
-            }
-        }
+        // the tile column by column, all 16 rows at once.  F runs down a
+        // column as a prefix maximum: with hp = max(diagonal + s, E[, 0]),
+        // F(row r) = max(Ftop - r e, max over k < r of hp(k) - o - (r-1-k) e)
+        // [, 0], since where F wins in a row H - o is below F - e (o >= e),
+        // so the recurrence can drop F from the H it passes down.  The row
+        // above comes from lane r - 1 by DPP row shifts, lane 0 takes the
+        // strip above's row; a column's residue and top words are
+        // broadcast from its lane
+        int Hprev = Hl;   // H(i, c - 1)
+        int E = El;       // E(i, c)
+        int dtop = corner;  // H(i0, c - 1): lane 0's diagonal
+        const int re = r * e;
+        for_cols(std::make_integer_sequence<int, kCkCols>{}, [&](auto xc) {
+            constexpr int x = decltype(xc)::value;
+            if (x >= nc) return;  // uniform in a 16-lane group
+            const int T = bcast16<x>(colT), htop = bcast16<x>(colH), ftop = bcast16<x>(colF);
+            const int diag = row_shr1(dtop, Hprev);
+            const int t = diag + (int)sm[qrow + min(T, A - 1)];
+            int hp = max(t, E);
+            if (MODE == LOCAL) hp = max(hp, 0);
+            int Y = row_shr1(ftop - e, hp - o + re);  // lane r: row r - 1's term, lane 0: the top's
+            Y = max(Y, row_shr_keep<1>(Y));
+            Y = max(Y, row_shr_keep<2>(Y));
+            Y = max(Y, row_shr_keep<4>(Y));
+            Y = max(Y, row_shr_keep<8>(Y));
+            int F = Y - re + e;
+            if (MODE == LOCAL) F = max(F, 0);
+            const int h = max(hp, F);
+            const int hup = row_shr1(htop, h);  // H(i - 1, c)
+            uint32_t code = (h == t) ? 1u : ((h == E) ? 2u : 3u);
+            if (MODE == LOCAL && h == 0) code = 0u;
+            code |= (E > Hprev - o) ? 4u : 0u;  // E(i, c) extends E(i, c - 1)
+            code |= (F > hup - o) ? 8u : 0u;    // F(i, c) extends F(i - 1, c)
+            code |= (qcode == T) ? 16u : 0u;    // residues equal (= or X on the diagonal)
+            if (r < nr) mine[x] = (uint8_t)code;
+            int En = max(E - e, h - o);
+            if (MODE == LOCAL) En = max(En, 0);
+            E = En;
+            Hprev = h;
+            dtop = htop;
+        });
         asm volatile("" ::: "memory");  // the codes are in LDS before any lane reads them
         // follow the codes out of the tile (every lane the same walk)
         bool stop = false;
