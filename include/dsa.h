@@ -353,7 +353,8 @@ int dsa_timing_reset(void);
  * recurrence (scores from an LDS profile, no boundary or end-cell work),
  * 8 in packed int16 (two targets per lane), 9 in 8-bit lanes of 32-bit
  * words (four targets per lane), size = columns per lane; 10 -> *rate = the
- * number of wrong results of the byte sign spread that 9 uses (must be 0).
+ * number of wrong results of the byte sign spread that 9 uses (must be 0);
+ * 11..14 -> 8 with 1..4 waves per SIMD instead of 8.
  */
 int dsa_probe(int which, int64_t size, double *rate);
 

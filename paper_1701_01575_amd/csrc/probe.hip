@@ -165,9 +165,10 @@ using namespace dsa;
 // number of wrong results); 8 = local cells per second, packed int16 (two
 // targets per lane), 9 = the same with four 8-bit targets per lane, each
 // over `size` columns; 10 = the byte sign-spread check of the 8-bit probe
-// (result: the number of wrong results).
+// (result: the number of wrong results); 11..14 = 8 with 1..4 waves per
+// SIMD instead of 8 (how many waves the column needs to keep a SIMD busy).
 extern "C" int dsa_probe(int which, int64_t size, double *rate) {
-    if (!rate || which < 0 || which > 10 || size <= 0) return DSA_E_INVAL;
+    if (!rate || which < 0 || which > 14 || size <= 0) return DSA_E_INVAL;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) != hipSuccess) return DSA_E_DEVICE;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
@@ -180,19 +181,21 @@ extern "C" int dsa_probe(int which, int64_t size, double *rate) {
     };
     if (ok(hipEventCreate(&a)) && ok(hipEventCreate(&b))) {
         float ms = 0.f;
-        if (which == 8 || which == 9) {
-            const int blocks = cus * 8;
+        if (which == 8 || which == 9 || (which >= 11 && which <= 14)) {
+            // 8 x 256-thread blocks per CU (8 waves per SIMD), or for 11..14
+            // the int16 column with 1..4 waves per SIMD
+            const int blocks = cus * (which >= 11 ? which - 10 : 8);
             const int cols = (int)std::min<int64_t>(size, 1 << 24);
             if (ok(hipMalloc(&p0, (size_t)blocks * 256 * sizeof(uint32_t)))) {
                 uint32_t *out = (uint32_t *)p0;
                 auto launch = [&]() {
-                    if (which == 8) hipLaunchKernelGGL(k_cells16, dim3(blocks), dim3(256), 0, 0, out, cols, 7u);
-                    else hipLaunchKernelGGL(k_cells8, dim3(blocks), dim3(256), 0, 0, out, cols, 7u);
+                    if (which == 9) hipLaunchKernelGGL(k_cells8, dim3(blocks), dim3(256), 0, 0, out, cols, 7u);
+                    else hipLaunchKernelGGL(k_cells16, dim3(blocks), dim3(256), 0, 0, out, cols, 7u);
                     return hipGetLastError();
                 };
                 if (ok(launch()) && ok(hipEventRecord(a, 0)) && ok(launch()) && ok(hipEventRecord(b, 0)) &&
                     ok(hipEventSynchronize(b)) && ok(hipEventElapsedTime(&ms, a, b)))
-                    *rate = (double)blocks * 256.0 * (which == 8 ? 2.0 : 4.0) * 16.0 * cols / (ms * 1e-3);
+                    *rate = (double)blocks * 256.0 * (which == 9 ? 4.0 : 2.0) * 16.0 * cols / (ms * 1e-3);
             }
         } else if (which == 7 || which == 10) {
             unsigned long long bad = 0;

@@ -47,6 +47,9 @@ def cells():
     print(f"local cells, packed int16 (2 targets per lane):  {r16 / 1e12:6.2f} T cells/s")
     print(f"local cells, 8-bit lanes (4 targets per lane):   {r8 / 1e12:6.2f} T cells/s")
     print(f"int16 / 8-bit: {r16 / r8:.2f}")
+    for w in (1, 2, 3, 4):
+        r = B.dsa_probe(10 + w, 16384)
+        print(f"local cells, packed int16, {w} wave(s) per SIMD: {r / 1e12:6.2f} T cells/s")
 
 
 if __name__ == "__main__":
