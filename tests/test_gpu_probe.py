@@ -23,3 +23,5 @@ def test_spread_and_cell_rates():
     assert B.dsa_probe(10, 1) == 0.0
     r16, r8 = B.dsa_probe(8, 4096), B.dsa_probe(9, 4096)
     assert r16 > 0 and r8 > 0
+    rw = [B.dsa_probe(10 + w, 1024) for w in (1, 2, 3, 4)]  # 1..4 waves per SIMD
+    assert all(r > 0 for r in rw)
