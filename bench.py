@@ -568,6 +568,9 @@ def main():
                    "residues": int(T.lengths.sum()),
                    "form": "batched (persistent, LPT units, replayed from a HIP graph)"},
         "eager_call_ms": round(eager_ms, 3),
+        # each timed replay by HIP events on its stream
+        "replay_ms": {"median": round(float(np.median(replay_ms)), 3), "min": round(min(replay_ms), 3),
+                      "max": round(max(replay_ms), 3)},
         "autotuned": tuned or None,
         "graph_replay_equals_eager": graph_agrees,
         "plain": None if plain_gcups is None else {
