@@ -712,6 +712,51 @@ struct PairPlan {
     size_t off_end = 0, off_bnd = 0, off_tpk = 0, off_tb = 0, off_bndw = 0, off_tbw = 0, total = 0;
 };
 
+// The large tables of a pair plan keep their memory per thread between calls:
+// the tables of 100,000 pairs are megabytes, and a fresh allocation is new
+// pages each call, whose faults cost more than the planning.  A
+// RecycledPairPlan borrows the thread's spare buffers and hands them back
+// when it ends; a second one alive at the same time simply starts empty.
+struct PlanBuffers {
+    std::vector<PairInfo> slots;
+    std::vector<PairGroup> groups;
+    std::vector<WfPair> wf;
+    std::vector<WfWave> waves;
+    std::vector<Pk16Unit> units;
+    std::vector<Pk16Pair> pkpairs;
+    std::vector<int32_t> pkflags;
+    std::vector<int8_t> lanemap;
+};
+thread_local PlanBuffers t_planbuf;
+struct RecycledPairPlan {
+    PairPlan P;
+    RecycledPairPlan() {
+        swap_all();
+        P.slots.clear();
+        P.groups.clear();
+        P.wf.clear();
+        P.waves.clear();
+        P.units.clear();
+        P.pkpairs.clear();
+        P.pkflags.clear();
+        P.lanemap.clear();
+    }
+    ~RecycledPairPlan() { swap_all(); }
+    RecycledPairPlan(const RecycledPairPlan &) = delete;
+    RecycledPairPlan &operator=(const RecycledPairPlan &) = delete;
+    void swap_all() {
+        PlanBuffers &b = t_planbuf;
+        P.slots.swap(b.slots);
+        P.groups.swap(b.groups);
+        P.wf.swap(b.wf);
+        P.waves.swap(b.waves);
+        P.units.swap(b.units);
+        P.pkpairs.swap(b.pkpairs);
+        P.pkflags.swap(b.pkflags);
+        P.lanemap.swap(b.lanemap);
+    }
+};
+
 PairCaps caps_of(const PairPlan &P) {
     PairCaps c;
     c.slots = (int64_t)P.slots.size();
@@ -790,7 +835,10 @@ static void sort_desc_stable(std::vector<int64_t> &idx, Key key) {
     const size_t n = idx.size();
     if (n < 2) return;
     uint64_t kmax = 0;
-    std::vector<uint64_t> keys(n);
+    // scratch kept per thread between calls (see PlanScratch)
+    static thread_local std::vector<uint64_t> keys, k2;
+    static thread_local std::vector<int64_t> i2;
+    keys.resize(n);
     for (size_t p = 0; p < n; p++) kmax = std::max(kmax, keys[p] = key(idx[p]));
     if (n < 2048) {
         std::vector<size_t> ord(n);
@@ -805,8 +853,8 @@ static void sort_desc_stable(std::vector<int64_t> &idx, Key key) {
     constexpr uint64_t kMask = (1u << kBits) - 1;
     int bits = 0;
     while (bits < 64 && (kmax >> bits) != 0) bits++;
-    std::vector<uint64_t> k2(n);
-    std::vector<int64_t> i2(n);
+    k2.resize(n);
+    i2.resize(n);
     std::vector<size_t> cnt(kMask + 2);
     for (int shift = 0; shift < bits; shift += kBits) {
         std::fill(cnt.begin(), cnt.end(), 0);
@@ -858,7 +906,12 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     P.traceback = traceback;
     P.plain = plain;
     auto is_wf = [&](const PairSpec &x) { return x.m >= route.rows && x.m * x.n >= route.cells; };
-    std::vector<int64_t> order, worder;
+    // the planner's scratch lists live per thread between calls: a fresh
+    // list of 100,000 entries per call is new pages each time, and faulting
+    // them in costs more than the planning itself
+    static thread_local std::vector<int64_t> order, worder;
+    order.clear();
+    worder.clear();
     order.reserve(sp.size());
     worder.reserve(sp.size());
     for (int64_t k = 0; k < (int64_t)sp.size(); k++) {
@@ -872,7 +925,10 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     if (!plain)  // strips, then target length (both below 2^17)
         sort_desc_stable(order, [&](int64_t k) { return ((uint64_t)strips(k) << 17) | (uint64_t)sp[k].n; });
     // CIGAR regions in result order: m + n + 1 runs each while capacity lasts
-    std::vector<int64_t> need(std::max<int64_t>(n_results, 1), 0), roff(need.size(), 0), rcap(need.size(), 0);
+    static thread_local std::vector<int64_t> need, roff, rcap;
+    need.assign(std::max<int64_t>(n_results, 1), 0);
+    roff.assign(need.size(), 0);
+    rcap.assign(need.size(), 0);
     for (const auto &x : sp) need[x.res] = x.m + x.n + 1;
     {
         int64_t acc = 0;
@@ -979,14 +1035,19 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     // segment (waves of 64 / seg units), the others to waves of the int32
     // kernel, and every packed wave also gets the int32 waves of its pairs
     // (they run only the pairs the packed fill flags).
-    std::vector<int> segk(sp.size(), 0);
+    static thread_local std::vector<int> segk;
+    segk.assign(sp.size(), 0);
     for (int64_t k : worder) segk[k] = wf_seg(sp[k].m);
     const bool use_pk = pk.on && !plain;
-    std::vector<int32_t> pbias(sp.size(), 0), phlim(sp.size(), 0);
-    std::vector<char> pkok(sp.size(), 0);
-    std::vector<int64_t> el;  // the pairs of the packed kind
+    static thread_local std::vector<int32_t> pbias, phlim;
+    static thread_local std::vector<char> pkok;
+    static thread_local std::vector<int64_t> el, rest;  // el: the pairs of the packed kind
+    pbias.assign(sp.size(), 0);
+    phlim.assign(sp.size(), 0);
+    pkok.assign(sp.size(), 0);
+    el.clear();
     if (use_pk) {
-        std::vector<int64_t> rest;
+        rest.clear();
         for (int64_t k : worder) {
             pk16_bias(pk, mode, sp[k].m, sp[k].n, &pbias[k], &phlim[k]);
             pkok[k] = phlim[k] >= kPk16MinLimit;
@@ -998,7 +1059,52 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
         sort_desc_stable(worder, [&](int64_t k) {
             return ((uint64_t)segk[k] << 33) | (uint64_t)(sp[k].m * sp[k].n);
         });
-    auto strips_of = [&](int64_t k) { return (sp[k].m + kTP - 1) / kTP; };
+    auto strips_in = [&](int64_t k) { return (sp[k].m + kTP - 1) / kTP; };
+    if (use_pk)
+        sort_desc_stable(el, [&](int64_t k) { return ((uint64_t)strips_in(k) << 17) | (uint64_t)sp[k].n; });
+    // the wavefront pairs renumbered in the order their waves take them
+    // (packed pairs, then the int32 kind), with what the loops below read of
+    // each: one gather per pair, then reads that follow each other in memory
+    // instead of jumping across the whole input
+    static thread_local std::vector<PairSpec> spw;
+    static thread_local std::vector<int> segw;
+    static thread_local std::vector<int32_t> biasw, hlimw;
+    static thread_local std::vector<int64_t> coffw, ccapw;
+    spw.resize(el.size() + worder.size());
+    segw.resize(spw.size());
+    biasw.resize(spw.size());
+    hlimw.resize(spw.size());
+    coffw.resize(spw.size());
+    ccapw.resize(spw.size());
+    {
+        // the order is a permutation of the input: each record is a cache
+        // miss, so the loop fetches 16 records ahead
+        size_t i = 0;
+        auto ahead = [&](int64_t k) {
+            __builtin_prefetch(&sp[k]);
+            __builtin_prefetch(&segk[k]);
+            __builtin_prefetch(&pbias[k]);
+            __builtin_prefetch(&phlim[k]);
+            __builtin_prefetch(&roff[sp[k].res]);
+            __builtin_prefetch(&rcap[sp[k].res]);
+        };
+        auto gather = [&](std::vector<int64_t> &list) {
+            for (size_t q = 0; q < list.size(); q++) {
+                if (q + 16 < list.size()) ahead(list[q + 16]);
+                const int64_t k = list[q];
+                spw[i] = sp[k];
+                segw[i] = segk[k];
+                biasw[i] = pbias[k];
+                hlimw[i] = phlim[k];
+                coffw[i] = roff[sp[k].res];
+                ccapw[i] = rcap[sp[k].res];
+                list[q] = (int64_t)i++;
+            }
+        };
+        gather(el);
+        gather(worder);
+    }
+    auto strips_of = [&](int64_t k) { return (spw[k].m + kTP - 1) / kTP; };
     // A wave to plan: packed (units [u_first, +u_count) of `units`) or int32
     // (pairs [first, +count) of `wo`, one segment width).
     struct WaveSpec {
@@ -1009,23 +1115,26 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
         int64_t cost = 0;                // steps: passes x (longest target + lanes - 1)
     };
     struct UnitSpec {
-        int64_t a = -1, b = -1;          // into sp
+        int64_t a = -1, b = -1;          // into spw
         int w = 0;
         int64_t nst = 0, cost = 0;
     };
-    std::vector<int64_t> wo;             // pairs of the int32 kind in wave order
-    std::vector<UnitSpec> us;
-    std::vector<WaveSpec> wv;
+    static thread_local std::vector<int64_t> wo;    // pairs of the int32 kind in wave order
+    static thread_local std::vector<UnitSpec> us, us_sorted;
+    static thread_local std::vector<WaveSpec> wv, wv_sorted;
+    static thread_local std::vector<int64_t> ui, wi;
+    wo.clear();
+    us.clear();
+    wv.clear();
     if (use_pk) {
         // units of two pairs with equal or neighbouring strip counts, as many
         // lanes as strips (passes of equal width beyond 64 strips)
-        sort_desc_stable(el, [&](int64_t k) { return ((uint64_t)strips_of(k) << 17) | (uint64_t)sp[k].n; });
         for (size_t q = 0; q < el.size(); q += 2) {
             UnitSpec u;
             u.a = el[q];
             u.b = q + 1 < el.size() ? el[q + 1] : -1;
             const int64_t S = std::max(strips_of(u.a), u.b >= 0 ? strips_of(u.b) : 0);
-            const int64_t nmax = std::max(sp[u.a].n, u.b >= 0 ? sp[u.b].n : 0);
+            const int64_t nmax = std::max(spw[u.a].n, u.b >= 0 ? spw[u.b].n : 0);
             // the fewest passes that fit 64 lanes (more passes of narrower
             // segments pack waves fuller but measured slower: the fill is
             // bound by each wave's issue, and fewer, longer waves hide less)
@@ -1035,12 +1144,12 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
             u.cost = passes * (nmax + u.w - 1);
             us.push_back(u);
         }
-        std::vector<int64_t> ui(us.size());
+        ui.resize(us.size());
         for (size_t v = 0; v < us.size(); v++) ui[v] = (int64_t)v;
         sort_desc_stable(ui, [&](int64_t v) { return (uint64_t)us[v].cost; });
-        std::vector<UnitSpec> sorted(us.size());
-        for (size_t v = 0; v < us.size(); v++) sorted[v] = us[ui[v]];
-        us.swap(sorted);
+        us_sorted.resize(us.size());
+        for (size_t v = 0; v < us.size(); v++) us_sorted[v] = us[ui[v]];
+        us.swap(us_sorted);
         // waves of consecutive units while their lanes fit in 64 (filling the
         // gaps best-fit with later, shorter units measured slower: fewer
         // waves hide less of each wave's latency)
@@ -1060,7 +1169,7 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     }
     for (size_t q = 0; q < worder.size(); q++) {  // the int32 kind
         const int64_t k = worder[q];
-        const int seg = segk[k];
+        const int seg = segw[k];
         if (plain || wv.empty() || wv.back().packed || wv.back().seg != seg || wv.back().count == kWave / seg) {
             WaveSpec x;
             x.first = (int64_t)wo.size();
@@ -1070,17 +1179,17 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
         WaveSpec &w = wv.back();
         w.count++;
         wo.push_back(k);
-        const PairSpec &x = sp[k];
+        const PairSpec &x = spw[k];
         const int64_t passes = ((x.m + kTP - 1) / kTP + seg - 1) / seg;
         w.cost = std::max(w.cost, passes * (x.n + seg - 1));
     }
     if (!plain) {
-        std::vector<int64_t> wi(wv.size());
+        wi.resize(wv.size());
         for (size_t v = 0; v < wv.size(); v++) wi[v] = (int64_t)v;
         sort_desc_stable(wi, [&](int64_t v) { return (uint64_t)wv[v].cost; });
-        std::vector<WaveSpec> sorted(wv.size());
-        for (size_t v = 0; v < wv.size(); v++) sorted[v] = wv[wi[v]];
-        wv.swap(sorted);
+        wv_sorted.resize(wv.size());
+        for (size_t v = 0; v < wv.size(); v++) wv_sorted[v] = wv[wi[v]];
+        wv.swap(wv_sorted);
     }
     // the pairs of a wave (k, its unit or -1, 0 for a unit's pair a, 1 for b),
     // segment widths of the int32 kernel from the widest, so that each of
@@ -1091,8 +1200,8 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
         for (int seg = kWave; seg >= 4; seg >>= 1) {
             if (w.packed) {
                 for (int64_t u = w.u_first; u < w.u_first + w.u_count; u++) {
-                    if (segk[us[u].a] == seg) out.push_back({us[u].a, u, 0});
-                    if (us[u].b >= 0 && segk[us[u].b] == seg) out.push_back({us[u].b, u, 1});
+                    if (segw[us[u].a] == seg) out.push_back({us[u].a, u, 0});
+                    if (us[u].b >= 0 && segw[us[u].b] == seg) out.push_back({us[u].b, u, 1});
                 }
             } else if (w.seg == seg) {
                 for (int64_t q = 0; q < w.count; q++) out.push_back({wo[w.first + q], -1, 0});
@@ -1102,8 +1211,8 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
     // a pair's region holds its int32 direction codes or its checkpoints
     auto region_words = [&](int64_t k, int64_t u) -> int64_t {
         if (!traceback) return 0;
-        const PairSpec &x = sp[k];
-        const int seg = segk[k];
+        const PairSpec &x = spw[k];
+        const int seg = segw[k];
         const int64_t strips = (x.m + kTP - 1) / kTP;
         const int64_t passes = (strips + seg - 1) / seg;
         const int64_t nblk = (x.n + seg - 1 + kWfBlock - 1) / kWfBlock;
@@ -1145,9 +1254,9 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
         // int32 waves over these pairs: one segment width each, 64 / seg pairs
         {
             for (size_t q0 = 0; q0 < wp.size();) {
-                const int seg = segk[wp[q0].k];
+                const int seg = segw[wp[q0].k];
                 size_t q1 = q0;
-                while (q1 < wp.size() && segk[wp[q1].k] == seg && (int64_t)(q1 - q0) < kWave / seg) q1++;
+                while (q1 < wp.size() && segw[wp[q1].k] == seg && (int64_t)(q1 - q0) < kWave / seg) q1++;
                 WfWave V;
                 V.p0 = (int32_t)(p0 + (int64_t)q0);
                 V.np = (int32_t)(q1 - q0);
@@ -1183,12 +1292,12 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
         }
         for (size_t q = 0; q < wp.size(); q++) {
             const int64_t k = wp[q].k, u = wp[q].u;
-            const PairSpec &x = sp[k];
+            const PairSpec &x = spw[k];
             const int64_t words = wwords[q];
             WfPair W;
             memset(&W, 0, sizeof(W));
             W.slot = (int32_t)P.slots.size();
-            W.seg = segk[k];
+            W.seg = segw[k];
             W.tb = wchunk / 2;  // plain: every pair starts at 0 (one at a time)
             wchunk += words;
             if (plain) {
@@ -1205,8 +1314,8 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
             memset(&K, 0, sizeof(K));
             if (u >= 0) {
                 K.nst = (int32_t)us[u].nst;
-                K.bias = pbias[k];
-                K.hlim = phlim[k];
+                K.bias = biasw[k];
+                K.hlim = hlimw[k];
                 K.w = us[u].w;
             }
             P.pkpairs.push_back(K);
@@ -1218,8 +1327,8 @@ void build_pair_plan(const std::vector<PairSpec> &sp, int64_t n_results, int mod
             I.m = (int32_t)x.m;
             I.n = (int32_t)x.n;
             I.res = x.res;
-            I.cig_off = roff[x.res];
-            I.cig_cap = (int32_t)rcap[x.res];
+            I.cig_off = coffw[k];
+            I.cig_cap = (int32_t)ccapw[k];
             I.pssm_row = x.pssm_row;
             P.slots.push_back(I);
         }
@@ -1299,7 +1408,8 @@ int make_pair_plan(const dsa_args *a, const dsa_out *out, PairPlan &P) {
         if (a->t_offsets[k + 1] < a->t_offsets[k]) return fail(DSA_E_INVAL, "t_offsets must be non-decreasing");
     if (a->top_k) return fail(DSA_E_INVAL, "top_k applies to database search only");
     const int ends = a->mode == DSA_SEMIGLOBAL ? (a->free_ends ? a->free_ends : (DSA_TB | DSA_TE)) : 0;
-    std::vector<PairSpec> sp(n);
+    static thread_local std::vector<PairSpec> sp;  // kept per thread, like the planner's lists
+    sp.resize(n);
     const int mx = max_abs_score(a);
     for (int64_t k = 0; k < n; k++) {
         sp[k].q_off = a->q_offsets[k];
@@ -1637,7 +1747,8 @@ extern "C" int dsa_workspace_size(const dsa_args *args, size_t *bytes) {
     int rc = check_common(args);
     if (rc) return rc;
     if (!args->db) {
-        PairPlan PP;
+        RecycledPairPlan RPP;
+        PairPlan &PP = RPP.P;
         if ((rc = make_pair_plan(args, nullptr, PP))) return rc;
         *bytes = PP.total;
         return DSA_OK;
@@ -2227,7 +2338,8 @@ static int run_search(const dsa_args *a, const dsa_out *out, Plan &P, int phase 
         if (out->t_begin) HIPCHK(launch_fill_i32(out->t_begin, -1, nq * P.K, st));
         if (out->cigar_len) HIPCHK(launch_fill_i32(out->cigar_len, 0, nq * P.K, st));
         if (sp.empty()) return DSA_OK;
-        PairPlan PP;
+        RecycledPairPlan RPP;
+        PairPlan &PP = RPP.P;
         build_pair_plan(sp, nq * P.K, P.mode, P.ends, true, out->cigar_capacity, A,
                         std::min(P.pair_caps.tb, P.pair_caps.tbw / 2) * 4, PP, false, pair_route(Tuning()));
         const PairCaps need = caps_of(PP);
@@ -2268,7 +2380,8 @@ static int align_phase(const dsa_args *args, const dsa_out *out, int phase) {
         if (hit) return fail(DSA_E_DEVICE, "injected fault (DSA_FAULT=" + g_fault_text + "): call failed before device work");
     }
     if (!args->db) {
-        PairPlan PP;
+        RecycledPairPlan RPP;
+        PairPlan &PP = RPP.P;
         {
             Range r("dsa:plan");
             if ((rc = make_pair_plan(args, out, PP))) return rc;
