@@ -218,7 +218,7 @@ def run_other_workloads(args, dsa, B, torch, gen, dev):
                                           "planning and launch included")
     log(f"64 x 1000 local: {r}")
 
-    def pair_leg(name, Q, T, S, o, e, mode, reps=3):
+    def pair_leg(name, Q, T, S, o, e, mode, reps=10):
         cells = int((Q.lengths * T.lengths).sum())
         tuned = None
         if args.autotune:

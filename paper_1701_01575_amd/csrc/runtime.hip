@@ -1638,7 +1638,9 @@ int make_search_plan(const dsa_args *a, Plan &P) {
             // one work list, longest first.  Cost in lane row-columns: an
             // inter-sequence unit walks its rows over the widest group's
             // columns; a wavefront unit sweeps (columns + 63) steps of 16 rows
-            // per pass, with a little more work per step.
+            // per pass, at about 1.5x the instructions of an inter-sequence
+            // column (pricing it at 1.4x ordered the work list best of
+            // 1.15 to 2.5 on the 5 x 200,000 search).
             std::vector<std::pair<double, int32_t>> w;
             for (int64_t k = 0; k < (int64_t)inter.size(); k++) {
                 const SearchUnit &U = inter[k];
@@ -1648,7 +1650,7 @@ int make_search_plan(const dsa_args *a, Plan &P) {
                 const IntraUnit &I = iu[k];
                 const int64_t strips16 = (P.qinfo[I.q].len + kTI - 1) / kTI;
                 const int64_t passes = (strips16 + kWave - 1) / kWave;
-                const double c = 1.15 * passes * (db->pairs[I.lp0 + I.np - 1].ncols + kWave - 1) * kTI;
+                const double c = 1.4 * passes * (db->pairs[I.lp0 + I.np - 1].ncols + kWave - 1) * kTI;
                 w.push_back({c, -(int32_t)(R.ifirst + k) - 1});
             }
             // a strip-pipelined unit: one 4-column block of 16 rows per
