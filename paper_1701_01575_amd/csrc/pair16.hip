@@ -10,9 +10,16 @@
 // are held as value + bias, with the bias chosen per pair so that every
 // value the recurrence can reach is a positive normal binary16 pattern
 // (pk16_bias in the runtime): one v_pk_maximum3_f16 then takes the three-way
-// maximum of H for both pairs.  Scores come from an int16 copy of the matrix
+// maximum of H for both pairs.  Scores come from an int8 copy of the matrix
 // in LDS (code A pads rows past a query and columns past a target with 0,
 // which keeps padding cells within the range of the real ones).
+//
+// Global and semi-global values are also held in a frame: the cell of strip
+// row r (0-15) and column j as value + bias + e (r + 1 + j).  There the
+// gap-extend decrements of E and F vanish (both become a maximum with
+// h - (o - e)), the diagonal gains 2e, which the score table carries (s +
+// 2e), and a strip's bottom row reaches the strip below 16e lower, in that
+// strip's frame.  Checkpoints keep the frame and the walk takes it off.
 //
 // Instead of direction codes the fill stores checkpoints, 0.5 byte per cell
 // like the codes: the bottom row of each strip (H and the F entering the next
@@ -120,7 +127,8 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
 #pragma unroll
         for (int x = 0; x < 4; x++) {
             const int en = 4 * d + x, r = en / RW, c = en - r * RW;
-            const int sc = (r < A && c < A) ? (int)P.subst[r * A + c] : 0;
+            int sc = (r < A && c < A) ? (int)P.subst[r * A + c] : 0;
+            if (MODE != LOCAL) sc += 2 * P.e;  // the diagonal's step between frames
             v |= (uint32_t)(uint8_t)(int8_t)sc << (8 * x);
         }
         smw[k] = v;
@@ -162,7 +170,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
     // q * RB + LB, column b at (b / 4) * 4 * kPkCopies + b % 4
     const int RB = RW / 4 * 4 * kPkCopies, LB = 4 * (int)(threadIdx.x % kPkCopies);
     const uint32_t bias2 = pack2(KA.bias, KB.bias);
-    const uint32_t o2 = dup(o), e2 = dup(e);
+    const uint32_t o2 = dup(o), e2 = dup(e), oe2 = dup(o - e), e16 = dup(16 * e);
     const char *smb = reinterpret_cast<const char *>(smw);
 
     // global and semi-global: H never exceeds the query's sum of positive row
@@ -198,7 +206,8 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
             rowAB[r] = pack2(cA * RB + LB, cB * RB + LB);
             H[r] = addu(pack2(left_or_pad(MODE, ends, o, e, i + 1, mA), left_or_pad(MODE, ends, o, e, i + 1, mB)),
                         bias2);
-            E[r] = (MODE == LOCAL) ? bias2 : subw(H[r], o2);
+            if (MODE != LOCAL) H[r] = addu(H[r], dup((r + 1) * e));  // column 0's frame
+            E[r] = (MODE == LOCAL) ? bias2 : subw(H[r], oe2);
         }
         uint32_t Hd_top = addu(pack2(left_or_pad(MODE, ends, o, e, i0, mA), left_or_pad(MODE, ends, o, e, i0, mB)),
                                bias2);
@@ -255,7 +264,12 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
                     if (pass == 0) {  // the top boundary row (0 past a target)
                         const int tv = top_value(MODE, ends, o, e, j);
                         rH = addu(pack2(j <= nA ? tv : 0, j <= nB ? tv : 0), bias2);
-                        rF = subw(rH, o2);
+                        if (MODE == LOCAL) {
+                            rF = subw(rH, o2);
+                        } else {
+                            rH = addu(rH, dup(e * j));
+                            rF = subw(rH, oe2);
+                        }
                     } else {
                         rH = lo_lo(wa0, wb0);
                         rF = hi_hi(wa0, wb0);
@@ -297,13 +311,14 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
                         if (r & 1) cm = max3h(cm, held, h);
                         else held = h;
                     }
-                    const uint32_t ho = subw(h, o2);
                     if (MODE == LOCAL) {
+                        const uint32_t ho = subw(h, o2);
                         E[r] = max3h(subw(E[r], e2), ho, bias2);
                         F = max3h(subw(F, e2), ho, bias2);
-                    } else {
-                        E[r] = maxu(subw(E[r], e2), ho);
-                        F = maxu(subw(F, e2), ho);
+                    } else {  // in the frame E and F share h - (o - e) and lose their decrement
+                        const uint32_t hx = subw(h, oe2);
+                        E[r] = maxu(E[r], hx);
+                        F = maxu(F, hx);
                     }
                     H[r] = h;
                 }
@@ -322,12 +337,12 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
                     }
                 } else {
                     if (lastA && j <= nA && ((ends & TE) || j == nA)) {
-                        const int v = (int)(row_of16(H, rlastA) & 0xffffu) - KA.bias;
+                        const int v = (int)(row_of16(H, rlastA) & 0xffffu) - KA.bias - e * (rlastA + 1 + j);
                         if (!(ends & TE)) resA = v;
                         else if (v > LsA) { LsA = v; LjA = j; }
                     }
                     if (lastB && j <= nB && ((ends & TE) || j == nB)) {
-                        const int v = (int)(row_of16(H, rlastB) >> 16) - KB.bias;
+                        const int v = (int)(row_of16(H, rlastB) >> 16) - KB.bias - e * (rlastB + 1 + j);
                         if (!(ends & TE)) resB = v;
                         else if (v > LsB) { LsB = v; LjB = j; }
                     }
@@ -335,21 +350,23 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
                         if (j == nA && s < SA) {
 #pragma unroll
                             for (int r = 0; r < T; r++) {
-                                const int v = (int)(H[r] & 0xffffu) - KA.bias;
+                                const int v = (int)(H[r] & 0xffffu) - KA.bias - e * (r + 1 + j);
                                 if (i0 + r < mA && v > QsA) { QsA = v; QiA = i0 + r + 1; }
                             }
                         }
                         if (j == nB && s < SB) {
 #pragma unroll
                             for (int r = 0; r < T; r++) {
-                                const int v = (int)(H[r] >> 16) - KB.bias;
+                                const int v = (int)(H[r] >> 16) - KB.bias - e * (r + 1 + j);
                                 if (i0 + r < mB && v > QsB) { QsB = v; QiB = i0 + r + 1; }
                             }
                         }
                     }
                 }
-                outH = H[T - 1];
-                outF = F;
+                // the bottom row in the frame of the strip below's row above
+                // (16 rows up): H at e j, the F entering it at e (j + 1)
+                outH = (MODE == LOCAL) ? H[T - 1] : subw(H[T - 1], e16);
+                outF = (MODE == LOCAL) ? F : subw(F, e16);
                 if (TB) {
                     // this step's bottom row, and every kCkCols steps the strip's column
                     if (s < SA) ckA[botA + (int64_t)t * nspA] = lo_lo(outH, outF);
@@ -581,6 +598,10 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
             const uint32_t w = ck[pk16_left_at(s, (c0 + l) / kCkCols - 1, S, seg, NST) + r];
             Hl = (int)(w & 0xffffu) - bias;
             El = (int)(w >> 16) - bias;
+            if (MODE != LOCAL) {  // the fill's frame: H(r, c0) at e (r + 1 + c0), E of c0 + 1 one e above
+                Hl -= e * (r + 1 + c0);
+                El -= e * (r + 2 + c0);
+            }
         } else {
             Hl = left_value(MODE, ends, o, e, ri);
             El = (MODE == LOCAL) ? 0 : Hl - o;
@@ -597,12 +618,17 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
                 const uint32_t w = ck[pk16_bot_at(s - 1, c + lp - 1, S, seg, NST)];
                 colH = (int)(w & 0xffffu) - bias;
                 colF = (int)(w >> 16) - bias;
+                if (MODE != LOCAL) {  // the row above at e c, the F entering the strip at e (c + 1)
+                    colH -= e * c;
+                    colF -= e * (c + 1);
+                }
             }
         }
         int corner;  // H(i0, c0), the diagonal of row i0 + 1 in column c0 + 1
         if (s == 0) corner = top_value(MODE, ends, o, e, c0);
         else if (c0 == 0) corner = left_value(MODE, ends, o, e, i0);
-        else corner = (int)(ck[pk16_bot_at(s - 1, c0 + lp - 1, S, seg, NST)] & 0xffffu) - bias;
+        else corner = (int)(ck[pk16_bot_at(s - 1, c0 + lp - 1, S, seg, NST)] & 0xffffu) - bias -
+                      (MODE != LOCAL ? e * c0 : 0);
         // the tile column by column, all 16 rows at once.  F runs down a
         // column as a prefix maximum: with hp = max(diagonal + s, E[, 0]),
         // F(row r) = max(Ftop - r e, max over k < r of hp(k) - o - (r-1-k) e)
