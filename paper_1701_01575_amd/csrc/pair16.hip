@@ -115,7 +115,10 @@ size_t pk16_lds_bytes(int A) {
     return (size_t)kPkCopies * (A + 1) * kPkRow(A) + (size_t)(A + 1) * 2 + 16;
 }
 
-template <int MODE, bool TB>
+// SH: the row shift below, set by the launcher for semi-global calls with a
+// free target begin (a template flag, so that the other instantiations keep
+// no trace of it and this one none of the per-lane last-row select)
+template <int MODE, bool TB, bool SH>
 __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_waves_per_eu(3))) k_pairpk(PairArgs P, Pk16Args X) {
     constexpr int T = kTP;
     extern __shared__ uint32_t smw[];
@@ -190,26 +193,36 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
     uint64_t gkA = end_key(0, 0, 0), gkB = gkA;  // local: the lane's best over its strips
     int gsA = 0, gjA = 0, gsB = 0, gjB = 0;      // global / semi: held by the lane of the last strip
     const bool qe_free = (MODE == SEMIGLOBAL) && (ends & QE);
+    // semi-global with a free target begin: each pair's rows sit pad = 16 S
+    // - m strip rows down, below virtual rows of score 0 (code A) with H = 0
+    // at column 0.  With the top row free those rows reproduce it exactly
+    // (H stays 0 in them and the F entering row 1 is -o), and the query's
+    // last row is row 15 of the pair's last strip, one register
+    constexpr bool shifted = SH;
+    const int padA = shifted ? SA * T - mA : 0, padB = shifted ? SB * T - mB : 0;
     int QsA = PAD32, QiA = 0, QsB = PAD32, QiB = 0;
     for (int pass = 0; pass < passes && !skip; pass++) {
         const int s = pass * SEG + lane;
         const int i0 = s * T;
+        const int i0A = i0 - padA, i0B = i0 - padB;  // the rows above the strip, per pair
         const bool act = s < S;
         const bool lastA = (s == SA - 1), lastB = (s == SB - 1);
-        const int rlastA = mA - 1 - i0, rlastB = mB - 1 - i0;
+        const int rlastA = mA - 1 - i0A, rlastB = mB - 1 - i0B;
         uint32_t rowAB[T], H[T], E[T];
 #pragma unroll
         for (int r = 0; r < T; r++) {
-            const int i = i0 + r;
-            const int cA = i < mA ? min((int)qA[i], A - 1) : A;
-            const int cB = i < mB ? min((int)qB[i], A - 1) : A;
+            const int iA = i0A + r, iB = i0B + r;  // 0-based query rows (virtual below 0)
+            const int cA = (iA >= 0 && iA < mA) ? min((int)qA[iA], A - 1) : A;
+            const int cB = (iB >= 0 && iB < mB) ? min((int)qB[iB], A - 1) : A;
             rowAB[r] = pack2(cA * RB + LB, cB * RB + LB);
-            H[r] = addu(pack2(left_or_pad(MODE, ends, o, e, i + 1, mA), left_or_pad(MODE, ends, o, e, i + 1, mB)),
+            H[r] = addu(pack2(left_or_pad(MODE, ends, o, e, max(iA + 1, 0), mA),
+                              left_or_pad(MODE, ends, o, e, max(iB + 1, 0), mB)),
                         bias2);
             if (MODE != LOCAL) H[r] = addu(H[r], dup((r + 1) * e));  // column 0's frame
             E[r] = (MODE == LOCAL) ? bias2 : subw(H[r], oe2);
         }
-        uint32_t Hd_top = addu(pack2(left_or_pad(MODE, ends, o, e, i0, mA), left_or_pad(MODE, ends, o, e, i0, mB)),
+        uint32_t Hd_top = addu(pack2(left_or_pad(MODE, ends, o, e, max(i0A, 0), mA),
+                                     left_or_pad(MODE, ends, o, e, max(i0B, 0), mB)),
                                bias2);
         uint32_t Bv = bias2, Bi2 = 0, Bj2 = 0;  // local: best of this strip, its row and column
         int resA = 0, LsA = 0, LjA = 0, resB = 0, LsB = 0, LjB = 0;
@@ -337,28 +350,36 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
                     }
                 } else {
                     if (lastA && j <= nA && ((ends & TE) || j == nA)) {
-                        const int v = (int)(row_of16(H, rlastA) & 0xffffu) - KA.bias - e * (rlastA + 1 + j);
+                        const uint32_t hl = shifted ? H[T - 1] : row_of16(H, rlastA);
+                        const int v = (int)(hl & 0xffffu) - KA.bias - e * (rlastA + 1 + j);
                         if (!(ends & TE)) resA = v;
                         else if (v > LsA) { LsA = v; LjA = j; }
                     }
                     if (lastB && j <= nB && ((ends & TE) || j == nB)) {
-                        const int v = (int)(row_of16(H, rlastB) >> 16) - KB.bias - e * (rlastB + 1 + j);
+                        const uint32_t hl = shifted ? H[T - 1] : row_of16(H, rlastB);
+                        const int v = (int)(hl >> 16) - KB.bias - e * (rlastB + 1 + j);
                         if (!(ends & TE)) resB = v;
                         else if (v > LsB) { LsB = v; LjB = j; }
                     }
                     if (qe_free) {
+                        // running row and frame counters, made opaque so that
+                        // no per-row constant is kept live through the step loop
                         if (j == nA && s < SA) {
+                            int iA = mA - rlastA, fr = KA.bias + e * (1 + j);  // 1-based row of strip row 0
+                            asm volatile("" : "+v"(iA), "+v"(fr));
 #pragma unroll
-                            for (int r = 0; r < T; r++) {
-                                const int v = (int)(H[r] & 0xffffu) - KA.bias - e * (r + 1 + j);
-                                if (i0 + r < mA && v > QsA) { QsA = v; QiA = i0 + r + 1; }
+                            for (int r = 0; r < T; r++, iA++, fr += e) {
+                                const int v = (int)(H[r] & 0xffffu) - fr;
+                                if (iA >= 1 && iA <= mA && v > QsA) { QsA = v; QiA = iA; }
                             }
                         }
                         if (j == nB && s < SB) {
+                            int iB = mB - rlastB, fr = KB.bias + e * (1 + j);
+                            asm volatile("" : "+v"(iB), "+v"(fr));
 #pragma unroll
-                            for (int r = 0; r < T; r++) {
-                                const int v = (int)(H[r] >> 16) - KB.bias - e * (r + 1 + j);
-                                if (i0 + r < mB && v > QsB) { QsB = v; QiB = i0 + r + 1; }
+                            for (int r = 0; r < T; r++, iB++, fr += e) {
+                                const int v = (int)(H[r] >> 16) - fr;
+                                if (iB >= 1 && iB <= mB && v > QsB) { QsB = v; QiB = iB; }
                             }
                         }
                     }
@@ -486,11 +507,20 @@ hipError_t launch_pairpk(const PairArgs &a, const Pk16Args &x, int mode, hipStre
     if (x.n_waves <= 0) return hipSuccess;
     const int nb = (x.n_waves + kPairWaves - 1) / kPairWaves;
     const size_t lds = pk16_lds_bytes(a.A);
-#define LP(MODE, TBV) hipLaunchKernelGGL((k_pairpk<MODE, TBV>), dim3(nb), dim3(kPairWaves * kWave), lds, s, a, x)
+    // semi-global with a free target begin: the row-shifted fill (the walk
+    // applies the same shift)
+    const bool sh = mode == SEMIGLOBAL && (a.ends & Ends::TB);
+#define LP(MODE, TBV, SHV) hipLaunchKernelGGL((k_pairpk<MODE, TBV, SHV>), dim3(nb), dim3(kPairWaves * kWave), lds, s, a, x)
     if (a.traceback) {
-        if (mode == LOCAL) LP(LOCAL, true); else if (mode == GLOBAL) LP(GLOBAL, true); else LP(SEMIGLOBAL, true);
+        if (mode == LOCAL) LP(LOCAL, true, false);
+        else if (mode == GLOBAL) LP(GLOBAL, true, false);
+        else if (sh) LP(SEMIGLOBAL, true, true);
+        else LP(SEMIGLOBAL, true, false);
     } else {
-        if (mode == LOCAL) LP(LOCAL, false); else if (mode == GLOBAL) LP(GLOBAL, false); else LP(SEMIGLOBAL, false);
+        if (mode == LOCAL) LP(LOCAL, false, false);
+        else if (mode == GLOBAL) LP(GLOBAL, false, false);
+        else if (sh) LP(SEMIGLOBAL, false, true);
+        else LP(SEMIGLOBAL, false, false);
     }
 #undef LP
     return hipGetLastError();
@@ -574,6 +604,9 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
     const uint8_t *grp = reinterpret_cast<const uint8_t *>(tile) + kCkCols * gbase;
     int state = 0;  // 0 = H, 1 = E, 2 = F
     int budget = 2 * (m + n) + 4;
+    // the fill's row shift (semi-global with a free target begin): rows sit
+    // pad strip rows down, below virtual rows of score 0
+    const int pad = (MODE == SEMIGLOBAL && (ends & Ends::TB)) ? S * kTP - m : 0;
     for (;;) {
         if (i == 0 || j == 0) {  // on the boundary, in state H
             if (MODE != LOCAL) {
@@ -583,7 +616,7 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
             break;
         }
         if (--budget < 0) break;
-        const int s = (i - 1) / kTP, i0 = s * kTP, l = s % seg;
+        const int s = (i + pad - 1) / kTP, i0 = s * kTP - pad, l = s % seg;  // i0: the row above the tile
         int c0 = j - 1 - ((j - 1 + l) & (kCkCols - 1));
         if (c0 < 1) c0 = 0;
         const int nr = i - i0, nc = j - c0;  // 1 .. 16 each
@@ -591,7 +624,8 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
         // lane x: column c0 + 1 + x, its residue and top-row H and F (the
         // bottom row of strip s - 1, or the top boundary)
         const int ri = i0 + r + 1;
-        const int qcode = (r < nr) ? (int)qc[ri - 1] : 0;
+        const bool virt = ri < 1;  // a virtual row: score 0, H 0 at column 0
+        const int qcode = (r < nr && !virt) ? (int)qc[ri - 1] : 0;
         const int qrow = min(qcode, A - 1) * A;
         int Hl, El;
         if (c0 >= 1) {
@@ -603,7 +637,7 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
                 El -= e * (r + 2 + c0);
             }
         } else {
-            Hl = left_value(MODE, ends, o, e, ri);
+            Hl = left_value(MODE, ends, o, e, max(ri, 0));
             El = (MODE == LOCAL) ? 0 : Hl - o;
         }
         const int lp = (s + seg - 1) % seg;  // lane of strip s - 1 in the fill
@@ -626,7 +660,7 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
         }
         int corner;  // H(i0, c0), the diagonal of row i0 + 1 in column c0 + 1
         if (s == 0) corner = top_value(MODE, ends, o, e, c0);
-        else if (c0 == 0) corner = left_value(MODE, ends, o, e, i0);
+        else if (c0 == 0) corner = left_value(MODE, ends, o, e, max(i0, 0));
         else corner = (int)(ck[pk16_bot_at(s - 1, c0 + lp - 1, S, seg, NST)] & 0xffffu) - bias -
                       (MODE != LOCAL ? e * c0 : 0);
         // the tile column by column, all 16 rows at once.  F runs down a
@@ -646,7 +680,7 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
             if (x >= nc) return;  // uniform in a 16-lane group
             const int T = bcast16<x>(colT), htop = bcast16<x>(colH), ftop = bcast16<x>(colF);
             const int diag = row_shr1(dtop, Hprev);
-            const int t = diag + (int)sm[qrow + min(T, A - 1)];
+            const int t = diag + (virt ? 0 : (int)sm[qrow + min(T, A - 1)]);
             int hp = max(t, E);
             if (MODE == LOCAL) hp = max(hp, 0);
             int Y = row_shr1(ftop - e, hp - o + re);  // lane r: row r - 1's term, lane 0: the top's
@@ -673,7 +707,7 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
         asm volatile("" ::: "memory");  // the codes are in LDS before any lane reads them
         // follow the codes out of the tile (every lane the same walk)
         bool stop = false;
-        while (i > i0 && j > c0) {
+        while (i > max(i0, 0) && j > c0) {
             if (--budget < 0) { stop = true; break; }
             const uint32_t code = grp[kCkCols * (i - i0 - 1) + (j - c0 - 1)];
             if (state == 0) {
