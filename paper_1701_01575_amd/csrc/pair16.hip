@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
         for (int x = 0; x < 4; x++) {
             const int en = 4 * d + x, r = en / RW, c = en - r * RW;
             int sc = (r < A && c < A) ? (int)P.subst[r * A + c] : 0;
-            if (MODE != LOCAL) sc += 2 * P.e;  // the diagonal's step between frames
+            sc += (MODE == LOCAL ? 1 : 2) * P.e;  // the diagonal's step between frames
             v |= (uint32_t)(uint8_t)(int8_t)sc << (8 * x);
         }
         smw[k] = v;
@@ -219,12 +219,17 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
                               left_or_pad(MODE, ends, o, e, max(iB + 1, 0), mB)),
                         bias2);
             if (MODE != LOCAL) H[r] = addu(H[r], dup((r + 1) * e));  // column 0's frame
-            E[r] = (MODE == LOCAL) ? bias2 : subw(H[r], oe2);
+            E[r] = (MODE == LOCAL) ? addu(bias2, e2) : subw(H[r], oe2);  // E of column 1, in its frame
         }
         uint32_t Hd_top = addu(pack2(left_or_pad(MODE, ends, o, e, max(i0A, 0), mA),
                                      left_or_pad(MODE, ends, o, e, max(i0B, 0), mB)),
                                bias2);
-        uint32_t Bv = bias2, Bi2 = 0, Bj2 = 0;  // local: best of this strip, its row and column
+        // local: the strip's best in the frame of the lane's current column
+        // (advanced by e every step, whether or not the lane is active),
+        // its row and column, and phi = bias + e (j + 1), the floor of E and
+        // F in that frame; column j = t - lane + 1 at step t
+        uint32_t Bv = subw(bias2, mulu(dup(lane), e2)), Bi2 = 0, Bj2 = 0;
+        uint32_t phi = addu(Bv, e2);
         int resA = 0, LsA = 0, LjA = 0, resB = 0, LsB = 0, LjB = 0;
         if (MODE != LOCAL) {
             if (lastA) { resA = left_value(MODE, ends, o, e, mA); LsA = resA; }
@@ -265,6 +270,10 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
         };
         fetch_col(1 - lane);
         for (int t = 0; t < nsteps; t++) {
+            if (MODE == LOCAL) {
+                Bv = addu(Bv, e2);
+                phi = addu(phi, e2);
+            }
 #pragma unroll
             for (int r = 0; r < T; r++) asm volatile("" : "+v"(rowAB[r]));  // the two row offsets stay one register
             uint32_t rH = (uint32_t)lane_above((int)outH);
@@ -278,6 +287,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
                         const int tv = top_value(MODE, ends, o, e, j);
                         rH = addu(pack2(j <= nA ? tv : 0, j <= nB ? tv : 0), bias2);
                         if (MODE == LOCAL) {
+                            rH = subw(phi, e2);  // 0 in the frame: bias + e j
                             rF = subw(rH, o2);
                         } else {
                             rH = addu(rH, dup(e * j));
@@ -324,12 +334,11 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
                         if (r & 1) cm = max3h(cm, held, h);
                         else held = h;
                     }
-                    if (MODE == LOCAL) {
-                        const uint32_t ho = subw(h, o2);
-                        E[r] = max3h(subw(E[r], e2), ho, bias2);
-                        F = max3h(subw(F, e2), ho, bias2);
-                    } else {  // in the frame E and F share h - (o - e) and lose their decrement
-                        const uint32_t hx = subw(h, oe2);
+                    const uint32_t hx = subw(h, oe2);  // in the frame E and F share h - (o - e)
+                    if (MODE == LOCAL) {  // E loses its decrement, F (in this column's frame) keeps it
+                        E[r] = max3h(E[r], hx, phi);
+                        F = subw(max3h(F, hx, phi), e2);
+                    } else {              // and in the row frame F loses it too
                         E[r] = maxu(E[r], hx);
                         F = maxu(F, hx);
                     }
@@ -347,6 +356,12 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
                         Bi2 = bfi(mk, addu(row, dup(i0 + 1)), Bi2);
                         Bj2 = bfi(mk, dup(j), Bj2);
                         Bv = cm;
+                        // a value past the finite binary16 range (the frame can
+                        // take padding columns there before the best itself):
+                        // the pair goes to int32, shifting the best back out of
+                        // the frame would hide it
+                        if ((cm & 0xffffu) >= 0x7c00u) flagA = 1;
+                        if ((cm >> 16) >= 0x7c00u) flagB = 1;
                     }
                 } else {
                     if (lastA && j <= nA && ((ends & TE) || j == nA)) {
@@ -417,7 +432,9 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
         }
         if (act) {
             if (MODE == LOCAL) {
-                const int bA = (int)(Bv & 0xffffu), bB = (int)(Bv >> 16);
+                // the best out of the frame of the last step's column
+                const uint32_t Bu = subw(Bv, mulu(dup(nsteps - lane), e2));
+                const int bA = (int)(Bu & 0xffffu), bB = (int)(Bu >> 16);
                 if (bA > KA.bias + KA.hlim) flagA = 1;
                 if (bB > KB.bias + KB.hlim) flagB = 1;
                 if (bA > KA.bias) gkA = umax64(gkA, end_key(bA - KA.bias, (int)(Bj2 & 0xffffu), (int)(Bi2 & 0xffffu)));
@@ -632,10 +649,10 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
             const uint32_t w = ck[pk16_left_at(s, (c0 + l) / kCkCols - 1, S, seg, NST) + r];
             Hl = (int)(w & 0xffffu) - bias;
             El = (int)(w >> 16) - bias;
-            if (MODE != LOCAL) {  // the fill's frame: H(r, c0) at e (r + 1 + c0), E of c0 + 1 one e above
-                Hl -= e * (r + 1 + c0);
-                El -= e * (r + 2 + c0);
-            }
+            // the fill's frame: H(r, c0) at e (r + 1 + c0) (local: e c0), E of c0 + 1 one e above
+            const int fr = e * ((MODE == LOCAL ? 0 : r + 1) + c0);
+            Hl -= fr;
+            El -= fr + e;
         } else {
             Hl = left_value(MODE, ends, o, e, max(ri, 0));
             El = (MODE == LOCAL) ? 0 : Hl - o;
@@ -652,17 +669,15 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
                 const uint32_t w = ck[pk16_bot_at(s - 1, c + lp - 1, S, seg, NST)];
                 colH = (int)(w & 0xffffu) - bias;
                 colF = (int)(w >> 16) - bias;
-                if (MODE != LOCAL) {  // the row above at e c, the F entering the strip at e (c + 1)
-                    colH -= e * c;
-                    colF -= e * (c + 1);
-                }
+                // the row above at e c, the F entering the strip at e (c + 1) (local: e c)
+                colH -= e * c;
+                colF -= e * (MODE == LOCAL ? c : c + 1);
             }
         }
         int corner;  // H(i0, c0), the diagonal of row i0 + 1 in column c0 + 1
         if (s == 0) corner = top_value(MODE, ends, o, e, c0);
         else if (c0 == 0) corner = left_value(MODE, ends, o, e, max(i0, 0));
-        else corner = (int)(ck[pk16_bot_at(s - 1, c0 + lp - 1, S, seg, NST)] & 0xffffu) - bias -
-                      (MODE != LOCAL ? e * c0 : 0);
+        else corner = (int)(ck[pk16_bot_at(s - 1, c0 + lp - 1, S, seg, NST)] & 0xffffu) - bias - e * c0;
         // the tile column by column, all 16 rows at once.  F runs down a
         // column as a prefix maximum: with hp = max(diagonal + s, E[, 0]),
         // F(row r) = max(Ftop - r e, max over k < r of hp(k) - o - (r-1-k) e)

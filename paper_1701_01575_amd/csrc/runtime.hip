@@ -892,9 +892,9 @@ constexpr int kPk16MinLimit = 256;
 void pk16_bias(const PkSpec &k, int mode, int64_t m, int64_t n, int32_t *bias, int32_t *hlim) {
     auto G = [&](int64_t L) -> int64_t { return L > 0 ? k.o + (L - 1) * (int64_t)k.e : 0; };
     const int64_t depth = (mode == DSA_LOCAL ? 0 : G(m) + G(n)) + k.o + k.e + k.smin;
-    // global and semi-global values are held in a frame e (r + 1 + j) above
-    // (strip row r, column j), at most e (17 + n) over the real cells
-    const int64_t frame = mode == DSA_LOCAL ? 0 : (int64_t)k.e * (17 + n);
+    // values are held in a frame e (r + 1 + j) above (strip row r, column j;
+    // local e j), at most e (17 + n) over the real cells
+    const int64_t frame = (int64_t)k.e * (17 + n);
     *bias = (int32_t)std::min<int64_t>(0x0400 + depth, 0x7fff);
     *hlim = (int32_t)std::max<int64_t>(0x7bff - (0x0400 + depth) - k.smax - frame, -1);
 }
@@ -1438,8 +1438,8 @@ int make_pair_plan(const dsa_args *a, const dsa_out *out, PairPlan &P) {
         }
         pk.o = a->gap_open;
         pk.e = a->gap_extend;
-        // global and semi-global fills score from an int8 table of s + 2e
-        if (a->mode != DSA_LOCAL && pk.smax + 2 * pk.e > 127) pk.on = false;
+        // the fill scores from an int8 table of s + 2e (local s + e)
+        if (pk.smax + (a->mode == DSA_LOCAL ? 1 : 2) * pk.e > 127) pk.on = false;
     }
     build_pair_plan(sp, n, a->mode, ends, tb, (tb && out) ? out->cigar_capacity : 0, a->alphabet_size,
                     tb_budget_bytes(), P, (a->flags & DSA_PLAIN) != 0, pair_route(tuning_for(pair_key(a))), pk);
