@@ -14,12 +14,16 @@
 // in LDS (code A pads rows past a query and columns past a target with 0,
 // which keeps padding cells within the range of the real ones).
 //
-// Global and semi-global values are also held in a frame: the cell of strip
-// row r (0-15) and column j as value + bias + e (r + 1 + j).  There the
-// gap-extend decrements of E and F vanish (both become a maximum with
+// Values are also held in a frame.  Global and semi-global: the cell of
+// strip row r (0-15) and column j as value + bias + e (r + 1 + j).  There
+// the gap-extend decrements of E and F vanish (both become a maximum with
 // h - (o - e)), the diagonal gains 2e, which the score table carries (s +
 // 2e), and a strip's bottom row reaches the strip below 16e lower, in that
-// strip's frame.  Checkpoints keep the frame and the walk takes it off.
+// strip's frame.  Local: column j alone, value + bias + e j (a frame that
+// grows down the rows would break the column maximum and the zero floor):
+// E loses its decrement, F keeps it, the floor of both is bias + e (j + 1)
+// and the table carries s + e.  Checkpoints keep the frame and the walk
+// takes it off.
 //
 // Instead of direction codes the fill stores checkpoints, 0.5 byte per cell
 // like the codes: the bottom row of each strip (H and the F entering the next
