@@ -114,3 +114,29 @@ def test_dna_reads(mode, dna, monkeypatch):
     exp = oracle.align_pairs(Q, T, c["matrix"], c["gap_open"], c["gap_extend"], mode=mode, traceback=True)
     compare_pairs(got, exp, True, f"dna {mode}")
     assert ((got["status"][:len(Q)] & 1) == 0).all()
+
+
+@pytest.mark.parametrize("mode,ends", [("local", None), ("global", None), ("semiglobal", None),
+                                       ("semiglobal", 2 | 8)])
+@pytest.mark.parametrize("o,e", [(60, 58), (70, 59), (120, 100)], ids=["e58", "e59", "e100"])
+def test_frame_limits(mode, ends, o, e, blosum, monkeypatch):
+    """The fill holds values in a frame that grows by e per row and column,
+    and its int8 score table carries s + 2e (local s + e).  With the largest
+    BLOSUM62 score 11, e = 58 puts s + 2e exactly at 127 (the table's
+    limit), e = 59 past it (global and semi-global pairs then run int32),
+    and e = 100 leaves only short pairs room for the frame.  Every result
+    must equal the oracle's, whichever kernel took the pair."""
+    _wavefront(monkeypatch)
+    rng = np.random.default_rng([170101575, 302, e])
+    qs, ts = [], []
+    for L, n in [(48, 60), (100, 90), (130, 200), (257, 250), (400, 380)]:
+        q, t = gen.related_pairs(int(rng.integers(1 << 30)), 1, L, L)
+        qs.append(q[0])
+        ts.append(t[0][:n] if len(t[0]) >= n else np.concatenate([t[0], gen.background_residues(rng, n - len(t[0]))]))
+        qs.append(gen.background_residues(rng, L))
+        ts.append(gen.background_residues(rng, n))
+    Q, T = SeqSet.from_list(qs), SeqSet.from_list([x.astype(np.uint8) for x in ts])
+    log(f"pairs16 frame limits {mode}/{ends} o={o} e={e} n={len(Q)}")
+    got = gpu_pairs(Q, T, blosum, o, e, mode, ends, traceback=True)
+    exp = oracle.align_pairs(Q, T, blosum, o, e, mode=mode, ends=ends, traceback=True)
+    compare_pairs(got, exp, True, f"frame limits {mode}/{ends} e={e}")
