@@ -352,7 +352,20 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
                 // chain's steps, rather than sunk past the end-cell branches
 #pragma unroll
                 for (int r = 0; r < T; r++) asm volatile("" : "+v"(E[r]));
-                if (MODE == LOCAL) {
+                if (MODE == LOCAL && TB) {
+                    // with traceback only the column of the strip's best is
+                    // kept, without a branch: the walk recomputes that tile
+                    // and finds the row there.  A value past the finite
+                    // binary16 range (the frame can take padding columns
+                    // there before the best itself) flags the pair: shifting
+                    // the best back out of the frame would hide it
+                    Bj2 = bfi(nzmask(cm ^ Bv), dup(j), Bj2);
+                    Bv = cm;
+                    if (maxu(cm, 0x7bff7bffu) != 0x7bff7bffu) {
+                        if ((cm & 0xffffu) >= 0x7c00u) flagA = 1;
+                        if ((cm >> 16) >= 0x7c00u) flagB = 1;
+                    }
+                } else if (MODE == LOCAL) {
                     const uint32_t d = cm ^ Bv;  // nonzero in a half whose best grew
                     if (d) {
                         const uint32_t mk = nzmask(d);
@@ -360,10 +373,6 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
                         Bi2 = bfi(mk, addu(row, dup(i0 + 1)), Bi2);
                         Bj2 = bfi(mk, dup(j), Bj2);
                         Bv = cm;
-                        // a value past the finite binary16 range (the frame can
-                        // take padding columns there before the best itself):
-                        // the pair goes to int32, shifting the best back out of
-                        // the frame would hide it
                         if ((cm & 0xffffu) >= 0x7c00u) flagA = 1;
                         if ((cm >> 16) >= 0x7c00u) flagB = 1;
                     }
@@ -441,8 +450,11 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
                 const int bA = (int)(Bu & 0xffffu), bB = (int)(Bu >> 16);
                 if (bA > KA.bias + KA.hlim) flagA = 1;
                 if (bB > KB.bias + KB.hlim) flagB = 1;
-                if (bA > KA.bias) gkA = umax64(gkA, end_key(bA - KA.bias, (int)(Bj2 & 0xffffu), (int)(Bi2 & 0xffffu)));
-                if (bB > KB.bias) gkB = umax64(gkB, end_key(bB - KB.bias, (int)(Bj2 >> 16), (int)(Bi2 >> 16)));
+                // with traceback the strip's first row stands for its row (rows
+                // of a lower strip all come later, and the walk finds the row)
+                const int iA = TB ? i0 + 1 : (int)(Bi2 & 0xffffu), iB = TB ? i0 + 1 : (int)(Bi2 >> 16);
+                if (bA > KA.bias) gkA = umax64(gkA, end_key(bA - KA.bias, (int)(Bj2 & 0xffffu), iA));
+                if (bB > KB.bias) gkB = umax64(gkB, end_key(bB - KB.bias, (int)(Bj2 >> 16), iB));
             } else {
                 if (lastA) {
                     if (ends & TE) { gsA = LsA; gjA = LjA; }
@@ -515,7 +527,9 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
         if (P.out_tend) P.out_tend[I.res] = te;
         if (P.out_status) P.out_status[I.res] = 0;  // exact in int16
         if (TB) {
-            P.end_i[slot] = (MODE == LOCAL && Gs == 0) ? -1 : Gi;
+            // local: -2 - the end cell's strip, whose row the walk finds (and
+            // writes q_end); -1 for a score of 0
+            P.end_i[slot] = (MODE == LOCAL) ? (Gs == 0 ? -1 : -2 - (Gi - 1) / T) : Gi;
             P.end_j[slot] = Gj;
         } else {
             if (P.out_qbeg) P.out_qbeg[I.res] = -1;
@@ -612,7 +626,7 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
     RunWriter Wr{P.cigar, I.cig_off, I.cig_off + I.cig_cap};
     Wr.store = (r == 0);
     int i = P.end_i[W.slot], j = P.end_j[W.slot];
-    if (i < 0) {  // local alignment of score 0: nothing to trace
+    if (i == -1) {  // local alignment of score 0: nothing to trace
         if (r == 0) {
             if (P.out_qbeg) P.out_qbeg[I.res] = -1;
             if (P.out_tbeg) P.out_tbeg[I.res] = -1;
@@ -625,6 +639,14 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
     const uint8_t *grp = reinterpret_cast<const uint8_t *>(tile) + kCkCols * gbase;
     int state = 0;  // 0 = H, 1 = E, 2 = F
     int budget = 2 * (m + n) + 4;
+    // local: the fill gave the end cell's strip (-2 - s) and column; its row
+    // is the first of the strip whose H in that column is the score, found
+    // in the first tile (until then i stands at the strip's last row)
+    int rs = -1;
+    if (MODE == LOCAL && i <= -2) {
+        rs = -2 - i;
+        i = min(rs * kTP + kTP, m);
+    }
     // the fill's row shift (semi-global with a free target begin): rows sit
     // pad strip rows down, below virtual rows of score 0
     const int pad = (MODE == SEMIGLOBAL && (ends & Ends::TB)) ? S * kTP - m : 0;
@@ -694,6 +716,7 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
         int E = El;       // E(i, c)
         int dtop = corner;  // H(i0, c - 1): lane 0's diagonal
         const int re = r * e;
+        int hj = 0;  // this row's H in column j, the tile's last
         for_cols(std::make_integer_sequence<int, kCkCols>{}, [&](auto xc) {
             constexpr int x = decltype(xc)::value;
             if (x >= nc) return;  // uniform in a 16-lane group
@@ -717,6 +740,7 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
             code |= (F > hup - o) ? 8u : 0u;    // F(i, c) extends F(i - 1, c)
             code |= (qcode == T) ? 16u : 0u;    // residues equal (= or X on the diagonal)
             if (r < nr) mine[x] = (uint8_t)code;
+            if (x == nc - 1) hj = h;
             int En = max(E - e, h - o);
             if (MODE == LOCAL) En = max(En, 0);
             E = En;
@@ -724,6 +748,13 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
             dtop = htop;
         });
         asm volatile("" ::: "memory");  // the codes are in LDS before any lane reads them
+        if (MODE == LOCAL && rs >= 0) {  // the end cell's row (uniform in the group)
+            const uint64_t bal = __ballot(r < nr && hj == P.out_score[I.res]);
+            const uint32_t g = (uint32_t)(bal >> (gbase & 63)) & 0xffffu;
+            if (g) i = i0 + __builtin_ctz(g) + 1;
+            rs = -1;
+            if (r == 0 && P.out_qend) P.out_qend[I.res] = i - 1;
+        }
         // follow the codes out of the tile (every lane the same walk)
         bool stop = false;
         while (i > max(i0, 0) && j > c0) {
