@@ -8,7 +8,9 @@ held with a per-pair bias) and its checkpoint walk, against the oracle:
   the other kind in the same segment;
 - an odd number of pairs per segment width (a segment with one pair);
 - pairs of very different target lengths sharing a segment;
-- every result equals the int32 path's (DSA_PAIR_INT32=1).
+- every result equals the int32 path's (DSA_PAIR_INT32=1);
+- the value frame at its limits: a gap extension that puts the score table
+  at the top of int8, one past it, and one that leaves the frame little room.
 """
 import numpy as np
 import pytest
