@@ -586,10 +586,13 @@ __device__ __forceinline__ int row_next(int v) {   // lane r + 1 of the 16-lane 
 __device__ __forceinline__ int row_shr1(int first, int v) {
     return __builtin_amdgcn_update_dpp(first, v, 0x111 /* row_shr:1 */, 0xf, 0xf, false);
 }
-// lane r - K's v, v itself in lanes r < K (a step of a prefix maximum)
+// One step of a prefix maximum down the 16 lanes of a row: max(v, lane r -
+// K's v), v itself in lanes r < K.  The shifted-in value defaults to the
+// maximum's identity, which lets the compiler fold the shift into the
+// maximum (v_max_i32 with a DPP operand).
 template <int K>
-__device__ __forceinline__ int row_shr_keep(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, 0x110 + K /* row_shr:K */, 0xf, 0xf, false);
+__device__ __forceinline__ int row_max_shr(int v) {
+    return max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x110 + K /* row_shr:K */, 0xf, 0xf, false));
 }
 // f(integral_constant<int, X>) for X in the sequence, in order
 template <int... X, class Fn>
@@ -726,10 +729,10 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
             int hp = max(t, E);
             if (MODE == LOCAL) hp = max(hp, 0);
             int Y = row_shr1(ftop - e, hp - o + re);  // lane r: row r - 1's term, lane 0: the top's
-            Y = max(Y, row_shr_keep<1>(Y));
-            Y = max(Y, row_shr_keep<2>(Y));
-            Y = max(Y, row_shr_keep<4>(Y));
-            Y = max(Y, row_shr_keep<8>(Y));
+            Y = row_max_shr<1>(Y);
+            Y = row_max_shr<2>(Y);
+            Y = row_max_shr<4>(Y);
+            Y = row_max_shr<8>(Y);
             int F = Y - re + e;
             if (MODE == LOCAL) F = max(F, 0);
             const int h = max(hp, F);
