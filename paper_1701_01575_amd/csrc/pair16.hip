@@ -763,25 +763,16 @@ __global__ void __launch_bounds__(kCkWalkThreads) k_walk_ck(PairArgs P, Pk16Args
         while (i > max(i0, 0) && j > c0) {
             if (--budget < 0) { stop = true; break; }
             const uint32_t code = grp[kCkCols * (i - i0 - 1) + (j - c0 - 1)];
-            if (state == 0) {
-                const uint32_t src = code & 3u;
-                if (src == 0u) { stop = true; break; }
-                if (src == 1u) {
-                    Wr.emit((code & 16u) ? OP_EQ : OP_X, 1);
-                    i--;
-                    j--;
-                } else {
-                    state = (src == 2u) ? 1 : 2;
-                }
-            } else if (state == 1) {
-                Wr.emit(OP_D, 1);
-                j--;
-                if (!((code >> 2) & 1u)) state = 0;
-            } else {
-                Wr.emit(OP_I, 1);
-                i--;
-                if (!((code >> 3) & 1u)) state = 0;
-            }
+            const uint32_t src = code & 3u;
+            if (state == 0 && src == 0u) { stop = true; break; }
+            // one move per step, the same for every lane and state: in H a
+            // gap source moves on at once as that gap (E or F at this cell,
+            // whose extend bit is in the same code)
+            const int g = state == 0 ? (src == 1u ? 0 : (int)src - 1) : state;  // 0 diagonal, 1 E, 2 F
+            Wr.emit(g == 0 ? ((code & 16u) ? OP_EQ : OP_X) : (g == 1 ? OP_D : OP_I), 1);
+            i -= (g != 1);
+            j -= (g != 2);
+            state = g == 0 ? 0 : (g == 1 ? (int)((code >> 2) & 1u) : 2 * (int)((code >> 3) & 1u));
         }
         asm volatile("" ::: "memory");  // the next tile's codes are written after these reads
         if (stop) break;
