@@ -565,27 +565,19 @@ __device__ void walk_pair(const PairArgs &P, const PairInfo &I, int i, int j, Co
                 else if (j == 0 && i > 0 && !(ends & QB)) { W.emit(OP_I, (uint32_t)i); i = 0; }
                 break;
             }
-            const uint32_t src = code(i, j) & 3u;
-            if (src == 0u) break;
-            if (src == 1u) {
-                W.emit(eq(i, j) ? OP_EQ : OP_X, 1);
-                i--; j--;
-            } else {
-                state = (src == 2u) ? 1 : 2;
-            }
-        } else if (state == 1) {
-            if (j <= 0 || i <= 0) break;  // codes never lead here; keeps reads in bounds
-            const uint32_t ext = (code(i, j) >> 2) & 1u;
-            W.emit(OP_D, 1);
-            j--;
-            if (!ext) state = 0;
-        } else {
-            if (j <= 0 || i <= 0) break;
-            const uint32_t ext = (code(i, j) >> 3) & 1u;
-            W.emit(OP_I, 1);
-            i--;
-            if (!ext) state = 0;
         }
+        if (j <= 0 || i <= 0) break;  // in a gap: codes never lead here; keeps reads in bounds
+        const uint32_t c = code(i, j), src = c & 3u;
+        if (state == 0 && src == 0u) break;
+        // one move per step, whatever the state: in H a gap source moves on
+        // at once as that gap (E or F at this cell, whose extend bit is in
+        // the same code), so lanes in different states stay on one path
+        const int g = state == 0 ? (src == 1u ? 0 : (int)src - 1) : state;  // 0 diagonal, 1 E, 2 F
+        W.emit(g == 0 ? (eq(i, j) ? OP_EQ : OP_X) : (g == 1 ? OP_D : OP_I), 1);
+        const uint32_t ext = (c >> (g == 1 ? 2 : 3)) & 1u;
+        i -= (g != 1);
+        j -= (g != 2);
+        state = (g != 0 && ext) ? g : 0;
     }
     W.flush();
     if (P.out_qbeg) P.out_qbeg[I.res] = i;
