@@ -115,8 +115,11 @@ __device__ __forceinline__ int left_or_pad(int mode, int ends, int o, int e, int
 // row maxima of the matrix (int16).
 constexpr int kPkCopies = 32;
 __host__ __device__ inline int kPkRow(int A) { return (A + 1 + 3) & ~3; }
+// Then, per target code 0..255 and 256 (past a target), the byte offset of
+// its column in the table (uint16).
+constexpr int kPkCodes = 257;
 size_t pk16_lds_bytes(int A) {
-    return (size_t)kPkCopies * (A + 1) * kPkRow(A) + (size_t)(A + 1) * 2 + 16;
+    return (size_t)kPkCopies * (A + 1) * kPkRow(A) + (size_t)(A + 1) * 2 + 16 + kPkCodes * 2 + 16;
 }
 
 // SH: the row shift below, set by the launcher for semi-global calls with a
@@ -141,6 +144,11 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
         smw[k] = v;
     }
     uint16_t *rmx = reinterpret_cast<uint16_t *>(smw + nd * kPkCopies);
+    uint16_t *coff = rmx + ((SS + 7) & ~7);
+    for (int q = threadIdx.x; q < kPkCodes; q += blockDim.x) {
+        const int b = q > 255 ? A : min(q, A - 1);  // code A (scores 0) past a target
+        coff[q] = (uint16_t)((b >> 2) * (4 * kPkCopies) + (b & 3));
+    }
     for (int q = threadIdx.x; q < SS; q += blockDim.x) {
         int mx = 0;
         if (q < A)
@@ -273,6 +281,9 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
             }
         };
         fetch_col(1 - lane);
+        // the column offsets of the codes in flight, looked up at the end of
+        // the step that loaded them (their loads are back by then)
+        uint32_t oa = coff[ca], ob = coff[cb];
         for (int t = 0; t < nsteps; t++) {
             if (MODE == LOCAL) {
                 Bv = addu(Bv, e2);
@@ -283,7 +294,7 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
             uint32_t rH = (uint32_t)lane_above((int)outH);
             uint32_t rF = (uint32_t)lane_above((int)outF);
             const int j = t - lane + 1;
-            const uint32_t ca0 = ca, cb0 = cb, wa0 = wa, wb0 = wb;
+            const uint32_t oa0 = oa, ob0 = ob, wa0 = wa, wb0 = wb;
             fetch_col(j + 1);
             if (act && j >= 1 && j <= nmax) {
                 if (lane == 0) {
@@ -302,11 +313,8 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
                         rF = hi_hi(wa0, wb0);
                     }
                 }
-                // column codes clamped to the alphabet, A (scores 0) past a target
-                const int bA = ca0 > 255u ? A : min((int)ca0, A - 1);
-                const int bB = cb0 > 255u ? A : min((int)cb0, A - 1);
-                const int bA2 = (bA >> 2) * (4 * kPkCopies) + (bA & 3);
-                const int bB2 = (bB >> 2) * (4 * kPkCopies) + (bB & 3);
+                // the columns' offsets in the score table
+                const int bA2 = (int)oa0, bB2 = (int)ob0;
                 uint32_t Hd = Hd_top;
                 Hd_top = rH;
                 uint32_t F = rF;
@@ -442,6 +450,8 @@ __global__ void __launch_bounds__(kPairWaves * kWave) __attribute__((amdgpu_wave
                                           hi_hi(H[4 * x + 2], E[4 * x + 2]), hi_hi(H[4 * x + 3], E[4 * x + 3]));
                 }
             }
+            oa = coff[ca];
+            ob = coff[cb];
         }
         if (act) {
             if (MODE == LOCAL) {
