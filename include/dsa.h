@@ -224,11 +224,14 @@ int dsa_cigar_capacity(const dsa_args *args, int64_t *entries);
  * global and semi-global mode).  A pair whose values could pass the int16
  * range is redone by the exact int32 kernels and carries DSA_ST_INT32: in
  * global and semi-global mode when its query's sum of positive row maxima
- * exceeds the limit the bias leaves (31,743 - bias - max S, with bias =
- * 1,024 + that depth), in local mode when its best score does.  These run int32 throughout: a
- * position-specific profile, more than 32 letters, DSA_FORCE_INT32,
- * DSA_PLAIN.  Smaller pairs, and the traceback of top-K hits, run exact
- * int32 kernels.
+ * exceeds the limit the bias leaves (31,743 - bias - max S - gap_extend
+ * (17 + n), with bias = 1,024 + that depth; the last term is the room the
+ * fill's value frame takes), in local mode when its best score does or a
+ * value of its fill passes the finite binary16 range.  These run int32
+ * throughout: a position-specific profile, more than 32 letters, max S +
+ * 2 gap_extend above 127 (max S + gap_extend in local mode: the fill's
+ * int8 score table carries that step), DSA_FORCE_INT32, DSA_PLAIN.
+ * Smaller pairs, and the traceback of top-K hits, run exact int32 kernels.
  * Errors: DSA_E_INVAL, DSA_E_RANGE, DSA_E_WORKSPACE, DSA_E_NOTSUP,
  * DSA_E_DEVICE.
  */
